@@ -1,0 +1,204 @@
+/*
+ * napy.h -- C ABI of libnapy: all-pairs Pearson and Spearman correlation with
+ * pairwise deletion of missing values on one AMD MI355X (gfx950).
+ *
+ * Method: NApy, "Efficient Statistics in Python for Large-Scale Heterogeneous
+ * Data with Enhanced Support for Missing Data" (arXiv 2505.00448).
+ *   - Section 3.2 defines the pairwise-complete set I(g,h) of a variable pair:
+ *     the samples where neither value is missing (it may be empty).
+ *   - Section 3.5.2: Pearson correlation on I(g,h), two-sided p from the Beta
+ *     CDF; r and p undefined (NaN) for |I| <= 1, p defined from |I| = 2 on.
+ *   - Section 3.5.3: Spearman correlation on I(g,h), each variable sorted
+ *     once, ranks re-derived inside I(g,h) in linear time, ties given their
+ *     average rank, two-sided p from the t distribution; rho and p undefined
+ *     for |I| <= 1, p undefined for |I| <= 2.
+ *   - Section 3.4: outputs are F x F matrices, entry (i, j) for variables i, j.
+ *
+ * Conventions shared by every entry point below:
+ *   - Every data pointer is a DEVICE pointer (hipMalloc'd or a PyTorch CUDA
+ *     tensor's data) unless the comment says host.  The caller owns every
+ *     buffer and the stream; the library never allocates device or host
+ *     memory and keeps no state between calls.
+ *   - Input X is samples x variables, row-major, float32: element (i, c) at
+ *     X[i * ldx + c], ldx >= F.  NaN marks a missing value; with
+ *     opts->use_sentinel != 0 a value equal to opts->sentinel is missing too.
+ *     +-Inf is a precondition violation (results undefined).
+ *   - Outputs are full symmetric F x F row-major matrices with leading
+ *     dimension ldo >= F (both triangles and the diagonal are written):
+ *     r and p float64, n int32.  Any of r, p, n may be NULL (not computed).
+ *     Undefined statistics are NaN, not errors.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous: they enqueue kernels and return; no device to
+ *     host traffic and no synchronisation happen inside a call.  Calls on
+ *     different streams with distinct buffers may run concurrently.
+ *   - `ws` is a caller-owned device workspace of at least the size returned
+ *     by the matching *_workspace() query (pure host function), aligned to
+ *     256 bytes.  Its contents on entry do not matter.
+ *   - Return value: a napy_status.  Arguments are validated on the host
+ *     before any HIP call, so a bad argument returns NAPY_E_INVALID (or
+ *     NAPY_E_WORKSPACE / NAPY_E_UNSUPPORTED) without touching the device.
+ *     NAPY_E_HIP reports a failed launch; napy_last_error() then describes it.
+ *     On any error the outputs are undefined.
+ */
+#ifndef NAPY_H
+#define NAPY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NAPY_OK = 0,
+    NAPY_E_INVALID = 1,     /* NULL input, negative size, ld too small, bad option */
+    NAPY_E_WORKSPACE = 2,   /* ws NULL or ws_bytes below the query's value */
+    NAPY_E_UNSUPPORTED = 3, /* shape outside the supported range (see each call) */
+    NAPY_E_HIP = 4          /* a HIP runtime call or kernel launch failed */
+} napy_status;
+
+typedef enum {
+    NAPY_PREC_FP32 = 0,   /* FP32 MFMA contractions, FP64 flush and combine */
+    NAPY_PREC_BF16X3 = 1, /* split-BF16 MFMA contractions, FP32 accumulate,
+                             FP64 flush and combine */
+    NAPY_PREC_FP64 = 2    /* FP64 MFMA contractions (validation mode) */
+} napy_precision;
+
+typedef struct {
+    int32_t precision;    /* napy_precision; used by the Pearson calls */
+    int32_t use_sentinel; /* 0: only NaN is missing; 1: also x == sentinel */
+    float sentinel;       /* the user's missing-value marker (Section 3.3) */
+    int32_t reserved;     /* must be 0 */
+} napy_opts;
+
+/* Static description of a status code (host, never NULL). */
+const char* napy_strerror(int status);
+
+/* Thread-local text describing the last NAPY_E_HIP / NAPY_E_UNSUPPORTED of
+ * the calling thread (host, never NULL, "" if none). */
+const char* napy_last_error(void);
+
+/* Library version as "major.minor.patch" (host, static string). */
+const char* napy_version(void);
+
+/* ------------------------------------------------------------------------
+ * Pearson (Sections 3.2, 3.5.2).  Per pair over I(g,h): n, r clamped to
+ * [-1, 1], and p = I_{1-r^2}((n-2)/2, 1/2).  n <= 1 -> r = p = NaN;
+ * n = 2 -> r = +-1, p = 1; zero variance of either side on I -> r = p = NaN.
+ * Computed as masked dense contractions on the matrix cores after centring
+ * every variable on its observed mean (r is shift invariant).
+ * Supported: 1 <= F <= 65535, 1 <= S <= 2^31 - 1.
+ * ------------------------------------------------------------------------ */
+size_t napy_pearson_workspace(int64_t S, int64_t F, const napy_opts* opts);
+
+int napy_pearson(const float* X, int64_t S, int64_t F, int64_t ldx,
+                 double* r, double* p, int32_t* n, int64_t ldo,
+                 void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Spearman (Sections 3.2, 3.5.3).  Each variable's observed values are sorted
+ * once; for every pair the ranks inside I(g,h) are re-derived by a prefix
+ * count of the partner's presence along that sorted order, with average
+ * ranks for ties (IEEE equality: -0 ties +0).  rho is the Pearson
+ * coefficient of those ranks, computed from exact integer sums.
+ * n <= 1 -> rho = p = NaN; n = 2 -> p = NaN; all tied on I -> NaN.
+ * Supported: 1 <= S <= 24576 samples, 1 <= F <= 65535.
+ * ------------------------------------------------------------------------ */
+size_t napy_spearman_workspace(int64_t S, int64_t F, const napy_opts* opts);
+
+int napy_spearman(const float* X, int64_t S, int64_t F, int64_t ldx,
+                  double* r, double* p, int32_t* n, int64_t ldo,
+                  void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Differentiation of the Pearson matrix (no counterpart in the paper; the
+ * derivative of the Section 3.5.2 definition).
+ *
+ * napy_pearson_fwd: napy_pearson plus `saved`, caller-owned float64
+ * [6][F][F] (ld F): n, Sx, Sy, Sxx, Syy, Sxy per ordered pair (g, h), the
+ * sums over I(g,h) of 1, x_g, x_h, x_g^2, x_h^2 and x_g x_h, where x is the
+ * data centred on each variable's observed mean.  Workspace as
+ * napy_pearson_workspace.
+ *
+ * napy_pearson_backward: given dR = dL/dR (float32, F x F, row-major, ld ldr;
+ * entries (g, h) and (h, g) are both read, the diagonal is ignored because
+ * r_gg is constant), writes dX = dL/dX (float32, S x F, ld lddx).  Missing
+ * entries get exactly 0, as do entries whose pairs have undefined r.  X,
+ * opts and S, F must be the forward's.
+ * ------------------------------------------------------------------------ */
+int napy_pearson_fwd(const float* X, int64_t S, int64_t F, int64_t ldx,
+                     double* r, double* p, int32_t* n, int64_t ldo, double* saved,
+                     void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+size_t napy_pearson_backward_workspace(int64_t S, int64_t F, const napy_opts* opts);
+
+int napy_pearson_backward(const float* X, int64_t S, int64_t F, int64_t ldx,
+                          const double* saved, const float* dR, int64_t ldr,
+                          float* dX, int64_t lddx,
+                          void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Subset queries on a resident base matrix (the paper's interactive
+ * explorer use case, Section 1): a query is a set of rows (samples) and a
+ * list of columns (variables) of the base X (S x F).  The result is exactly
+ * the full call applied to X[rows][:, cols] (Fq x Fq outputs, ld ldo >= Fq).
+ *
+ * rows: device int32 [Sq], distinct, ascending, each in [0, S).
+ * cols: device int32 [Fq], distinct, each in [0, F).
+ *
+ * Spearman subsets reuse a prepared base: napy_spearman_base_prepare sorts
+ * every column of X once into `base` (caller-owned device buffer of
+ * napy_spearman_base_bytes(S, F) bytes, 256-byte aligned), and
+ * napy_spearman_subset compacts each selected column's sorted order by the
+ * row set, so no query sorts again.  The base stays valid while X is
+ * unchanged; S <= 24576.
+ * ------------------------------------------------------------------------ */
+size_t napy_pearson_subset_workspace(int64_t Sq, int64_t Fq, const napy_opts* opts);
+
+int napy_pearson_subset(const float* X, int64_t S, int64_t F, int64_t ldx,
+                        const int32_t* rows, int64_t Sq, const int32_t* cols, int64_t Fq,
+                        double* r, double* p, int32_t* n, int64_t ldo,
+                        void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+size_t napy_spearman_base_bytes(int64_t S, int64_t F);
+
+int napy_spearman_base_prepare(const float* X, int64_t S, int64_t F, int64_t ldx,
+                               void* base, size_t base_bytes,
+                               const napy_opts* opts, void* stream);
+
+size_t napy_spearman_subset_workspace(int64_t S, int64_t Sq, int64_t Fq, const napy_opts* opts);
+
+int napy_spearman_subset(const void* base, int64_t S, int64_t F,
+                         const int32_t* rows, int64_t Sq, const int32_t* cols, int64_t Fq,
+                         double* r, double* p, int32_t* n, int64_t ldo,
+                         void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Test hooks (not part of the computation path).
+ *
+ * napy_spearman_pair_ranks: the doubled average ranks 2*rank that the
+ * Spearman path assigns inside I(g,h) (Section 3.5.3), scattered to sample
+ * order: rank2_g[i], rank2_h[i] (device int32 [S]) for i in I(g,h), -1 for
+ * every other sample.  Uses napy_spearman_workspace(S, F) bytes.
+ *
+ * napy_pvalue_device: evaluates the library's device p-value routine,
+ * p[k] = I_{1-r[k]^2}((n[k]-2)/2, 1/2) (NaN for n < 3), on device arrays.
+ *
+ * napy_pvalue_host: the same routine compiled for the host (host arrays);
+ * it lets the p-value arithmetic be checked on a machine without a GPU and
+ * is never used by any computation above.
+ * ------------------------------------------------------------------------ */
+int napy_spearman_pair_ranks(const float* X, int64_t S, int64_t F, int64_t ldx,
+                             int32_t g, int32_t h, int32_t* rank2_g, int32_t* rank2_h,
+                             void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+int napy_pvalue_device(const double* r, const int32_t* n, double* p, int64_t count, void* stream);
+
+int napy_pvalue_host(const double* r, const int32_t* n, double* p, int64_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NAPY_H */

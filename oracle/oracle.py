@@ -171,8 +171,8 @@ def pvalue_mp(r: float, n: int, dps: int = 50) -> float:
     """The same p in arbitrary precision (mpmath), for pins."""
     import mpmath
     with mpmath.workdps(dps):
-        a = mpmath.mpf(n - 2) / 2
-        x = 1 - mpmath.mpf(r) ** 2
+        a = mpmath.mpf(int(n) - 2) / 2
+        x = 1 - mpmath.mpf(float(r)) ** 2
         return float(mpmath.betainc(a, mpmath.mpf(1) / 2, 0, x, regularized=True))
 
 

@@ -1,0 +1,269 @@
+// C ABI of libnapy: argument validation (host only, before any HIP call),
+// workspace queries and dispatch to the Pearson and Spearman drivers.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "napy_internal.hpp"
+#include "pvalue.hpp"
+
+namespace napy {
+
+static thread_local char g_last_error[512] = "";
+
+void set_last_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+int hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return NAPY_OK;
+    set_last_error("%s: %s", what, hipGetErrorString(e));
+    return NAPY_E_HIP;
+}
+
+int check_launch(const char* what) { return hip_status(hipGetLastError(), what); }
+
+// Spearman drivers (spearman.hip)
+size_t spearman_ws_bytes(int64_t S, int64_t F);
+int spearman_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                 int64_t ldo, void* ws, const napy_opts* opts, hipStream_t st);
+int spearman_pair_ranks_run(const float* X, int64_t S, int64_t F, int64_t ldx, int g, int h, int32_t* rg,
+                            int32_t* rh, void* ws, const napy_opts* opts, hipStream_t st);
+size_t spearman_base_bytes(int64_t S, int64_t F);
+int spearman_base_prepare_run(const float* X, int64_t S, int64_t F, int64_t ldx, void* base,
+                              const napy_opts* opts, hipStream_t st);
+size_t spearman_subset_ws_bytes(int64_t S, int64_t Sq, int64_t Fq);
+int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t* rows, int64_t Sq,
+                        const int32_t* cols, int64_t Fq, double* r, double* p, int32_t* n, int64_t ldo,
+                        void* ws, hipStream_t st);
+// backward (backward.hip)
+size_t backward_ws_bytes(int64_t S, int64_t F);
+int backward_run(const float* X, int64_t S, int64_t F, int64_t ldx, const double* saved, const float* dR,
+                 int64_t ldr, float* dX, int64_t lddx, void* ws, const napy_opts* opts, hipStream_t st);
+
+constexpr int64_t MAX_F = 65535;
+constexpr int64_t MAX_S = 2147483647;
+constexpr int64_t MAX_S_SPEARMAN = 24576;
+
+static int check_shape(int64_t S, int64_t F)
+{
+    if (S < 0 || F < 1) {
+        set_last_error("S must be >= 0 and F >= 1 (got S=%lld, F=%lld)", (long long)S, (long long)F);
+        return NAPY_E_INVALID;
+    }
+    if (F > MAX_F || S > MAX_S) {
+        set_last_error("shape S=%lld F=%lld outside the supported range", (long long)S, (long long)F);
+        return NAPY_E_UNSUPPORTED;
+    }
+    return NAPY_OK;
+}
+
+static int check_common(const float* X, int64_t S, int64_t F, int64_t ldx, int64_t ldo, void* ws,
+                        size_t ws_bytes, size_t need, const napy_opts* opts)
+{
+    NAPY_TRY(check_shape(S, F));
+    if (!X && S > 0) return NAPY_E_INVALID;
+    if (ldx < F || ldo < F) return NAPY_E_INVALID;
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return NAPY_OK;
+}
+
+}  // namespace napy
+
+using namespace napy;
+
+extern "C" {
+
+const char* napy_strerror(int status)
+{
+    switch (status) {
+    case NAPY_OK: return "success";
+    case NAPY_E_INVALID: return "invalid argument";
+    case NAPY_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case NAPY_E_UNSUPPORTED: return "shape outside the supported range";
+    case NAPY_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char* napy_last_error(void) { return g_last_error; }
+
+const char* napy_version(void) { return "0.1.0"; }
+
+size_t napy_pearson_workspace(int64_t S, int64_t F, const napy_opts* opts)
+{
+    if (S < 0 || F < 1 || F > MAX_F || !opts_ok(opts)) return 0;
+    return pearson_ws_bytes(S, F, opt_prec(opts));
+}
+
+int napy_pearson(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                 int64_t ldo, void* ws, size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    NAPY_TRY(check_common(X, S, F, ldx, ldo, ws, ws_bytes, pearson_ws_bytes(S, F, opt_prec(opts)), opts));
+    return pearson_run(X, S, F, ldx, r, p, n, ldo, nullptr, ws, ws_bytes, opts, (hipStream_t)stream);
+}
+
+int napy_pearson_fwd(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                     int64_t ldo, double* saved, void* ws, size_t ws_bytes, const napy_opts* opts,
+                     void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    NAPY_TRY(check_common(X, S, F, ldx, ldo, ws, ws_bytes, pearson_ws_bytes(S, F, opt_prec(opts)), opts));
+    if (!saved) return NAPY_E_INVALID;
+    return pearson_run(X, S, F, ldx, r, p, n, ldo, saved, ws, ws_bytes, opts, (hipStream_t)stream);
+}
+
+size_t napy_spearman_workspace(int64_t S, int64_t F, const napy_opts* opts)
+{
+    if (S < 0 || F < 1 || F > MAX_F || S > MAX_S_SPEARMAN || !opts_ok(opts)) return 0;
+    return spearman_ws_bytes(S, F);
+}
+
+int napy_spearman(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                  int64_t ldo, void* ws, size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    if (S > MAX_S_SPEARMAN) {
+        set_last_error("Spearman supports S <= %lld samples (got %lld)", (long long)MAX_S_SPEARMAN,
+                       (long long)S);
+        return NAPY_E_UNSUPPORTED;
+    }
+    NAPY_TRY(check_common(X, S, F, ldx, ldo, ws, ws_bytes, spearman_ws_bytes(S, F), opts));
+    return spearman_run(X, S, F, ldx, r, p, n, ldo, ws, opts, (hipStream_t)stream);
+}
+
+size_t napy_pearson_backward_workspace(int64_t S, int64_t F, const napy_opts* opts)
+{
+    if (S < 0 || F < 1 || F > MAX_F || !opts_ok(opts)) return 0;
+    return backward_ws_bytes(S, F);
+}
+
+int napy_pearson_backward(const float* X, int64_t S, int64_t F, int64_t ldx, const double* saved,
+                          const float* dR, int64_t ldr, float* dX, int64_t lddx, void* ws, size_t ws_bytes,
+                          const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    if ((!X && S > 0) || !saved || !dR || (!dX && S > 0)) return NAPY_E_INVALID;
+    if (ldx < F || ldr < F || lddx < F) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < backward_ws_bytes(S, F) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return backward_run(X, S, F, ldx, saved, dR, ldr, dX, lddx, ws, opts, (hipStream_t)stream);
+}
+
+size_t napy_pearson_subset_workspace(int64_t Sq, int64_t Fq, const napy_opts* opts)
+{
+    if (Sq < 0 || Fq < 1 || Fq > MAX_F || !opts_ok(opts)) return 0;
+    Carver c(nullptr);
+    c.take<float>((size_t)(Sq > 0 ? Sq : 1) * Fq);
+    return c.bytes() + pearson_ws_bytes(Sq, Fq, opt_prec(opts));
+}
+
+int napy_pearson_subset(const float* X, int64_t S, int64_t F, int64_t ldx, const int32_t* rows, int64_t Sq,
+                        const int32_t* cols, int64_t Fq, double* r, double* p, int32_t* n, int64_t ldo,
+                        void* ws, size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    NAPY_TRY(check_shape(Sq, Fq));
+    if ((!X && S > 0) || (!rows && Sq > 0) || !cols) return NAPY_E_INVALID;
+    if (ldx < F || ldo < Fq || Sq > S || Fq > F) return NAPY_E_INVALID;
+    const size_t need = napy_pearson_subset_workspace(Sq, Fq, opts);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    Carver c(ws);
+    float* Xq = c.take<float>((size_t)(Sq > 0 ? Sq : 1) * Fq);
+    char* rest = (char*)ws + c.bytes();
+    hipStream_t st = (hipStream_t)stream;
+    if (Sq > 0) NAPY_TRY(gather_launch(X, ldx, rows, Sq, cols, Fq, Xq, st));
+    return pearson_run(Xq, Sq, Fq, Fq, r, p, n, ldo, nullptr, rest, ws_bytes - c.bytes(), opts, st);
+}
+
+size_t napy_spearman_base_bytes(int64_t S, int64_t F)
+{
+    if (S < 0 || F < 1 || F > MAX_F || S > MAX_S_SPEARMAN) return 0;
+    return spearman_base_bytes(S, F);
+}
+
+int napy_spearman_base_prepare(const float* X, int64_t S, int64_t F, int64_t ldx, void* base,
+                               size_t base_bytes, const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    if (S > MAX_S_SPEARMAN) return NAPY_E_UNSUPPORTED;
+    if ((!X && S > 0) || ldx < F) return NAPY_E_INVALID;
+    if (!base || base_bytes < spearman_base_bytes(S, F) || ((uintptr_t)base & 255)) return NAPY_E_WORKSPACE;
+    return spearman_base_prepare_run(X, S, F, ldx, base, opts, (hipStream_t)stream);
+}
+
+size_t napy_spearman_subset_workspace(int64_t S, int64_t Sq, int64_t Fq, const napy_opts* opts)
+{
+    if (S < 0 || Sq < 0 || Sq > S || Fq < 1 || Fq > MAX_F || S > MAX_S_SPEARMAN || !opts_ok(opts)) return 0;
+    return spearman_subset_ws_bytes(S, Sq, Fq);
+}
+
+int napy_spearman_subset(const void* base, int64_t S, int64_t F, const int32_t* rows, int64_t Sq,
+                         const int32_t* cols, int64_t Fq, double* r, double* p, int32_t* n, int64_t ldo,
+                         void* ws, size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    NAPY_TRY(check_shape(Sq, Fq));
+    if (S > MAX_S_SPEARMAN) return NAPY_E_UNSUPPORTED;
+    if (!base || (!rows && Sq > 0) || !cols) return NAPY_E_INVALID;
+    if (ldo < Fq || Sq > S || Fq > F) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < spearman_subset_ws_bytes(S, Sq, Fq) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return spearman_subset_run(base, S, F, rows, Sq, cols, Fq, r, p, n, ldo, ws, (hipStream_t)stream);
+}
+
+int napy_spearman_pair_ranks(const float* X, int64_t S, int64_t F, int64_t ldx, int32_t g, int32_t h,
+                             int32_t* rank2_g, int32_t* rank2_h, void* ws, size_t ws_bytes,
+                             const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    if (S > MAX_S_SPEARMAN) return NAPY_E_UNSUPPORTED;
+    if ((!X && S > 0) || ldx < F || g < 0 || h < 0 || g >= F || h >= F) return NAPY_E_INVALID;
+    if ((!rank2_g || !rank2_h) && S > 0) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < spearman_ws_bytes(S, F) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return spearman_pair_ranks_run(X, S, F, ldx, g, h, rank2_g, rank2_h, ws, opts, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace napy {
+__global__ void k_pvalue(const double* __restrict__ r, const int32_t* __restrict__ n, double* __restrict__ p,
+                         int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = corr_pvalue(r[i], (int64_t)n[i]);
+}
+}  // namespace napy
+
+extern "C" {
+
+int napy_pvalue_device(const double* r, const int32_t* n, double* p, int64_t count, void* stream)
+{
+    if (count < 0 || (count > 0 && (!r || !n || !p))) return NAPY_E_INVALID;
+    if (count == 0) return NAPY_OK;
+    hipLaunchKernelGGL(k_pvalue, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, (hipStream_t)stream, r,
+                       n, p, count);
+    return check_launch("pvalue");
+}
+
+int napy_pvalue_host(const double* r, const int32_t* n, double* p, int64_t count)
+{
+    if (count < 0 || (count > 0 && (!r || !n || !p))) return NAPY_E_INVALID;
+    for (int64_t i = 0; i < count; ++i) p[i] = corr_pvalue(r[i], (int64_t)n[i]);
+    return NAPY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal helpers shared by the libnapy translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/napy.h"
+
+namespace napy {
+
+// ---- status reporting ------------------------------------------------------
+void set_last_error(const char* fmt, ...);
+int hip_status(hipError_t e, const char* what);
+// Checks the launch just enqueued; returns NAPY_OK or NAPY_E_HIP.
+int check_launch(const char* what);
+
+#define NAPY_TRY(expr)                 \
+    do {                               \
+        int _st = (expr);              \
+        if (_st != NAPY_OK) return _st; \
+    } while (0)
+
+// ---- workspace carving -------------------------------------------------------
+// Regions are carved in order from one caller buffer, each 256-byte aligned.
+struct Carver {
+    char* base;
+    size_t off;
+    explicit Carver(void* b) : base((char*)b), off(0) {}
+    template <class T>
+    T* take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (off + 255) & ~(size_t)255; }
+};
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// ---- option validation -------------------------------------------------------
+inline bool opts_ok(const napy_opts* o)
+{
+    if (!o) return true;  // NULL means defaults
+    if (o->precision < 0 || o->precision > 2) return false;
+    if (o->use_sentinel != 0 && o->use_sentinel != 1) return false;
+    if (o->reserved != 0) return false;
+    return true;
+}
+inline int opt_prec(const napy_opts* o) { return o ? o->precision : NAPY_PREC_FP32; }
+inline int opt_use_sent(const napy_opts* o) { return o ? o->use_sentinel : 0; }
+inline float opt_sent(const napy_opts* o) { return o ? o->sentinel : 0.0f; }
+
+// ---- device helpers ------------------------------------------------------------
+__device__ __forceinline__ bool is_missing(float v, int use_sent, float sent)
+{
+    return (v != v) || (use_sent && v == sent);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// number of set bits of `mask` strictly below the calling lane
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// ---- shared launch helpers ---------------------------------------------------------
+// Column statistics: observed count and mean of every column of X (S x F).
+struct ColStats {
+    int32_t* n;     // [F]
+    float* mu32;    // [F] observed mean rounded to float
+    double* mu64;   // [F] observed mean in double
+    int32_t* pcnt;  // [R][F] partial counts
+    double* psum;   // [R][F] partial sums
+    int rows_chunks;
+};
+int colstats_plan_chunks(int64_t S, int64_t F);
+void colstats_carve(Carver& c, int64_t S, int64_t F, ColStats& cs);
+int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+                    const ColStats& cs, hipStream_t st);
+
+// Row/column gather for subset queries: Xq[i][c] = X[rows[i]][cols[c]].
+int gather_launch(const float* X, int64_t ldx, const int32_t* rows, int64_t Sq,
+                  const int32_t* cols, int64_t Fq, float* Xq, hipStream_t st);
+
+// Internal Pearson driver; `saved` may be NULL.
+int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
+                int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
+                const napy_opts* opts, hipStream_t st);
+size_t pearson_ws_bytes(int64_t S, int64_t F, int prec);
+
+}  // namespace napy

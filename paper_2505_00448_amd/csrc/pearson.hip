@@ -1,0 +1,667 @@
+// Pearson correlation with pairwise deletion as masked dense contractions on
+// the gfx950 matrix cores (NApy, arXiv 2505.00448, Sections 3.2 and 3.5.2).
+//
+// For a pair (g, h) with pairwise-complete set I(g,h) and data centred on each
+// column's observed mean (r is shift invariant), the six sums
+//     n = sum_I 1, Sx = sum_I x_g, Sy = sum_I x_h,
+//     Sxx = sum_I x_g^2, Syy = sum_I x_h^2, Sxy = sum_I x_g x_h
+// are entries of products of the zero-filled data X0 (S x F), the 0/1
+// presence matrix M and Q = X0 o X0:
+//     n = M'M, Sx = X0'M, Sy = M'X0, Sxx = Q'M, Syy = M'Q, Sxy = X0'X0.
+// Missing values are removed by the zero fill and the partner's mask inside
+// every product, so no per-pair subsetting is needed.
+//
+// Kernels:
+//   k_colstats_*     observed count and mean per column (HBM-bound, 1 pass).
+//   k_pearson_tiles  one 64 x 64 output tile of the upper triangle over one
+//                    range of samples (split-K).  The tile's panels are read
+//                    straight from X (row-major, variables contiguous),
+//                    centred, converted to the precision's operand planes and
+//                    staged through LDS; four waves each own a 32 x 32 block.
+//                    FP32 accumulators are flushed into FP64 registers every
+//                    FLUSH samples; the FP64 partial sums go to the workspace.
+//   k_pearson_combine  sums the split-K partials in FP64, forms
+//                    C = n Sxy - Sx Sy, Vx = n Sxx - Sx^2, Vy = n Syy - Sy^2,
+//                    r = C / sqrt(Vx Vy) and p, and writes both triangles.
+//
+// Precisions (napy_opts.precision):
+//   FP32    v_mfma_f32_16x16x4_f32, 6 products per pair-sample.
+//   BF16X3  v_mfma_f32_32x32x16_bf16 on split operands: x0 = hi + lo,
+//           q = qh + qm + ql (bf16 each); 15 products per pair-sample:
+//           n 1, Sx 2, Sy 2, Sxx 3, Syy 3, Sxy 4 (hi.hi, hi.lo, lo.hi, lo.lo).
+//   FP64    v_mfma_f64_16x16x4_f64 (validation mode).
+#include <type_traits>
+
+#include "napy_internal.hpp"
+#include "pvalue.hpp"
+
+namespace napy {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TILE = 64;
+constexpr int TILE_ELEMS = TILE * TILE;
+constexpr int NSTAT = 6;  // n, Sx, Sy, Sxx, Syy, Sxy
+
+// ---------------------------------------------------------------------------
+// K1: column statistics
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colstats_partial(
+    const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+    int64_t rows_per, int32_t* __restrict__ pcnt, double* __restrict__ psum)
+{
+    __shared__ int32_t sc[4][64];
+    __shared__ double ss[4][64];
+    const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int64_t col = (int64_t)blockIdx.x * 64 + c;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+    const int64_t r1 = min(S, r0 + rows_per);
+    int32_t cnt = 0;
+    double sum = 0.0;
+    if (col < F) {
+        for (int64_t i = r0 + rl; i < r1; i += 4) {
+            const float v = X[i * ldx + col];
+            if (!is_missing(v, use_sent, sent)) {
+                ++cnt;
+                sum += (double)v;
+            }
+        }
+    }
+    sc[rl][c] = cnt;
+    ss[rl][c] = sum;
+    __syncthreads();
+    if (rl == 0 && col < F) {
+        pcnt[(int64_t)blockIdx.y * F + col] = sc[0][c] + sc[1][c] + sc[2][c] + sc[3][c];
+        psum[(int64_t)blockIdx.y * F + col] = ((ss[0][c] + ss[1][c]) + ss[2][c]) + ss[3][c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_colstats_final(
+    int R, int64_t F, const int32_t* __restrict__ pcnt, const double* __restrict__ psum,
+    int32_t* __restrict__ ncol, float* __restrict__ mu32, double* __restrict__ mu64)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= F) return;
+    int32_t n = 0;
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) {
+        n += pcnt[(int64_t)r * F + c];
+        s += psum[(int64_t)r * F + c];
+    }
+    const double m = n > 0 ? s / (double)n : 0.0;
+    ncol[c] = n;
+    mu64[c] = m;
+    mu32[c] = (float)m;
+}
+
+int colstats_plan_chunks(int64_t S, int64_t F)
+{
+    const int64_t cb = ceil_div(F, 64);
+    int64_t R = ceil_div(2048, cb);
+    const int64_t rmax = ceil_div(S, 64);
+    if (R > rmax) R = rmax;
+    if (R < 1) R = 1;
+    return (int)R;
+}
+
+void colstats_carve(Carver& c, int64_t S, int64_t F, ColStats& cs)
+{
+    cs.rows_chunks = colstats_plan_chunks(S, F);
+    cs.n = c.take<int32_t>(F);
+    cs.mu32 = c.take<float>(F);
+    cs.mu64 = c.take<double>(F);
+    cs.pcnt = c.take<int32_t>((size_t)cs.rows_chunks * F);
+    cs.psum = c.take<double>((size_t)cs.rows_chunks * F);
+}
+
+int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+                    const ColStats& cs, hipStream_t st)
+{
+    const int R = cs.rows_chunks;
+    const int64_t rows_per = ceil_div(S, R);
+    dim3 g1((unsigned)ceil_div(F, 64), (unsigned)R);
+    hipLaunchKernelGGL(k_colstats_partial, g1, dim3(256), 0, st, X, S, F, ldx, use_sent, sent,
+                       rows_per, cs.pcnt, cs.psum);
+    NAPY_TRY(check_launch("colstats_partial"));
+    hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, R, F,
+                       cs.pcnt, cs.psum, cs.n, cs.mu32, cs.mu64);
+    return check_launch("colstats_final");
+}
+
+// ---------------------------------------------------------------------------
+// gather for subset queries
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(const float* __restrict__ X, int64_t ldx,
+                                                const int32_t* __restrict__ rows, int64_t Sq,
+                                                const int32_t* __restrict__ cols, int64_t Fq,
+                                                float* __restrict__ Xq)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= Fq) return;
+    const int64_t src_c = cols[c];
+    for (int64_t i = blockIdx.y; i < Sq; i += gridDim.y)
+        Xq[i * Fq + c] = X[(int64_t)rows[i] * ldx + src_c];
+}
+
+int gather_launch(const float* X, int64_t ldx, const int32_t* rows, int64_t Sq, const int32_t* cols,
+                  int64_t Fq, float* Xq, hipStream_t st)
+{
+    int64_t gy = Sq < 1024 ? Sq : 1024;
+    if (gy < 1) gy = 1;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)ceil_div(Fq, 256), (unsigned)gy), dim3(256), 0, st,
+                       X, ldx, rows, Sq, cols, Fq, Xq);
+    return check_launch("gather");
+}
+
+// ---------------------------------------------------------------------------
+// K2: tile contractions
+// ---------------------------------------------------------------------------
+template <int PREC>
+struct TileCfg;
+template <>
+struct TileCfg<NAPY_PREC_FP32> {
+    static constexpr int BK = 32;     // samples per LDS slab
+    static constexpr int LDK = 36;    // LDS row stride (elements)
+    static constexpr int FLUSH = 256; // FP32 -> FP64 flush period (samples)
+    static constexpr int RPT = 8;     // rows per thread in the staging step
+};
+template <>
+struct TileCfg<NAPY_PREC_BF16X3> {
+    static constexpr int BK = 32;
+    static constexpr int LDK = 40;
+    static constexpr int FLUSH = 1024;
+    static constexpr int RPT = 8;
+};
+template <>
+struct TileCfg<NAPY_PREC_FP64> {
+    static constexpr int BK = 16;
+    static constexpr int LDK = 18;
+    static constexpr int FLUSH = 0;
+    static constexpr int RPT = 4;
+};
+
+// tile index -> (tg, th), tg <= th, row-major over the upper triangle of T x T
+__device__ __forceinline__ void tile_coords(int t, int T, int& tg, int& th)
+{
+    // start(g) = g*T - g*(g-1)/2
+    int g = (int)((2.0f * T + 1.0f - sqrtf((2.0f * T + 1.0f) * (2.0f * T + 1.0f) - 8.0f * t)) * 0.5f);
+    if (g < 0) g = 0;
+    if (g > T - 1) g = T - 1;
+    while (g > 0 && g * T - g * (g - 1) / 2 > t) --g;
+    while (g + 1 < T && (g + 1) * T - (g + 1) * g / 2 <= t) ++g;
+    tg = g;
+    th = g + (t - (g * T - g * (g - 1) / 2));
+}
+
+// Maps the hardware block index to a logical work index so that every XCD
+// (blocks are dealt to the 8 XCDs round-robin) receives a contiguous range of
+// logical work, which keeps neighbouring tiles' panels in one L2.
+__device__ __forceinline__ int xcd_logical_block(int bid, int nb)
+{
+    const int x = bid & 7, q = bid >> 3;
+    const int base = nb >> 3, rem = nb & 7;
+    return x * base + (x < rem ? x : rem) + q;
+}
+
+template <int PREC>
+struct LdsPlan;
+template <>
+struct LdsPlan<NAPY_PREC_FP32> {
+    static constexpr int ELEMS = 2 * TILE * TileCfg<NAPY_PREC_FP32>::LDK;  // floats per buffer
+};
+template <>
+struct LdsPlan<NAPY_PREC_BF16X3> {
+    static constexpr int ELEMS = 2 * 6 * TILE * TileCfg<NAPY_PREC_BF16X3>::LDK;  // bf16 per buffer
+};
+template <>
+struct LdsPlan<NAPY_PREC_FP64> {
+    static constexpr int ELEMS = 2 * TILE * TileCfg<NAPY_PREC_FP64>::LDK;  // doubles per buffer
+};
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
+__device__ __forceinline__ float from_bf16(__bf16 v) { return (float)v; }
+
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void k_pearson_tiles(
+    const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+    const float* __restrict__ mu32, const double* __restrict__ mu64, int T, int ntiles, int nsplit,
+    int64_t ksplit, double* __restrict__ part)
+{
+    using C = TileCfg<PREC>;
+    constexpr int BK = C::BK, LDK = C::LDK, RPT = C::RPT;
+
+    const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+    const int t = lb / nsplit, split = lb % nsplit;
+    int tg, th;
+    tile_coords(t, T, tg, th);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    const int64_t kbeg = (int64_t)split * ksplit;
+    int64_t kend = kbeg + ksplit;
+    if (kend > S) kend = S;
+    const int nslab = kend > kbeg ? (int)ceil_div(kend - kbeg, BK) : 0;
+
+    // staging coordinates: column c of the panel, rows [kg*RPT, kg*RPT+RPT) of the slab
+    const int sc = tid & 63, kg = tid >> 6;
+    const int64_t colG = (int64_t)tg * TILE + sc, colH = (int64_t)th * TILE + sc;
+    const bool okG = colG < F, okH = colH < F;
+
+    // ---- LDS ----------------------------------------------------------------
+    using LT = typename std::conditional<PREC == NAPY_PREC_FP64, double,
+               typename std::conditional<PREC == NAPY_PREC_FP32, float, __bf16>::type>::type;
+    constexpr int BUF = LdsPlan<PREC>::ELEMS;
+    __shared__ __attribute__((aligned(16))) LT lds[2 * BUF];
+
+    // raw staging registers for the two panels
+    float rawG[RPT], rawH[RPT];
+
+    auto load_raw = [&](int slab) {
+        const int64_t i0 = kbeg + (int64_t)slab * BK + kg * RPT;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int64_t i = i0 + j;
+            const bool in = i < kend;
+            rawG[j] = (in && okG) ? X[i * ldx + colG] : __builtin_nanf("");
+            rawH[j] = (in && okH) ? X[i * ldx + colH] : __builtin_nanf("");
+        }
+    };
+
+    const float muG32 = okG ? mu32[colG] : 0.0f, muH32 = okH ? mu32[colH] : 0.0f;
+    const double muG64 = okG ? mu64[colG] : 0.0, muH64 = okH ? mu64[colH] : 0.0;
+
+    auto store_lds = [&](int buf) {
+        LT* base = lds + buf * BUF;
+        if constexpr (PREC == NAPY_PREC_FP32) {
+            // layout [side][col][LDK]; missing -> NaN
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                float v[RPT];
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const float raw = side ? rawH[j] : rawG[j];
+                    const float mu = side ? muH32 : muG32;
+                    v[j] = is_missing(raw, use_sent, sent) ? __builtin_nanf("") : raw - mu;
+                }
+                float* dst = base + (side * TILE + sc) * LDK + kg * RPT;
+                *(f32x4*)(dst) = f32x4{v[0], v[1], v[2], v[3]};
+                *(f32x4*)(dst + 4) = f32x4{v[4], v[5], v[6], v[7]};
+            }
+        } else if constexpr (PREC == NAPY_PREC_FP64) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                double v[RPT];
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const float raw = side ? rawH[j] : rawG[j];
+                    const double mu = side ? muH64 : muG64;
+                    v[j] = is_missing(raw, use_sent, sent) ? __builtin_nan("") : (double)raw - mu;
+                }
+                double* dst = base + (side * TILE + sc) * LDK + kg * RPT;
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) dst[j] = v[j];
+            }
+        } else {
+            // BF16X3: layout [side][plane][col][LDK], planes xh, xl, qh, qm, ql, m
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                bf16x8 pl[6];
+#pragma unroll
+                for (int j = 0; j < RPT; ++j) {
+                    const float raw = side ? rawH[j] : rawG[j];
+                    const float mu = side ? muH32 : muG32;
+                    const bool miss = is_missing(raw, use_sent, sent);
+                    const float x = miss ? 0.0f : raw - mu;
+                    const __bf16 xh = to_bf16(x);
+                    const __bf16 xl = to_bf16(x - from_bf16(xh));
+                    const float q = x * x;
+                    const __bf16 qh = to_bf16(q);
+                    const float q1 = q - from_bf16(qh);
+                    const __bf16 qm = to_bf16(q1);
+                    const __bf16 ql = to_bf16(q1 - from_bf16(qm));
+                    pl[0][j] = xh;
+                    pl[1][j] = xl;
+                    pl[2][j] = qh;
+                    pl[3][j] = qm;
+                    pl[4][j] = ql;
+                    pl[5][j] = miss ? to_bf16(0.0f) : to_bf16(1.0f);
+                }
+#pragma unroll
+                for (int pp = 0; pp < 6; ++pp)
+                    *(bf16x8*)(base + ((side * 6 + pp) * TILE + sc) * LDK + kg * RPT) = pl[pp];
+            }
+        }
+    };
+
+    // ---- accumulators ---------------------------------------------------------
+    // BF16X3: one 32x32 block per wave, acc32[stat] f32x16.
+    // FP32/FP64: four 16x16 sub-blocks per wave, acc[sub][stat] x4.
+    constexpr int NSUB = (PREC == NAPY_PREC_BF16X3) ? 1 : 4;
+    constexpr int NREG = (PREC == NAPY_PREC_BF16X3) ? 16 : 4;
+    using AccT = typename std::conditional<PREC == NAPY_PREC_FP64, double, float>::type;
+    AccT acc[NSUB][NSTAT][NREG];
+    double acc64[NSUB][NSTAT][NREG];
+#pragma unroll
+    for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+        for (int s = 0; s < NSTAT; ++s)
+#pragma unroll
+            for (int r = 0; r < NREG; ++r) {
+                acc[a][s][r] = 0;
+                acc64[a][s][r] = 0.0;
+            }
+
+    auto flush = [&]() {
+        if constexpr (PREC != NAPY_PREC_FP64) {
+#pragma unroll
+            for (int a = 0; a < NSUB; ++a)
+#pragma unroll
+                for (int s = 0; s < NSTAT; ++s)
+#pragma unroll
+                    for (int r = 0; r < NREG; ++r) {
+                        acc64[a][s][r] += (double)acc[a][s][r];
+                        acc[a][s][r] = 0.0f;
+                    }
+        }
+    };
+
+    auto compute = [&](int buf) {
+        const LT* base = lds + buf * BUF;
+        if constexpr (PREC == NAPY_PREC_BF16X3) {
+            const int rr = lane & 31, kq = (lane >> 5) * 8;
+#pragma unroll
+            for (int kk = 0; kk < BK / 16; ++kk) {
+                const int k = kk * 16 + kq;
+                bf16x8 a[6], b[6];
+#pragma unroll
+                for (int pp = 0; pp < 6; ++pp) {
+                    a[pp] = *(const bf16x8*)(base + ((0 * 6 + pp) * TILE + wm * 32 + rr) * LDK + k);
+                    b[pp] = *(const bf16x8*)(base + ((1 * 6 + pp) * TILE + wn * 32 + rr) * LDK + k);
+                }
+                f32x16 cn, cx, cy, cxx, cyy, cxy;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    cn[r] = acc[0][0][r];
+                    cx[r] = acc[0][1][r];
+                    cy[r] = acc[0][2][r];
+                    cxx[r] = acc[0][3][r];
+                    cyy[r] = acc[0][4][r];
+                    cxy[r] = acc[0][5][r];
+                }
+                cn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[5], cn, 0, 0, 0);
+                cx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[5], cx, 0, 0, 0);
+                cy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[0], cy, 0, 0, 0);
+                cxx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[5], cxx, 0, 0, 0);
+                cyy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[2], cyy, 0, 0, 0);
+                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], cxy, 0, 0, 0);
+                cx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[5], cx, 0, 0, 0);
+                cy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[1], cy, 0, 0, 0);
+                cxx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[5], cxx, 0, 0, 0);
+                cyy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[3], cyy, 0, 0, 0);
+                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], cxy, 0, 0, 0);
+                cxx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[4], b[5], cxx, 0, 0, 0);
+                cyy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[4], cyy, 0, 0, 0);
+                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], cxy, 0, 0, 0);
+                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], cxy, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    acc[0][0][r] = cn[r];
+                    acc[0][1][r] = cx[r];
+                    acc[0][2][r] = cy[r];
+                    acc[0][3][r] = cxx[r];
+                    acc[0][4][r] = cyy[r];
+                    acc[0][5][r] = cxy[r];
+                }
+            }
+        } else {
+            const int rr = lane & 15, kq = lane >> 4;
+#pragma unroll
+            for (int kk = 0; kk < BK / 4; ++kk) {
+                const int k = kk * 4 + kq;
+                AccT xa[2], ma[2], qa[2], xb[2], mb[2], qb[2];
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const AccT va = base[(0 * TILE + wm * 32 + s2 * 16 + rr) * LDK + k];
+                    const AccT vb = base[(1 * TILE + wn * 32 + s2 * 16 + rr) * LDK + k];
+                    const bool pa = va == va, pb = vb == vb;
+                    xa[s2] = pa ? va : (AccT)0;
+                    ma[s2] = pa ? (AccT)1 : (AccT)0;
+                    qa[s2] = xa[s2] * xa[s2];
+                    xb[s2] = pb ? vb : (AccT)0;
+                    mb[s2] = pb ? (AccT)1 : (AccT)0;
+                    qb[s2] = xb[s2] * xb[s2];
+                }
+#pragma unroll
+                for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) {
+                        const int sub = ia * 2 + ib;
+                        if constexpr (PREC == NAPY_PREC_FP32) {
+                            f32x4 c[NSTAT];
+#pragma unroll
+                            for (int s = 0; s < NSTAT; ++s)
+                                c[s] = f32x4{acc[sub][s][0], acc[sub][s][1], acc[sub][s][2], acc[sub][s][3]};
+                            c[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], mb[ib], c[0], 0, 0, 0);
+                            c[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ia], mb[ib], c[1], 0, 0, 0);
+                            c[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], xb[ib], c[2], 0, 0, 0);
+                            c[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[ia], mb[ib], c[3], 0, 0, 0);
+                            c[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], qb[ib], c[4], 0, 0, 0);
+                            c[5] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ia], xb[ib], c[5], 0, 0, 0);
+#pragma unroll
+                            for (int s = 0; s < NSTAT; ++s)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) acc[sub][s][r] = c[s][r];
+                        } else {
+                            f64x4 c[NSTAT];
+#pragma unroll
+                            for (int s = 0; s < NSTAT; ++s)
+                                c[s] = f64x4{acc[sub][s][0], acc[sub][s][1], acc[sub][s][2], acc[sub][s][3]};
+                            c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], mb[ib], c[0], 0, 0, 0);
+                            c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ia], mb[ib], c[1], 0, 0, 0);
+                            c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], xb[ib], c[2], 0, 0, 0);
+                            c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[ia], mb[ib], c[3], 0, 0, 0);
+                            c[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], qb[ib], c[4], 0, 0, 0);
+                            c[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ia], xb[ib], c[5], 0, 0, 0);
+#pragma unroll
+                            for (int s = 0; s < NSTAT; ++s)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) acc[sub][s][r] = c[s][r];
+                        }
+                    }
+            }
+        }
+    };
+
+    // ---- main loop: one barrier per slab, staging of slab s+1 overlaps the
+    // contractions of slab s ------------------------------------------------------
+    constexpr int FLUSH_SLABS = C::FLUSH > 0 ? C::FLUSH / BK : 0;
+    if (nslab > 0) {
+        load_raw(0);
+        store_lds(0);
+        __syncthreads();
+        for (int s = 0; s < nslab; ++s) {
+            const bool more = s + 1 < nslab;
+            if (more) load_raw(s + 1);
+            compute(s & 1);
+            if (more) store_lds((s + 1) & 1);
+            if constexpr (FLUSH_SLABS > 0) {
+                if ((s + 1) % FLUSH_SLABS == 0) flush();
+            }
+            __syncthreads();
+        }
+    }
+    flush();
+
+    // ---- epilogue: FP64 partials [split][stat][tile][64][64] -----------------------
+#pragma unroll
+    for (int s = 0; s < NSTAT; ++s) {
+        double* dst = part + (((int64_t)split * NSTAT + s) * ntiles + t) * TILE_ELEMS;
+        if constexpr (PREC == NAPY_PREC_BF16X3) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int j = wn * 32 + (lane & 31);
+                dst[i * TILE + j] = acc64[0][s][r];
+            }
+        } else {
+#pragma unroll
+            for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = wm * 32 + ia * 16 + 4 * (lane >> 4) + r;
+                        const int j = wn * 32 + ib * 16 + (lane & 15);
+                        const double v = (PREC == NAPY_PREC_FP64) ? (double)acc[ia * 2 + ib][s][r]
+                                                                   : acc64[ia * 2 + ib][s][r];
+                        dst[i * TILE + j] = v;
+                    }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: combine split-K partials, r, p, n; both triangles
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pearson_combine(
+    const double* __restrict__ part, int T, int ntiles, int nsplit, int64_t F, double var_tol,
+    double* __restrict__ r, double* __restrict__ p, int32_t* __restrict__ n, int64_t ldo,
+    double* __restrict__ saved)
+{
+    const int t = blockIdx.x / (TILE_ELEMS / 256);
+    const int e = (blockIdx.x % (TILE_ELEMS / 256)) * 256 + threadIdx.x;
+    int tg, th;
+    tile_coords(t, T, tg, th);
+    const int i = e / TILE, j = e % TILE;
+    const int64_t g = (int64_t)tg * TILE + i, h = (int64_t)th * TILE + j;
+    if (g >= F || h >= F) return;
+    if (tg == th && i > j) return;
+    double st[NSTAT];
+#pragma unroll
+    for (int s = 0; s < NSTAT; ++s) st[s] = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+        for (int s = 0; s < NSTAT; ++s)
+            st[s] += part[(((int64_t)sp * NSTAT + s) * ntiles + t) * TILE_ELEMS + e];
+    const double cn = st[0], sx = st[1], sy = st[2], sxx = st[3], syy = st[4], sxy = st[5];
+    const int64_t ni = (int64_t)(cn + 0.5);
+    double rv = __builtin_nan(""), pv = __builtin_nan("");
+    if (ni >= 2) {
+        const double vx = cn * sxx - sx * sx;
+        const double vy = cn * syy - sy * sy;
+        if (vx > var_tol * cn * sxx && vy > var_tol * cn * syy) {
+            const double cxy = cn * sxy - sx * sy;
+            rv = cxy / sqrt(vx * vy);
+            rv = rv > 1.0 ? 1.0 : (rv < -1.0 ? -1.0 : rv);
+            pv = (ni == 2) ? 1.0 : corr_pvalue(rv, ni);
+        }
+    }
+    if (r) {
+        r[g * ldo + h] = rv;
+        r[h * ldo + g] = rv;
+    }
+    if (p) {
+        p[g * ldo + h] = pv;
+        p[h * ldo + g] = pv;
+    }
+    if (n) {
+        n[g * ldo + h] = (int32_t)ni;
+        n[h * ldo + g] = (int32_t)ni;
+    }
+    if (saved) {
+        const int64_t FF = F * F;
+        const double vgh[NSTAT] = {cn, sx, sy, sxx, syy, sxy};
+        const double vhg[NSTAT] = {cn, sy, sx, syy, sxx, sxy};
+#pragma unroll
+        for (int s = 0; s < NSTAT; ++s) {
+            saved[s * FF + g * F + h] = vgh[s];
+            saved[s * FF + h * F + g] = vhg[s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+struct PearsonPlan {
+    int T, ntiles, nsplit;
+    int64_t ksplit;
+};
+
+static PearsonPlan pearson_plan(int64_t S, int64_t F, int prec)
+{
+    PearsonPlan pl;
+    pl.T = (int)ceil_div(F, TILE);
+    pl.ntiles = pl.T * (pl.T + 1) / 2;
+    const int BK = (prec == NAPY_PREC_FP64) ? 16 : 32;
+    int64_t want = ceil_div(512, pl.ntiles);
+    int64_t maxs = S / 512;
+    if (maxs < 1) maxs = 1;
+    if (want > maxs) want = maxs;
+    if (want < 1) want = 1;
+    pl.ksplit = round_up(ceil_div(S, want), BK);
+    if (pl.ksplit < BK) pl.ksplit = BK;
+    pl.nsplit = (int)ceil_div(S, pl.ksplit);
+    if (pl.nsplit < 1) pl.nsplit = 1;
+    return pl;
+}
+
+static void pearson_carve(Carver& c, int64_t S, int64_t F, int prec, ColStats& cs, double** part)
+{
+    PearsonPlan pl = pearson_plan(S, F, prec);
+    colstats_carve(c, S, F, cs);
+    *part = c.take<double>((size_t)pl.nsplit * NSTAT * pl.ntiles * TILE_ELEMS);
+}
+
+size_t pearson_ws_bytes(int64_t S, int64_t F, int prec)
+{
+    Carver c(nullptr);
+    ColStats cs;
+    double* part;
+    pearson_carve(c, S, F, prec, cs, &part);
+    return c.bytes();
+}
+
+int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
+                int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
+                const napy_opts* opts, hipStream_t st)
+{
+    const int prec = opt_prec(opts);
+    const int us = opt_use_sent(opts);
+    const float sv = opt_sent(opts);
+    (void)ws_bytes;
+    Carver c(ws);
+    ColStats cs;
+    double* part;
+    pearson_carve(c, S, F, prec, cs, &part);
+    PearsonPlan pl = pearson_plan(S, F, prec);
+
+    NAPY_TRY(colstats_launch(X, S, F, ldx, us, sv, cs, st));
+    const unsigned nb = (unsigned)(pl.ntiles * pl.nsplit);
+    switch (prec) {
+    case NAPY_PREC_FP32:
+        hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_FP32>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv,
+                           cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
+        break;
+    case NAPY_PREC_BF16X3:
+        hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_BF16X3>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us,
+                           sv, cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
+        break;
+    default:
+        hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_FP64>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv,
+                           cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
+        break;
+    }
+    NAPY_TRY(check_launch("pearson_tiles"));
+    const double tol = (prec == NAPY_PREC_FP64) ? 1e-12 : 1e-5;
+    hipLaunchKernelGGL(k_pearson_combine, dim3((unsigned)(pl.ntiles * (TILE_ELEMS / 256))), dim3(256), 0, st,
+                       part, pl.T, pl.ntiles, pl.nsplit, F, tol, r, p, n, ldo, saved);
+    return check_launch("pearson_combine");
+}
+
+}  // namespace napy

@@ -1,0 +1,111 @@
+// Two-sided p-value of a correlation coefficient, FP64.
+//
+// NApy (arXiv 2505.00448) takes Pearson's p from the Beta CDF (Section 3.5.2)
+// and Spearman's from the t distribution (Section 3.5.3).  Under the null the
+// coefficient r on [-1, 1] follows Beta(n/2 - 1, n/2 - 1), and the two-sided
+// tail is the regularized incomplete beta function
+//
+//     p = I_{1 - r^2}(a, 1/2),   a = (n - 2) / 2,
+//
+// which is also the two-sided Student-t tail with n - 2 degrees of freedom.
+//
+// Method: the continued fraction of I_x(a, b) (Abramowitz & Stegun 26.5.8)
+// evaluated with the modified Lentz algorithm (Lentz 1976; Thompson & Barnett
+// 1986).  It converges fast for x < (a + 1) / (a + b + 2); otherwise the
+// symmetry I_x(a, b) = 1 - I_{1-x}(b, a) is used, so the tail that is computed
+// directly is always the small one.  The prefactor x^a (1-x)^b / (a B(a,b)) is
+// formed in logs.  ln B(a, 1/2) = ln(sqrt(pi)) - [ln G(a + 1/2) - ln G(a)];
+// for a >= 20 the bracket is evaluated as 0.5 ln a plus the asymptotic series
+// obtained from Stirling's series of both log-gammas (so no two large
+// log-gammas are subtracted), below that from lgamma directly.
+//
+// Compiled for host and device: the host copy serves only to unit-test the
+// arithmetic on a machine without a GPU.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#ifndef NAPY_HD
+#define NAPY_HD __host__ __device__
+#endif
+
+namespace napy {
+
+// ln G(a + 1/2) - ln G(a)
+NAPY_HD inline double lgamma_half_ratio(double a)
+{
+    if (a >= 20.0) {
+        const double ia = 1.0 / a;
+        const double ia2 = ia * ia;
+        // -1/(8a) + 1/(192a^3) - 1/(640a^5) + 17/(14336a^7) - 31/(18432a^9)
+        double s = -31.0 / 18432.0;
+        s = s * ia2 + 17.0 / 14336.0;
+        s = s * ia2 - 1.0 / 640.0;
+        s = s * ia2 + 1.0 / 192.0;
+        s = s * ia2 - 1.0 / 8.0;
+        return 0.5 * log(a) + s * ia;
+    }
+    return lgamma(a + 0.5) - lgamma(a);
+}
+
+// Continued fraction part of I_x(a, b) (modified Lentz).  Returns h with
+// I_x(a, b) = x^a (1-x)^b / (a B(a, b)) * h.
+NAPY_HD inline double betacf_lentz(double a, double b, double x)
+{
+    const double tiny = 1e-300;
+    const double eps = 1e-16;
+    const double qab = a + b, qap = a + 1.0, qam = a - 1.0;
+    double c = 1.0;
+    double d = 1.0 - qab * x / qap;
+    if (fabs(d) < tiny) d = tiny;
+    d = 1.0 / d;
+    double h = d;
+    for (int m = 1; m <= 2000; ++m) {
+        const double dm = (double)m;
+        const double m2 = 2.0 * dm;
+        double aa = dm * (b - dm) * x / ((qam + m2) * (a + m2));
+        d = 1.0 + aa * d;
+        if (fabs(d) < tiny) d = tiny;
+        c = 1.0 + aa / c;
+        if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        h *= d * c;
+        aa = -(a + dm) * (qab + dm) * x / ((a + m2) * (qap + m2));
+        d = 1.0 + aa * d;
+        if (fabs(d) < tiny) d = tiny;
+        c = 1.0 + aa / c;
+        if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        const double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < eps) break;
+    }
+    return h;
+}
+
+// p = I_{1-r^2}((n-2)/2, 1/2) for n >= 3 and finite r; NaN otherwise.
+NAPY_HD inline double corr_pvalue(double r, int64_t n)
+{
+    if (!(r == r) || n < 3) return NAN;
+    const double ar = fabs(r);
+    if (ar >= 1.0) return 0.0;
+    if (ar == 0.0) return 1.0;
+    const double a = 0.5 * (double)(n - 2);
+    const double y = ar * ar;                 // r^2
+    const double x = (1.0 - ar) * (1.0 + ar); // 1 - r^2 without cancellation
+    const double lnx = log1p(-y);
+    const double lny = 2.0 * log(ar);
+    // ln B(a, 1/2) = 0.5 ln(pi) - [ln G(a+1/2) - ln G(a)]
+    const double lnB = 0.57236494292470008707 - lgamma_half_ratio(a);
+    if (x < (a + 1.0) / (a + 2.5)) {
+        const double lf = a * lnx + 0.5 * lny - log(a) - lnB;
+        return exp(lf) * betacf_lentz(a, 0.5, x);
+    }
+    // 1 - I_{r^2}(1/2, a)
+    const double lf = 0.5 * lny + a * lnx + 0.69314718055994530942 - lnB;
+    double p = 1.0 - exp(lf) * betacf_lentz(0.5, a, y);
+    return p < 0.0 ? 0.0 : p;
+}
+
+}  // namespace napy

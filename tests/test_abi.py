@@ -1,0 +1,151 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol that
+include/napy.h declares, rejects bad arguments on the host before touching the
+device, and its p-value arithmetic (compiled for the host through the
+napy_pvalue_host hook) matches the definition."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2505_00448_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "napy.h")
+
+
+def _declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(napy_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    decl = _declared_symbols()
+    assert len(decl) >= 19
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == decl
+    # the exported names of the shared object itself (dynamic symbol table)
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (napy_[a-z0-9_]+)\b", out))
+    assert set(decl) <= exported
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for st in range(5):
+        assert lib.napy_strerror(st)
+    assert lib.napy_version() == b"0.1.0"
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def test_invalid_arguments_rejected_on_host():
+    lib = _lib.load()
+    o = _lib.make_opts("fp32")
+    O = ctypes.byref(o)
+    ws_need = lib.napy_pearson_workspace(100, 10, O)
+    assert ws_need > 0
+    # NULL X
+    assert lib.napy_pearson(None, 100, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, ws_need, O, None) == _lib.NAPY_E_INVALID
+    # negative S, F = 0
+    assert lib.napy_pearson(FAKE, -1, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, ws_need, O, None) == _lib.NAPY_E_INVALID
+    assert lib.napy_pearson(FAKE, 100, 0, 10, FAKE, FAKE, FAKE, 10, FAKE, ws_need, O, None) == _lib.NAPY_E_INVALID
+    # ldx, ldo too small
+    assert lib.napy_pearson(FAKE, 100, 10, 9, FAKE, FAKE, FAKE, 10, FAKE, ws_need, O, None) == _lib.NAPY_E_INVALID
+    assert lib.napy_pearson(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 9, FAKE, ws_need, O, None) == _lib.NAPY_E_INVALID
+    # workspace missing / too small / misaligned
+    assert lib.napy_pearson(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 10, None, ws_need, O, None) == _lib.NAPY_E_WORKSPACE
+    assert lib.napy_pearson(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, ws_need - 1, O, None) == _lib.NAPY_E_WORKSPACE
+    assert lib.napy_pearson(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 10, ctypes.c_void_p(0x1004), ws_need, O,
+                            None) == _lib.NAPY_E_WORKSPACE
+    # bad options
+    bad = _lib.make_opts("fp32")
+    bad.precision = 7
+    assert lib.napy_pearson(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, ws_need, ctypes.byref(bad),
+                            None) == _lib.NAPY_E_INVALID
+    bad = _lib.make_opts("fp32")
+    bad.reserved = 1
+    assert lib.napy_pearson_workspace(100, 10, ctypes.byref(bad)) == 0
+    # too many variables
+    assert lib.napy_pearson(FAKE, 100, 70000, 70000, FAKE, FAKE, FAKE, 70000, FAKE, 1 << 40, O,
+                            None) == _lib.NAPY_E_UNSUPPORTED
+    # Spearman sample limit
+    assert lib.napy_spearman_workspace(30000, 10, O) == 0
+    assert lib.napy_spearman(FAKE, 30000, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, 1 << 30, O,
+                             None) == _lib.NAPY_E_UNSUPPORTED
+    sw = lib.napy_spearman_workspace(100, 10, O)
+    assert sw > 0
+    assert lib.napy_spearman(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, sw - 1, O, None) == _lib.NAPY_E_WORKSPACE
+    # backward
+    bw = lib.napy_pearson_backward_workspace(100, 10, O)
+    assert lib.napy_pearson_backward(FAKE, 100, 10, 10, None, FAKE, 10, FAKE, 10, FAKE, bw, O,
+                                     None) == _lib.NAPY_E_INVALID
+    assert lib.napy_pearson_backward(FAKE, 100, 10, 10, FAKE, FAKE, 9, FAKE, 10, FAKE, bw, O,
+                                     None) == _lib.NAPY_E_INVALID
+    # subsets
+    assert lib.napy_pearson_subset(FAKE, 100, 10, 10, FAKE, 200, FAKE, 5, FAKE, FAKE, FAKE, 5, FAKE, 1 << 30, O,
+                                   None) == _lib.NAPY_E_INVALID  # Sq > S
+    assert lib.napy_spearman_subset(None, 100, 10, FAKE, 50, FAKE, 5, FAKE, FAKE, FAKE, 5, FAKE, 1 << 30, O,
+                                    None) == _lib.NAPY_E_INVALID
+    assert lib.napy_spearman_base_prepare(FAKE, 100, 10, 10, FAKE, 1, O, None) == _lib.NAPY_E_WORKSPACE
+    # debug hooks
+    assert lib.napy_spearman_pair_ranks(FAKE, 100, 10, 10, 10, 0, FAKE, FAKE, FAKE, 1 << 30, O,
+                                        None) == _lib.NAPY_E_INVALID
+    assert lib.napy_pvalue_device(None, None, None, 5, None) == _lib.NAPY_E_INVALID
+    assert lib.napy_pvalue_device(None, None, None, 0, None) == _lib.NAPY_OK
+
+
+def test_workspace_queries_grow_with_shape():
+    lib = _lib.load()
+    for prec in ("fp32", "bf16x3", "fp64"):
+        o = _lib.make_opts(prec)
+        a = lib.napy_pearson_workspace(1000, 100, ctypes.byref(o))
+        b = lib.napy_pearson_workspace(10000, 1000, ctypes.byref(o))
+        assert 0 < a < b
+        assert a % 256 == 0 and b % 256 == 0
+    o = _lib.make_opts("fp32")
+    assert 0 < lib.napy_spearman_workspace(100, 10, ctypes.byref(o)) < lib.napy_spearman_workspace(
+        10000, 1000, ctypes.byref(o))
+    assert lib.napy_spearman_base_bytes(20000, 2000) > 0
+
+
+def _host_p(r, n):
+    lib = _lib.load()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    p = np.empty_like(r)
+    st = lib.napy_pvalue_host(r.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+                              p.ctypes.data_as(ctypes.c_void_p), r.size)
+    assert st == _lib.NAPY_OK
+    return p
+
+
+def test_pvalue_arithmetic_closed_forms():
+    rs = np.array([0.0, 0.2, -0.45, 0.9, -0.999, 1.0, -1.0])
+    p3 = _host_p(rs, np.full(rs.size, 3))
+    p4 = _host_p(rs, np.full(rs.size, 4))
+    assert np.allclose(p3, 1 - 2 / np.pi * np.arcsin(np.abs(rs)), rtol=0, atol=1e-14)
+    assert np.allclose(p4, 1 - np.abs(rs), rtol=0, atol=1e-14)
+    assert np.all(np.isnan(_host_p([0.5, np.nan], [2, 10])))
+
+
+def test_pvalue_arithmetic_against_mpmath():
+    from oracle import oracle as orc
+    rng = np.random.default_rng(12)
+    ns = rng.choice([5, 9, 21, 40, 41, 42, 100, 999, 6650, 10000, 24576], size=300)
+    rs = np.where(ns > 2000, rng.uniform(-0.08, 0.08, ns.size), rng.uniform(-0.995, 0.995, ns.size))
+    p = _host_p(rs, ns)
+    for r, n, pv in zip(rs, ns, p):
+        ref = orc.pvalue_mp(float(r), int(n))
+        if ref < 1e-300:
+            assert pv < 1e-290
+        else:
+            assert abs(pv - ref) <= 1e-12 * ref, (r, n, pv, ref)

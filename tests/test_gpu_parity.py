@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: counts and ranks bit-exact; Pearson |dr| <= 1e-6 (FP32, BF16x3) and
+<= 1e-12 (FP64 validation mode); Spearman |drho| <= 1e-12; NaN placement
+exact; p through its conditioning (tests/parity_util.py).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as orc
+from parity_util import assert_counts_equal, assert_p_close, assert_r_close
+
+pytestmark = pytest.mark.gpu
+
+R_TOL = {"fp32": 1e-6, "bf16x3": 1e-6, "fp64": 1e-12}
+
+
+def _napy():
+    import paper_2505_00448_amd as napy
+    return napy
+
+
+def _to_dev(X, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _run(method, X, dev, precision="fp32", missing=None):
+    napy = _napy()
+    Xd = _to_dev(X, dev)
+    if method == "pearson":
+        out = napy.pearson(Xd, precision=precision, missing=missing)
+    else:
+        out = napy.spearman(Xd, missing=missing)
+    return _np(out["r"]), _np(out["p"]), _np(out["n"])
+
+
+def _check_full(method, X, dev, precision="fp32", missing=None, where=""):
+    r, p, n = _run(method, X, dev, precision, missing)
+    if method == "pearson":
+        ro, po, no = orc.pearson(X, missing=missing)
+        tol = R_TOL[precision]
+    else:
+        ro, po, no = orc.spearman(X, missing=missing)
+        tol = 1e-12
+    assert_counts_equal(n, no, where)
+    worst = assert_r_close(r, ro, tol, where)
+    assert_p_close(p, po, ro, no, max(worst, 1e-15), where)
+    assert np.array_equal(r, r.T, equal_nan=True), f"{where}: r not symmetric"
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# small configuration (500 x 50), all methods and precisions
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
+def test_pearson_small(gpu_device, precision):
+    X = synth.cfg_plain_small()
+    _check_full("pearson", X, gpu_device, precision, where=f"pearson-500x50-{precision}")
+
+
+def test_spearman_small(gpu_device):
+    X = synth.cfg_plain_small()
+    _check_full("spearman", X, gpu_device, where="spearman-500x50")
+
+
+def test_spearman_heavy_ties(gpu_device):
+    X = synth.heavy_ties(700, 40, levels=5, missing=0.2)
+    _check_full("spearman", X, gpu_device, where="spearman-heavy-ties")
+
+
+@pytest.mark.parametrize("method", ["pearson", "spearman"])
+def test_edge_matrix(gpu_device, method):
+    X = synth.edge_matrix()
+    precisions = ["fp32", "bf16x3", "fp64"] if method == "pearson" else ["fp32"]
+    for prec in precisions:
+        _check_full(method, X, gpu_device, prec, where=f"edge-{method}-{prec}")
+
+
+# ---------------------------------------------------------------------------
+# ragged shapes: several tiles, partial tiles, tiny and empty inputs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("S,F", [(1, 3), (2, 5), (3, 1), (0, 4), (777, 130), (1500, 65), (64, 64), (65, 129)])
+def test_ragged_shapes(gpu_device, S, F):
+    rng = np.random.default_rng(S * 1000 + F)
+    X = rng.standard_normal((S, F)).astype(np.float32)
+    if S:
+        X[rng.random((S, F)) < 0.25] = np.nan
+    for prec in ("fp32", "bf16x3", "fp64"):
+        _check_full("pearson", X, gpu_device, prec, where=f"ragged-pearson-{S}x{F}-{prec}")
+    _check_full("spearman", X, gpu_device, where=f"ragged-spearman-{S}x{F}")
+
+
+def test_paper_shape(gpu_device):
+    X = synth.paper_shape(250, 250)
+    _check_full("pearson", X, gpu_device, "fp32", where="paper-shape-pearson")
+    _check_full("pearson", X, gpu_device, "bf16x3", where="paper-shape-pearson-bf16x3")
+    _check_full("spearman", X, gpu_device, where="paper-shape-spearman")
+
+
+def test_sentinel_missing_value(gpu_device):
+    X = synth.cfg_plain_small(F=20)
+    Xs = np.where(np.isnan(X), np.float32(-999.0), X).astype(np.float32)
+    for method in ("pearson", "spearman"):
+        r1, p1, n1 = _run(method, X, gpu_device)
+        r2, p2, n2 = _run(method, Xs, gpu_device, missing=-999.0)
+        assert np.array_equal(n1, n2)
+        assert np.array_equal(r1, r2, equal_nan=True)
+
+
+def test_signed_zero_and_constant_subsets(gpu_device):
+    rng = np.random.default_rng(1)
+    S = 300
+    x = rng.standard_normal(S).astype(np.float32)
+    zeros = np.where(rng.random(S) < 0.5, np.float32(0.0), np.float32(-0.0))
+    const_on_subset = np.where(np.arange(S) < 150, np.float32(2.0), x)
+    binary = (rng.random(S) < 0.5).astype(np.float32)
+    pois = rng.poisson(4, S).astype(np.float32)
+    X = np.stack([x, zeros, const_on_subset, binary, pois, -x], axis=1)
+    miss = np.zeros_like(X, dtype=bool)
+    miss[150:, 0] = True  # column 0 only present where column 2 is constant
+    X[miss] = np.nan
+    for prec in ("fp32", "bf16x3", "fp64"):
+        _check_full("pearson", X, gpu_device, prec, where=f"constant-subsets-{prec}")
+    _check_full("spearman", X, gpu_device, where="constant-subsets-spearman")
+
+
+# ---------------------------------------------------------------------------
+# ranks, bit-exact
+# ---------------------------------------------------------------------------
+
+def test_pair_ranks_bit_exact(gpu_device):
+    napy = _napy()
+    X = np.concatenate([synth.heavy_ties(900, 6, levels=4, missing=0.3),
+                        synth.cfg_plain_small(S=900, F=6)], axis=1)
+    Xd = _to_dev(X, gpu_device)
+    for g, h in [(0, 1), (2, 7), (8, 9), (3, 3), (11, 4), (6, 10)]:
+        rg, rh = napy.spearman_pair_ranks(Xd, g, h)
+        og, oh, n = orc.pair_ranks(X, g, h)
+        exp_g = np.where(np.isnan(og), -1, np.round(2 * np.nan_to_num(og))).astype(np.int64)
+        exp_h = np.where(np.isnan(oh), -1, np.round(2 * np.nan_to_num(oh))).astype(np.int64)
+        assert np.array_equal(_np(rg).astype(np.int64), exp_g), (g, h)
+        assert np.array_equal(_np(rh).astype(np.int64), exp_h), (g, h)
+
+
+# ---------------------------------------------------------------------------
+# p-value routine at the GPU's own (r, n)
+# ---------------------------------------------------------------------------
+
+def test_device_pvalue_against_mpmath(gpu_device):
+    import torch
+    napy = _napy()
+    rng = np.random.default_rng(5)
+    ns = np.array([3, 4, 5, 7, 10, 37, 100, 1000, 3500, 6650, 10000, 20000, 24576] * 12, dtype=np.int32)
+    rs = np.concatenate([rng.uniform(-0.999, 0.999, ns.size // 2),
+                         rng.uniform(-0.05, 0.05, ns.size - ns.size // 2)])
+    p = _np(napy.pvalue_device(torch.from_numpy(rs).to(gpu_device), torch.from_numpy(ns).to(gpu_device)))
+    for r, n, pv in zip(rs, ns, p):
+        ref = orc.pvalue_mp(float(r), int(n))
+        if ref < 1e-300:
+            assert pv < 1e-290
+        else:
+            assert abs(pv - ref) <= 1e-10 * ref, (r, n, pv, ref)
+    # closed forms
+    p3 = _np(napy.pvalue_device(torch.tensor([0.3, -0.8], dtype=torch.float64, device=gpu_device),
+                                torch.tensor([3, 4], dtype=torch.int32, device=gpu_device)))
+    assert abs(p3[0] - (1 - 2 / math.pi * math.asin(0.3))) <= 1e-13
+    assert abs(p3[1] - 0.2) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# determinism and subset queries
+# ---------------------------------------------------------------------------
+
+def test_bitwise_determinism(gpu_device):
+    X = synth.cfg_gpu_headline(S=3000, F=200)
+    for method, prec in (("pearson", "fp32"), ("pearson", "bf16x3"), ("spearman", "fp32")):
+        a = _run(method, X, gpu_device, prec)
+        b = _run(method, X, gpu_device, prec)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v, equal_nan=True), (method, prec)
+
+
+def test_subset_queries_match_full_calls(gpu_device):
+    import torch
+    napy = _napy()
+    X = synth.cfg_serving_base(S=2000, F=150)
+    Xd = _to_dev(X, gpu_device)
+    base = napy.SpearmanBase(Xd)
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        rows = np.sort(rng.choice(2000, size=int(rng.integers(50, 1900)), replace=False)).astype(np.int32)
+        cols = rng.choice(150, size=int(rng.integers(2, 150)), replace=False).astype(np.int32)
+        rt = torch.from_numpy(rows).to(gpu_device)
+        ct = torch.from_numpy(cols).to(gpu_device)
+        sub = X[np.ix_(rows, cols)]
+        for prec in ("fp32", "bf16x3"):
+            got = napy.pearson_subset(Xd, rt, ct, precision=prec)
+            ref = napy.pearson(_to_dev(sub, gpu_device), precision=prec)
+            for k in ("r", "p", "n"):
+                assert np.array_equal(_np(got[k]), _np(ref[k]), equal_nan=True), (trial, prec, k)
+        got = base.subset(rt, ct)
+        ref = napy.spearman(_to_dev(sub, gpu_device))
+        for k in ("r", "p", "n"):
+            assert np.array_equal(_np(got[k]), _np(ref[k]), equal_nan=True), (trial, "spearman", k)
+        # and against the oracle
+        ro, po, no = orc.spearman(sub)
+        assert_counts_equal(_np(got["n"]), no, "subset-spearman")
+        assert_r_close(_np(got["r"]), ro, 1e-12, "subset-spearman")
+
+
+# ---------------------------------------------------------------------------
+# full-size headline configuration (10,000 x 1,000): sampled pairs + properties
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def headline():
+    return synth.cfg_gpu_headline()
+
+
+def _sample_pairs(F, k, seed):
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, F, k)
+    h = rng.integers(0, F, k)
+    d = np.arange(0, F, max(1, F // 50))
+    return np.concatenate([g, d]), np.concatenate([h, d])
+
+
+@pytest.mark.parametrize("method,precision", [("pearson", "fp32"), ("pearson", "bf16x3"),
+                                              ("pearson", "fp64"), ("spearman", "fp32")])
+def test_headline_full_size(gpu_device, headline, method, precision):
+    X = headline
+    S, F = X.shape
+    r, p, n = _run(method, X, gpu_device, precision)
+    # counts: whole matrix against an exact integer product of the masks
+    M = (~np.isnan(X)).astype(np.int32)
+    assert_counts_equal(n, M.T @ M, f"{method}-full-n")
+    assert np.array_equal(r, r.T, equal_nan=True)
+    assert np.nanmax(np.abs(r)) <= 1.0
+    gi, hi = _sample_pairs(F, 1500, 17)
+    if method == "pearson":
+        ro, po, no = orc.pearson_pairs(X, gi, hi)
+        tol = R_TOL[precision]
+    else:
+        ro, po, no = orc.spearman_pairs(X, gi, hi)
+        tol = 1e-12
+    where = f"headline-{method}-{precision}"
+    assert_counts_equal(n[gi, hi], no, where)
+    worst = assert_r_close(r[gi, hi], ro, tol, where)
+    assert_p_close(p[gi, hi], po, ro, no, max(worst, 1e-15), where)
