@@ -112,6 +112,26 @@ int napy_spearman(const float* X, int64_t S, int64_t F, int64_t ldx,
                   void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Stage timing: napy_pearson / napy_spearman with `stage_events`, a host
+ * array of 4 caller-created hipEvent_t handles (passed as void*; a NULL
+ * entry is skipped).  Event 0 is recorded on `stream` before the first
+ * kernel, events 1..3 after each stage:
+ *   Pearson:  1 column statistics, 2 masked contractions, 3 combine + p;
+ *   Spearman: 1 sort of every column, 2 per-pair re-ranking scan,
+ *             3 combine + p.
+ * Results are those of the plain calls.
+ * ------------------------------------------------------------------------ */
+int napy_pearson_profiled(const float* X, int64_t S, int64_t F, int64_t ldx,
+                          double* r, double* p, int32_t* n, int64_t ldo,
+                          void* ws, size_t ws_bytes, const napy_opts* opts, void* stream,
+                          void* const* stage_events);
+
+int napy_spearman_profiled(const float* X, int64_t S, int64_t F, int64_t ldx,
+                           double* r, double* p, int32_t* n, int64_t ldo,
+                           void* ws, size_t ws_bytes, const napy_opts* opts, void* stream,
+                           void* const* stage_events);
+
+/* ------------------------------------------------------------------------
  * Differentiation of the Pearson matrix (no counterpart in the paper; the
  * derivative of the Section 3.5.2 definition).
  *

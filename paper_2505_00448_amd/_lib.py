@@ -26,6 +26,7 @@ EXPORTS = [
     "napy_strerror", "napy_last_error", "napy_version",
     "napy_pearson_workspace", "napy_pearson",
     "napy_spearman_workspace", "napy_spearman",
+    "napy_pearson_profiled", "napy_spearman_profiled",
     "napy_pearson_fwd", "napy_pearson_backward_workspace", "napy_pearson_backward",
     "napy_pearson_subset_workspace", "napy_pearson_subset",
     "napy_spearman_base_bytes", "napy_spearman_base_prepare",
@@ -69,6 +70,8 @@ def load() -> ctypes.CDLL:
         "napy_pearson": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P]),
         "napy_spearman_workspace": (sz, [i64, i64, O]),
         "napy_spearman": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P]),
+        "napy_pearson_profiled": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P, P]),
+        "napy_spearman_profiled": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P, P]),
         "napy_pearson_fwd": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, P, sz, O, P]),
         "napy_pearson_backward_workspace": (sz, [i64, i64, O]),
         "napy_pearson_backward": (ctypes.c_int, [P, i64, i64, i64, P, P, i64, P, i64, P, sz, O, P]),

@@ -39,6 +39,8 @@ def _prep_input(X: torch.Tensor, samples_axis: int, check_finite: bool) -> torch
         X = X.to(torch.float32)
     if X.stride(1) != 1 or X.stride(0) < X.shape[1]:
         X = X.contiguous()
+    if X.shape[0] == 0 and X.stride(0) < X.shape[1]:
+        X = torch.empty((0, X.shape[1]), dtype=torch.float32, device=X.device)
     if check_finite and bool(torch.isinf(X).any()):
         raise ValueError("X contains +-Inf; only NaN (or the chosen sentinel) may mark missing values")
     return X

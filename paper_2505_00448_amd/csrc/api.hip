@@ -31,7 +31,7 @@ int check_launch(const char* what) { return hip_status(hipGetLastError(), what);
 // Spearman drivers (spearman.hip)
 size_t spearman_ws_bytes(int64_t S, int64_t F);
 int spearman_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
-                 int64_t ldo, void* ws, const napy_opts* opts, hipStream_t st);
+                 int64_t ldo, void* ws, const napy_opts* opts, hipStream_t st, void* const* ev);
 int spearman_pair_ranks_run(const float* X, int64_t S, int64_t F, int64_t ldx, int g, int h, int32_t* rg,
                             int32_t* rh, void* ws, const napy_opts* opts, hipStream_t st);
 size_t spearman_base_bytes(int64_t S, int64_t F);
@@ -139,7 +139,29 @@ int napy_spearman(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, 
         return NAPY_E_UNSUPPORTED;
     }
     NAPY_TRY(check_common(X, S, F, ldx, ldo, ws, ws_bytes, spearman_ws_bytes(S, F), opts));
-    return spearman_run(X, S, F, ldx, r, p, n, ldo, ws, opts, (hipStream_t)stream);
+    return spearman_run(X, S, F, ldx, r, p, n, ldo, ws, opts, (hipStream_t)stream, nullptr);
+}
+
+int napy_pearson_profiled(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                          int64_t ldo, void* ws, size_t ws_bytes, const napy_opts* opts, void* stream,
+                          void* const* stage_events)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    NAPY_TRY(check_common(X, S, F, ldx, ldo, ws, ws_bytes, pearson_ws_bytes(S, F, opt_prec(opts)), opts));
+    return pearson_run(X, S, F, ldx, r, p, n, ldo, nullptr, ws, ws_bytes, opts, (hipStream_t)stream,
+                       stage_events);
+}
+
+int napy_spearman_profiled(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                           int64_t ldo, void* ws, size_t ws_bytes, const napy_opts* opts, void* stream,
+                           void* const* stage_events)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    if (S > MAX_S_SPEARMAN) return NAPY_E_UNSUPPORTED;
+    NAPY_TRY(check_common(X, S, F, ldx, ldo, ws, ws_bytes, spearman_ws_bytes(S, F), opts));
+    return spearman_run(X, S, F, ldx, r, p, n, ldo, ws, opts, (hipStream_t)stream, stage_events);
 }
 
 size_t napy_pearson_backward_workspace(int64_t S, int64_t F, const napy_opts* opts)

@@ -114,9 +114,17 @@ int gather_launch(const float* X, int64_t ldx, const int32_t* rows, int64_t Sq,
                   const int32_t* cols, int64_t Fq, float* Xq, hipStream_t st);
 
 // Internal Pearson driver; `saved` may be NULL.
+// `ev` (may be NULL): up to 4 caller-created events recorded on `st` before
+// the first kernel and after each of the three stages.
 int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
                 int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
-                const napy_opts* opts, hipStream_t st);
+                const napy_opts* opts, hipStream_t st, void* const* ev = nullptr);
+
+inline int record_stage(void* const* ev, int i, hipStream_t st)
+{
+    if (!ev || !ev[i]) return NAPY_OK;
+    return hip_status(hipEventRecord((hipEvent_t)ev[i], st), "hipEventRecord");
+}
 size_t pearson_ws_bytes(int64_t S, int64_t F, int prec);
 
 }  // namespace napy

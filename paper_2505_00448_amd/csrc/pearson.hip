@@ -26,9 +26,13 @@
 //
 // Precisions (napy_opts.precision):
 //   FP32    v_mfma_f32_16x16x4_f32, 6 products per pair-sample.
-//   BF16X3  v_mfma_f32_32x32x16_bf16 on split operands: x0 = hi + lo,
-//           q = qh + qm + ql (bf16 each); 15 products per pair-sample:
-//           n 1, Sx 2, Sy 2, Sxx 3, Syy 3, Sxy 4 (hi.hi, hi.lo, lo.hi, lo.lo).
+//   BF16X3  v_mfma_f32_32x32x16_bf16 on operands split into three bf16
+//           pieces each, x0 = xh + xm + xl and q = qh + qm + ql (exact for
+//           float32 inputs); 19 products per pair-sample: n 1, Sx 3, Sy 3,
+//           Sxx 3, Syy 3, Sxy 6 (every piece product down to 2^-18 relative:
+//           hh, hm, mh, hl, mm, lh).  A two-piece split of x (16 significant
+//           bits) perturbs r by more than 1e-6 on short or adversarial
+//           columns, so the third piece is kept.
 //   FP64    v_mfma_f64_16x16x4_f64 (validation mode).
 #include <type_traits>
 
@@ -214,7 +218,8 @@ struct LdsPlan<NAPY_PREC_FP32> {
 };
 template <>
 struct LdsPlan<NAPY_PREC_BF16X3> {
-    static constexpr int ELEMS = 2 * 6 * TILE * TileCfg<NAPY_PREC_BF16X3>::LDK;  // bf16 per buffer
+    static constexpr int NPL = 7;  // xh, xm, xl, qh, qm, ql, m
+    static constexpr int ELEMS = 2 * NPL * TILE * TileCfg<NAPY_PREC_BF16X3>::LDK;  // bf16 per buffer
 };
 template <>
 struct LdsPlan<NAPY_PREC_FP64> {
@@ -307,57 +312,83 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
                 for (int j = 0; j < RPT; ++j) dst[j] = v[j];
             }
         } else {
-            // BF16X3: layout [side][plane][col][LDK], planes xh, xl, qh, qm, ql, m
+            // BF16X3: layout [side][plane][col][LDK], planes xh, xm, xl, qh, qm, ql, m
+            constexpr int NPL = LdsPlan<PREC>::NPL;
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                bf16x8 pl[6];
+                bf16x8 pl[NPL];
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) {
                     const float raw = side ? rawH[j] : rawG[j];
                     const float mu = side ? muH32 : muG32;
                     const bool miss = is_missing(raw, use_sent, sent);
                     const float x = miss ? 0.0f : raw - mu;
+                    // x = xh + xm + xl exactly: each residual is exact in float32
                     const __bf16 xh = to_bf16(x);
-                    const __bf16 xl = to_bf16(x - from_bf16(xh));
+                    const float x1 = x - from_bf16(xh);
+                    const __bf16 xm = to_bf16(x1);
+                    const __bf16 xl = to_bf16(x1 - from_bf16(xm));
                     const float q = x * x;
                     const __bf16 qh = to_bf16(q);
                     const float q1 = q - from_bf16(qh);
                     const __bf16 qm = to_bf16(q1);
                     const __bf16 ql = to_bf16(q1 - from_bf16(qm));
                     pl[0][j] = xh;
-                    pl[1][j] = xl;
-                    pl[2][j] = qh;
-                    pl[3][j] = qm;
-                    pl[4][j] = ql;
-                    pl[5][j] = miss ? to_bf16(0.0f) : to_bf16(1.0f);
+                    pl[1][j] = xm;
+                    pl[2][j] = xl;
+                    pl[3][j] = qh;
+                    pl[4][j] = qm;
+                    pl[5][j] = ql;
+                    pl[6][j] = miss ? to_bf16(0.0f) : to_bf16(1.0f);
                 }
 #pragma unroll
-                for (int pp = 0; pp < 6; ++pp)
-                    *(bf16x8*)(base + ((side * 6 + pp) * TILE + sc) * LDK + kg * RPT) = pl[pp];
+                for (int pp = 0; pp < NPL; ++pp)
+                    *(bf16x8*)(base + ((side * NPL + pp) * TILE + sc) * LDK + kg * RPT) = pl[pp];
             }
         }
     };
 
     // ---- accumulators ---------------------------------------------------------
-    // BF16X3: one 32x32 block per wave, acc32[stat] f32x16.
     // FP32/FP64: four 16x16 sub-blocks per wave, acc[sub][stat] x4.
+    // BF16X3: one 32x32 block per wave.  The matrix cores add each product
+    // block into the accumulator with one float32 rounding (toward zero), so
+    // the products of the leading pieces and the much smaller products of
+    // the trailing pieces go to separate accumulators: the leading ones then
+    // see one rounding per 16 samples, and the trailing ones' roundings are
+    // 2^-9 smaller.  Counts are exact in float32 and never flushed; the sums
+    // of centred values Sx, Sy stay small (their partial sums wander around
+    // zero), so only Sxx, Syy and Sxy, whose partial sums grow with the
+    // sample count, are flushed into FP64.
     constexpr int NSUB = (PREC == NAPY_PREC_BF16X3) ? 1 : 4;
     constexpr int NREG = (PREC == NAPY_PREC_BF16X3) ? 16 : 4;
+    constexpr int NACC = (PREC == NAPY_PREC_BF16X3) ? 11 : NSTAT;  // BF16X3: n, then (main, low) x 5
     using AccT = typename std::conditional<PREC == NAPY_PREC_FP64, double, float>::type;
-    AccT acc[NSUB][NSTAT][NREG];
-    double acc64[NSUB][NSTAT][NREG];
+    AccT acc[NSUB][NACC][NREG];
+    constexpr int N64 = (PREC == NAPY_PREC_BF16X3) ? 3 : NSTAT;  // FP64 sums (BF16X3: Sxx, Syy, Sxy)
+    double acc64[NSUB][N64][NREG];
 #pragma unroll
-    for (int a = 0; a < NSUB; ++a)
+    for (int a = 0; a < NSUB; ++a) {
 #pragma unroll
-        for (int s = 0; s < NSTAT; ++s)
+        for (int s = 0; s < NACC; ++s)
 #pragma unroll
-            for (int r = 0; r < NREG; ++r) {
-                acc[a][s][r] = 0;
-                acc64[a][s][r] = 0.0;
-            }
+            for (int r = 0; r < NREG; ++r) acc[a][s][r] = 0;
+#pragma unroll
+        for (int s = 0; s < N64; ++s)
+#pragma unroll
+            for (int r = 0; r < NREG; ++r) acc64[a][s][r] = 0.0;
+    }
 
     auto flush = [&]() {
-        if constexpr (PREC != NAPY_PREC_FP64) {
+        if constexpr (PREC == NAPY_PREC_BF16X3) {
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+#pragma unroll
+                for (int r = 0; r < NREG; ++r) {
+                    acc64[0][s][r] += (double)acc[0][5 + 2 * s][r] + (double)acc[0][6 + 2 * s][r];
+                    acc[0][5 + 2 * s][r] = 0.0f;
+                    acc[0][6 + 2 * s][r] = 0.0f;
+                }
+        } else if constexpr (PREC == NAPY_PREC_FP32) {
 #pragma unroll
             for (int a = 0; a < NSUB; ++a)
 #pragma unroll
@@ -373,50 +404,49 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
     auto compute = [&](int buf) {
         const LT* base = lds + buf * BUF;
         if constexpr (PREC == NAPY_PREC_BF16X3) {
+            constexpr int NPL = LdsPlan<PREC>::NPL;
             const int rr = lane & 31, kq = (lane >> 5) * 8;
 #pragma unroll
             for (int kk = 0; kk < BK / 16; ++kk) {
                 const int k = kk * 16 + kq;
-                bf16x8 a[6], b[6];
+                bf16x8 a[NPL], b[NPL];
 #pragma unroll
-                for (int pp = 0; pp < 6; ++pp) {
-                    a[pp] = *(const bf16x8*)(base + ((0 * 6 + pp) * TILE + wm * 32 + rr) * LDK + k);
-                    b[pp] = *(const bf16x8*)(base + ((1 * 6 + pp) * TILE + wn * 32 + rr) * LDK + k);
+                for (int pp = 0; pp < NPL; ++pp) {
+                    a[pp] = *(const bf16x8*)(base + ((0 * NPL + pp) * TILE + wm * 32 + rr) * LDK + k);
+                    b[pp] = *(const bf16x8*)(base + ((1 * NPL + pp) * TILE + wn * 32 + rr) * LDK + k);
                 }
-                f32x16 cn, cx, cy, cxx, cyy, cxy;
+                f32x16 c[11];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    cn[r] = acc[0][0][r];
-                    cx[r] = acc[0][1][r];
-                    cy[r] = acc[0][2][r];
-                    cxx[r] = acc[0][3][r];
-                    cyy[r] = acc[0][4][r];
-                    cxy[r] = acc[0][5][r];
-                }
-                cn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[5], cn, 0, 0, 0);
-                cx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[5], cx, 0, 0, 0);
-                cy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[0], cy, 0, 0, 0);
-                cxx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[5], cxx, 0, 0, 0);
-                cyy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[2], cyy, 0, 0, 0);
-                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], cxy, 0, 0, 0);
-                cx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[5], cx, 0, 0, 0);
-                cy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[1], cy, 0, 0, 0);
-                cxx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[5], cxx, 0, 0, 0);
-                cyy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[3], cyy, 0, 0, 0);
-                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], cxy, 0, 0, 0);
-                cxx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[4], b[5], cxx, 0, 0, 0);
-                cyy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[5], b[4], cyy, 0, 0, 0);
-                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], cxy, 0, 0, 0);
-                cxy = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], cxy, 0, 0, 0);
+                for (int q = 0; q < 11; ++q)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    acc[0][0][r] = cn[r];
-                    acc[0][1][r] = cx[r];
-                    acc[0][2][r] = cy[r];
-                    acc[0][3][r] = cxx[r];
-                    acc[0][4][r] = cyy[r];
-                    acc[0][5][r] = cxy[r];
-                }
+                    for (int r = 0; r < 16; ++r) c[q][r] = acc[0][q][r];
+                // planes: 0 xh, 1 xm, 2 xl, 3 qh, 4 qm, 5 ql, 6 m
+                // accumulators: 0 n, 1/2 Sx, 3/4 Sy, 5/6 Sxx, 7/8 Syy, 9/10 Sxy (main/low)
+#define NAPY_MF(q, x, y) c[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c[q], 0, 0, 0)
+                NAPY_MF(0, a[6], b[6]);
+                NAPY_MF(1, a[0], b[6]);
+                NAPY_MF(3, a[6], b[0]);
+                NAPY_MF(5, a[3], b[6]);
+                NAPY_MF(7, a[6], b[3]);
+                NAPY_MF(9, a[0], b[0]);
+                NAPY_MF(2, a[1], b[6]);
+                NAPY_MF(4, a[6], b[1]);
+                NAPY_MF(6, a[4], b[6]);
+                NAPY_MF(8, a[6], b[4]);
+                NAPY_MF(10, a[0], b[1]);
+                NAPY_MF(2, a[2], b[6]);
+                NAPY_MF(4, a[6], b[2]);
+                NAPY_MF(6, a[5], b[6]);
+                NAPY_MF(8, a[6], b[5]);
+                NAPY_MF(10, a[1], b[0]);
+                NAPY_MF(10, a[0], b[2]);
+                NAPY_MF(10, a[1], b[1]);
+                NAPY_MF(10, a[2], b[0]);
+#undef NAPY_MF
+#pragma unroll
+                for (int q = 0; q < 11; ++q)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[0][q][r] = c[q][r];
             }
         } else {
             const int rr = lane & 15, kq = lane >> 4;
@@ -506,7 +536,14 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
             for (int r = 0; r < 16; ++r) {
                 const int i = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int j = wn * 32 + (lane & 31);
-                dst[i * TILE + j] = acc64[0][s][r];
+                double v;
+                if (s == 0)
+                    v = (double)acc[0][0][r];
+                else if (s <= 2)
+                    v = (double)acc[0][2 * s - 1][r] + (double)acc[0][2 * s][r];
+                else
+                    v = acc64[0][s - 3][r];
+                dst[i * TILE + j] = v;
             }
         } else {
 #pragma unroll
@@ -515,7 +552,10 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
                 for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int i = wm * 32 + ia * 16 + 4 * (lane >> 4) + r;
+                        // 16x16 blocks: f32 rows are 4*(lane/16) + r, f64 rows are
+                        // lane/16 + 4*r; columns are lane%16 in both
+                        const int ri = (PREC == NAPY_PREC_FP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
+                        const int i = wm * 32 + ia * 16 + ri;
                         const int j = wn * 32 + ib * 16 + (lane & 15);
                         const double v = (PREC == NAPY_PREC_FP64) ? (double)acc[ia * 2 + ib][s][r]
                                                                    : acc64[ia * 2 + ib][s][r];
@@ -629,7 +669,7 @@ size_t pearson_ws_bytes(int64_t S, int64_t F, int prec)
 
 int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
                 int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
-                const napy_opts* opts, hipStream_t st)
+                const napy_opts* opts, hipStream_t st, void* const* ev)
 {
     const int prec = opt_prec(opts);
     const int us = opt_use_sent(opts);
@@ -641,7 +681,9 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
     pearson_carve(c, S, F, prec, cs, &part);
     PearsonPlan pl = pearson_plan(S, F, prec);
 
+    NAPY_TRY(record_stage(ev, 0, st));
     NAPY_TRY(colstats_launch(X, S, F, ldx, us, sv, cs, st));
+    NAPY_TRY(record_stage(ev, 1, st));
     const unsigned nb = (unsigned)(pl.ntiles * pl.nsplit);
     switch (prec) {
     case NAPY_PREC_FP32:
@@ -658,10 +700,12 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
         break;
     }
     NAPY_TRY(check_launch("pearson_tiles"));
+    NAPY_TRY(record_stage(ev, 2, st));
     const double tol = (prec == NAPY_PREC_FP64) ? 1e-12 : 1e-5;
     hipLaunchKernelGGL(k_pearson_combine, dim3((unsigned)(pl.ntiles * (TILE_ELEMS / 256))), dim3(256), 0, st,
                        part, pl.T, pl.ntiles, pl.nsplit, F, tol, r, p, n, ldo, saved);
-    return check_launch("pearson_combine");
+    NAPY_TRY(check_launch("pearson_combine"));
+    return record_stage(ev, 3, st);
 }
 
 }  // namespace napy

@@ -495,7 +495,9 @@ __global__ __launch_bounds__(256) void k_spearman_final(const double4* __restric
     const int64_t num = A - K, Da = Ba - K, Db = Bb - K;
     double rho = __builtin_nan(""), pv = __builtin_nan("");
     if (nn >= 2 && Da > 0 && Db > 0) {
-        rho = (double)num / (sqrt((double)Da) * sqrt((double)Db));
+        // sqrt of the product (not the product of roots) so that identical
+        // rank vectors give exactly 1
+        rho = (double)num / sqrt((double)Da * (double)Db);
         rho = rho > 1.0 ? 1.0 : (rho < -1.0 ? -1.0 : rho);
         if (nn >= 3) pv = corr_pvalue(rho, nn);
     }
@@ -673,15 +675,19 @@ size_t spearman_ws_bytes(int64_t S, int64_t F)
 }
 
 int spearman_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
-                 int64_t ldo, void* ws, const napy_opts* opts, hipStream_t st)
+                 int64_t ldo, void* ws, const napy_opts* opts, hipStream_t st, void* const* ev)
 {
     Carver c(ws);
     SpearWs w;
     spear_carve(c, S, F, w);
+    NAPY_TRY(record_stage(ev, 0, st));
     NAPY_TRY(sort_launch(X, S, F, ldx, opt_use_sent(opts), opt_sent(opts), w.keys, w.base, st));
+    NAPY_TRY(record_stage(ev, 1, st));
     PairOut po{w.sums, w.ab, nullptr, nullptr, 0, 0};
     NAPY_TRY(pairs_launch(w.base, S, F, po, st));
-    return final_launch(w, F, r, p, n, ldo, st);
+    NAPY_TRY(record_stage(ev, 2, st));
+    NAPY_TRY(final_launch(w, F, r, p, n, ldo, st));
+    return record_stage(ev, 3, st);
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t count, int32_t v)

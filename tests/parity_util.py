@@ -3,11 +3,10 @@
 Counts are compared bit-exactly.  r within an absolute bound (1e-6 for the
 FP32 / BF16x3 contractions, 1e-12 for the FP64 validation mode and for
 Spearman, whose sums are exact integers).  NaN placement must match exactly.
-P-values are compared through their conditioning: a p computed from an r that
-is off by dr moves by |d ln p / dr| * dr in log space, with
-    d ln p / dr = -2 sign(r) (1 - r^2)^(a-1) / (B(a, 1/2) p),  a = (n-2)/2,
-so |ln p_gpu - ln p_oracle| <= 2 |d ln p/dr| dr_max + 1e-9 is required; where
-the oracle's p underflows below 1e-300 the GPU's must be below 1e-290.
+P-values are compared through their conditioning: the GPU's p must lie
+between the p-values of the oracle's |r| moved by twice the observed r error
+either way (p is monotone in |r|), up to 1e-9 relative for the p routine
+itself; this is the exact form of |d ln p| <= |d ln p / dr| |dr|.
 """
 
 import numpy as np
@@ -38,6 +37,10 @@ def assert_r_close(r_gpu, r_orc, tol, where=""):
 
 
 def assert_p_close(p_gpu, p_orc, r_orc, n, dr_max, where=""):
+    """p = I_{1-r^2}((n-2)/2, 1/2) falls monotonically in |r|, so an r that
+    is within d of the oracle's gives a p between the values at |r| + d and
+    |r| - d (d = 2 dr_max plus rounding); 1e-9 relative slack covers the
+    p routine's own error.  n = 2 (Pearson p = 1) must match exactly."""
     from scipy import special
     p_gpu = np.asarray(p_gpu, dtype=np.float64).ravel()
     p_orc = np.asarray(p_orc, dtype=np.float64).ravel()
@@ -47,18 +50,23 @@ def assert_p_close(p_gpu, p_orc, r_orc, n, dr_max, where=""):
     bad = np.flatnonzero(ng != no)
     assert bad.size == 0, f"{where}: p NaN placement differs at {bad.size} entries (first {bad[:5]})"
     ok = ~no
-    tiny = ok & (p_orc < 1e-300)
-    assert np.all(p_gpu[tiny] < 1e-290), f"{where}: underflowed p not reproduced"
-    m = ok & ~tiny & (n >= 3)
+    two = ok & (n == 2)
+    assert np.array_equal(p_gpu[two], p_orc[two]), f"{where}: p at n=2 differs"
+    m = ok & (n >= 3)
     if not m.any():
         return
+    d = 2.0 * dr_max + 4e-16
     a = (n[m] - 2) / 2.0
-    rr = np.clip(np.abs(r[m]), 0, 1 - 1e-16)
-    log_dp = np.log(2.0) + (a - 1) * np.log1p(-rr * rr) - special.betaln(a, 0.5) - np.log(p_orc[m])
-    bound = 2.0 * np.exp(log_dp) * dr_max + 1e-9
-    err = np.abs(np.log(np.maximum(p_gpu[m], 1e-320)) - np.log(p_orc[m]))
-    worst = np.argmax(err - bound)
-    assert np.all(err <= bound), (f"{where}: p off: |dlnp|={err[worst]:.3e} bound={bound[worst]:.3e} "
-                                  f"p_gpu={p_gpu[m][worst]:.6e} p_orc={p_orc[m][worst]:.6e} n={n[m][worst]}")
-    exact_one = ok & (n == 2)
-    assert np.array_equal(p_gpu[exact_one], p_orc[exact_one]), f"{where}: p at n=2 differs"
+    ar = np.abs(r[m])
+    r_hi = np.clip(ar + d, 0.0, 1.0)
+    r_lo = np.clip(ar - d, 0.0, 1.0)
+    p_min = special.betainc(a, 0.5, np.clip(1.0 - r_hi * r_hi, 0.0, 1.0))
+    p_max = special.betainc(a, 0.5, np.clip(1.0 - r_lo * r_lo, 0.0, 1.0))
+    pg = p_gpu[m]
+    ok_lo = pg >= p_min * (1 - 1e-9) - 1e-300
+    ok_hi = pg <= p_max * (1 + 1e-9) + 1e-300
+    good = ok_lo & ok_hi
+    if not good.all():
+        w = int(np.flatnonzero(~good)[0])
+        raise AssertionError(f"{where}: p_gpu={pg[w]:.6e} outside [{p_min[w]:.6e}, {p_max[w]:.6e}] "
+                             f"(p_orc={p_orc[m][w]:.6e}, r={r[m][w]!r}, n={n[m][w]})")
