@@ -98,7 +98,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
-    ap.add_argument("--cpu-pairs", type=int, default=40000,
+    ap.add_argument("--cpu-pairs", type=int, default=250000,
                     help="pairs in the oracle's timed sample (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
