@@ -23,14 +23,16 @@
 //                    (sorted position of sample i, 0xFFFF if missing),
 //                    runs[c][k] = s | e << 16 (tie run of position k), n_c and
 //                    a has-ties flag.
-//   k_spearman_pairs one workgroup per (column a, block of 16 partners b);
-//                    pos_a lives in LDS, each wave takes one partner at a
-//                    time.  Walk 1 streams b's sorted order, looks up a's
-//                    position of every sample, ballots the complete ones
-//                    (b-side presence mask per 64 positions plus prefix) and
-//                    sets their bits in an a-side bitmap; a prefix over the
-//                    bitmap words follows; walk 2 streams b's order again and
-//                    forms both doubled ranks from popcounts and the sums.
+//   k_presence       presence words: bit j of pres[w][i] = sample i present
+//                    in column 32 w + j.
+//   k_spearman_pairs one workgroup per (column a, block of 16 partners b).  pos_a lives in LDS.  Step 1 builds
+//                    the "partner present" bitmaps along a's sorted order for
+//                    all partners at once (one presence-word gather per
+//                    position, one ballot per partner) plus per-64 prefix
+//                    counts.  Step 2: each wave walks one partner's sorted
+//                    order once; b's count of complete samples below each
+//                    position comes from ballot + mbcnt, a's from the bitmap
+//                    by popcount; both doubled ranks and the sums follow.
 //   k_spearman_final one thread per pair: rho, p, n into both triangles.
 #include "napy_internal.hpp"
 #include "pvalue.hpp"
@@ -40,26 +42,31 @@ namespace napy {
 constexpr int SORT_THREADS = 1024;
 constexpr int SORT_EPT = 24;  // elements per thread
 constexpr int SPEARMAN_MAX_S = SORT_THREADS * SORT_EPT;  // 24576
-constexpr int PAIR_BLOCK = 16;  // partners per workgroup
-constexpr int PAIR_WAVES = 4;
 
 struct SpearBase {
     uint16_t* ord;     // [F][ld]
     uint16_t* pos;     // [F][ld]
     uint32_t* runs;    // [F][ld]
+    uint64_t* tbits;   // [F][ld/64]: bit k set if sorted position k lies in a tie run
     int32_t* ncol;     // [F]
     int32_t* hasties;  // [F]
     int64_t ld;
 };
 
-static inline int64_t spear_ld(int64_t S) { return round_up(S > 0 ? S : 1, 64); }
+// Row stride of the per-column arrays: room for every sample plus one dummy
+// sample index S whose position is always "missing", so sorted-order reads
+// past a column's observed count need no bounds test.
+static inline int64_t spear_ld(int64_t S) { return round_up(S + 1, 64); }
+// sorted orders may be read up to this many entries past the last row
+constexpr int64_t ORD_TAIL = 512;
 
 static void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
 {
     b.ld = spear_ld(S);
-    b.ord = c.take<uint16_t>((size_t)F * b.ld);
+    b.ord = c.take<uint16_t>((size_t)F * b.ld + ORD_TAIL);
     b.pos = c.take<uint16_t>((size_t)F * b.ld);
     b.runs = c.take<uint32_t>((size_t)F * b.ld);
+    b.tbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
     b.ncol = c.take<int32_t>(F);
     b.hasties = c.take<int32_t>(F);
 }
@@ -312,6 +319,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
             }
         }
     }
+    // padding: sorted positions past the observed count hold the dummy
+    // sample S, whose position is "missing"
+    for (int64_t k = ncount + t; k < ld; k += SORT_THREADS) ordc[k] = (uint16_t)S;
+    for (int64_t i = S + t; i < ld; i += SORT_THREADS) posc[i] = 0xFFFF;
+    if (col == (int)gridDim.x - 1)
+        for (int64_t k = t; k < ORD_TAIL; k += SORT_THREADS) ordc[ld + k] = (uint16_t)S;
     const int anytie = __syncthreads_or(tie_here ? 1 : 0);
     if (t == 0) {
         out.ncol[col] = ncount;
@@ -341,142 +354,328 @@ __device__ __forceinline__ int64_t sum_sq_doubled_untied(int64_t n)
     return (n * (n + 1) * (2 * n + 1) / 6) * 4;
 }
 
-__global__ __launch_bounds__(256) void k_spearman_pairs(SpearBase bs, int64_t S, int64_t F, PairOut po)
+// Tie bits: bit k of tbits[c][k / 64] is set when sorted position k of column
+// c belongs to a run of two or more equal values.
+__global__ __launch_bounds__(256) void k_tiebits(SpearBase bs)
+{
+    const int64_t c = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int nc = bs.ncol[c];
+    bool tie = false;
+    if (k < nc) {
+        const uint32_t rr = bs.runs[c * bs.ld + k];
+        tie = (rr >> 16) - (rr & 0xFFFFu) > 1u;
+    }
+    const uint64_t m = __ballot(tie);
+    if ((threadIdx.x & 63) == 0 && k < bs.ld) bs.tbits[c * (bs.ld / 64) + (k >> 6)] = m;
+}
+
+static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tiebits, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)F), dim3(256), 0, st, bs);
+    return check_launch("tiebits");
+}
+
+// Presence words: pres[w][i] bit j = sample i present in column 32 w + j.
+__global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64_t F, uint32_t* __restrict__ pres)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t w = blockIdx.y;
+    if (i >= bs.ld) return;
+    uint32_t word = 0u;
+    if (i < S) {
+        const int64_t c0 = w * 32;
+        const int nj = (int)min((int64_t)32, F - c0);
+        for (int j = 0; j < nj; ++j) word |= (uint32_t)(bs.pos[(c0 + j) * bs.ld + i] != 0xFFFF) << j;
+    }
+    pres[w * bs.ld + i] = word;
+}
+
+constexpr int PAIR_THREADS = 512;
+constexpr int PAIR_WAVES = PAIR_THREADS / 64;
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// bits of `mask` at lanes below x (x in 0..64)
+__device__ __forceinline__ uint64_t bits_below(uint64_t mask, uint32_t x)
+{
+    return x >= 64u ? mask : (mask & ((1ull << x) - 1ull));
+}
+
+struct WalkSums {
+    uint32_t n;
+    uint64_t A, Ba, Bb;  // per-lane partial sums (A, Ba, Bb) plus uniform extras
+    uint64_t A_u, Bb_u;  // wave-uniform contributions (deferred tie runs of b)
+};
+
+// Walk of partner b's sorted order for the pair (a, b).  The complete
+// samples are those with an a-position; b's count of complete samples below
+// each position comes from ballot + mbcnt, a's from the partner bitmap KAj /
+// prefix PAj by popcount.  Doubled rank of a tied sample: C(start) + C(end) + 1
+// over its tie run.  On the a side tied positions (bit in tA) look their run
+// up.  On the b side a chunk of 64 positions with ties (bit word tbB[c] != 0)
+// resolves the runs inside the chunk from its ballot mask; the one run that
+// may continue into the next chunk is carried as wave-uniform state (its start
+// count, and the sum of a-ranks and count of its complete samples so far) and
+// settled where it ends.
+template <bool TA, bool TB>
+__device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
+                                          const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ runsA,
+                                          int nbv, int na, const uint16_t* posA, const uint64_t* tA,
+                                          const uint64_t* KAj, const uint16_t* PAj, int lane, bool dbg,
+                                          int32_t* dbg_ra, int32_t* dbg_rb, WalkSums& ws)
+{
+    auto cnt_a = [&](uint32_t x) -> uint32_t {
+        const uint64_t m = KAj[x >> 6];
+        return (uint32_t)PAj[x >> 6] + (uint32_t)__popcll(m & ((1ull << (x & 63)) - 1ull));
+    };
+    const int ncb = (nbv + 63) >> 6;
+    uint32_t carry = 0;
+    uint64_t sA = 0, sBa = 0, sBb = 0;
+    uint64_t uA = 0, uBb = 0;            // wave-uniform
+    uint32_t open_cs = 0, pend_sum = 0, pend_t = 0;
+    bool open = false;
+    constexpr int U = 4;
+    for (int c0 = 0; c0 < ncb; c0 += U) {
+        // all loads of the group are issued before any use: b's sorted order
+        // (global, coalesced), a-positions (LDS gather), a-side counts (LDS)
+        uint32_t iv[U], pv[U], ca[U];
+        uint64_t tbw[U];
+        // sorted positions past b's observed count hold a dummy sample whose
+        // a-position is "missing", and the rows are padded, so no bounds tests
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            iv[u] = ordB[(c0 + u) * 64 + lane];
+            if constexpr (TB) tbw[u] = (c0 + u < ncb) ? tbB[c0 + u] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) pv[u] = posA[iv[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ca[u] = cnt_a(min(pv[u], (uint32_t)na));
+        if constexpr (TA) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t p = pv[u];
+                const bool kept = p != 0xFFFFu;
+                const uint32_t pp = kept ? p : 0u;
+                const bool tied = kept && ((tA[pp >> 6] >> (pp & 63)) & 1ull);
+                if (tied) {
+                    const uint32_t rr = runsA[pp];
+                    ca[u] = cnt_a(rr & 0xFFFFu) + cnt_a(rr >> 16) + 1u;  // doubled rank already
+                } else {
+                    ca[u] = 2u * ca[u] + 2u;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u;
+            if (c >= ncb) break;
+            const uint32_t p = pv[u];
+            const bool kept = p != 0xFFFFu;
+            const uint64_t mask = __ballot(kept);
+            const uint32_t cb = carry + mbcnt64(mask);
+            const uint32_t Ra = TA ? ca[u] : 2u * ca[u] + 2u;
+            uint32_t Rb = 2u * cb + 2u;
+            bool direct = kept;
+            if constexpr (TB) {
+                if (tbw[u] != 0ull || open) {
+                    const uint32_t lo = (uint32_t)c * 64u;
+                    const int k = c * 64 + lane;
+                    const uint32_t rr = (k < nbv) ? runsB[k] : ((uint32_t)k | ((uint32_t)(k + 1) << 16));
+                    const uint32_t rs = rr & 0xFFFFu, re = rr >> 16;
+                    const uint32_t cs = (rs >= lo) ? carry + (uint32_t)__popcll(bits_below(mask, rs - lo)) : open_cs;
+                    const bool ends = re <= lo + 64u;
+                    const uint32_t ce = carry + (uint32_t)__popcll(bits_below(mask, ends ? re - lo : 64u));
+                    Rb = cs + ce + 1u;
+                    // settle the run carried in from the previous chunk (lane 0
+                    // belongs to it) if it ends here
+                    if (open) {
+                        const uint32_t e0 = __shfl(re, 0, 64);
+                        if (e0 <= lo + 64u) {
+                            const uint32_t r_open = __shfl(Rb, 0, 64);
+                            uA += (uint64_t)r_open * pend_sum;
+                            uBb += (uint64_t)pend_t * r_open * r_open;
+                            if (dbg) {
+                                // test hook only: report the settled rank of every
+                                // complete sample of the run
+                                const uint32_t s0 = __shfl(rs, 0, 64);
+                                for (uint32_t kk = s0 + (uint32_t)lane; kk < e0; kk += 64u) {
+                                    const uint32_t ii = ordB[kk];
+                                    if (posA[ii] != 0xFFFFu) dbg_rb[ii] = (int32_t)r_open;
+                                }
+                            }
+                            pend_sum = 0;
+                            pend_t = 0;
+                            open = false;
+                        }
+                    }
+                    const bool defer = kept && !ends;
+                    direct = kept && ends;
+                    const uint64_t dm = __ballot(defer);
+                    if (dm) {
+                        pend_sum += wave_sum_u32(defer ? Ra : 0u);
+                        pend_t += (uint32_t)__popcll(dm);
+                        open = true;
+                        open_cs = __shfl(cs, 63, 64);
+                    } else if (!open) {
+                        // a run can also continue with no complete sample yet
+                        const uint32_t e63 = __shfl(re, 63, 64);
+                        const bool v63 = (c * 64 + 63) < nbv;
+                        if (v63 && e63 > lo + 64u) {
+                            open = true;
+                            open_cs = __shfl(cs, 63, 64);
+                        }
+                    }
+                }
+            }
+            carry += (uint32_t)__popcll(mask);
+            if (direct) {
+                sA += __umul24(Ra, Rb);
+                if constexpr (TB) sBb += __umul24(Rb, Rb);
+            }
+            if constexpr (TA) {
+                if (kept) sBa += __umul24(Ra, Ra);
+            }
+            if (dbg && kept) {
+                dbg_ra[iv[u]] = (int32_t)Ra;
+                if (direct) dbg_rb[iv[u]] = (int32_t)Rb;
+            }
+        }
+    }
+    ws.n = carry;
+    ws.A = sA;
+    ws.Ba = sBa;
+    ws.Bb = sBb;
+    ws.A_u = uA;
+    ws.Bb_u = uBb;
+}
+
+// One workgroup per (column a, block of PB partner columns).  Step 1 builds,
+// for all PB partners at once, the bitmap "partner present" along a's sorted
+// order (one presence-word gather per position, one ballot per partner) and
+// its per-64 prefix counts.  Step 2 walks each partner's sorted order once
+// (pair_walk).
+template <int PB>
+__global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint32_t* __restrict__ pres,
+                                                                 int64_t S, int64_t F, PairOut po)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool dbg = po.dbg_ra != nullptr;
     const int64_t a = dbg ? po.dbg_a : (int64_t)blockIdx.y;
-    const int64_t b0 = dbg ? po.dbg_b : (int64_t)blockIdx.x * PAIR_BLOCK;
-    const int nb_here = dbg ? 1 : PAIR_BLOCK;
-    if (a >= F) return;
-    if (!dbg && b0 + PAIR_BLOCK - 1 < a) return;
-    if (b0 >= F) return;
+    const int64_t blk = dbg ? po.dbg_b / PB : (int64_t)blockIdx.x;
+    const int64_t b0 = blk * PB;
+    if (a >= F || b0 >= F) return;
+    if (!dbg && b0 + PB - 1 < a) return;
 
     const int64_t ld = bs.ld;
-    const int nwa_max = (int)ceil_div(S, 32) + 1;
-    const int ncb_max = (int)ceil_div(S, 64) + 1;
+    const int64_t nwd = ld / 64;  // tie-bit words per column
+    const int ncmax = (int)ceil_div(S, 64) + 1;
+    const size_t off_ka = (size_t)round_up(ld * 2, 16);
+    const size_t off_pa = off_ka + (size_t)PB * ncmax * 8;
+    const size_t off_ta = (size_t)round_up((int64_t)(off_pa + (size_t)PB * ncmax * 2), 16);
     uint16_t* posA = (uint16_t*)smem_raw;
-    unsigned char* wbase = smem_raw + round_up(ld * 2, 16);
-    const size_t per_wave = round_up((size_t)nwa_max * 8 + (size_t)ncb_max * 12, 16);
-    unsigned char* wmem = wbase + per_wave * wave;
-    uint64_t* KB = (uint64_t*)wmem;                       // [ncb_max]
-    uint32_t* KA = (uint32_t*)(wmem + (size_t)ncb_max * 8);  // [nwa_max]
-    uint32_t* PA = KA + nwa_max;                          // [nwa_max]
-    uint32_t* PB = PA + nwa_max;                          // [ncb_max]
-
-    // stage pos_a
-    {
-        const uint32_t* src = (const uint32_t*)(bs.pos + a * ld);
-        uint32_t* dst = (uint32_t*)posA;
-        for (int64_t w = threadIdx.x; w < ld / 2; w += 256) dst[w] = src[w];
-    }
-    __syncthreads();
+    uint64_t* KA = (uint64_t*)(smem_raw + off_ka);  // [PB][ncmax]
+    uint16_t* PA = (uint16_t*)(smem_raw + off_pa);  // [PB][ncmax]
+    uint64_t* TAb = (uint64_t*)(smem_raw + off_ta); // [nwd] tie bits of a
 
     const int na = bs.ncol[a];
     const int tA = bs.hasties[a];
+    const uint16_t* ordA = bs.ord + a * ld;
     const uint32_t* runsA = bs.runs + a * ld;
-    const int nwa = (na + 31) >> 5;
+    const int nca = (na + 63) >> 6;
+    {
+        const uint32_t* src = (const uint32_t*)(bs.pos + a * ld);
+        uint32_t* dst = (uint32_t*)posA;
+        for (int64_t w = threadIdx.x; w < ld / 2; w += PAIR_THREADS) dst[w] = src[w];
+        if (tA)
+            for (int64_t w = threadIdx.x; w < nwd; w += PAIR_THREADS) TAb[w] = bs.tbits[a * nwd + w];
+    }
 
-    for (int q = wave; q < nb_here; q += PAIR_WAVES) {
-        const int64_t b = b0 + q;
-        if (b >= F || (!dbg && b < a)) continue;
+    // ---- step 1: partner presence along a's order, PB partners at once -----
+    const uint32_t* presw = pres + (b0 >> 5) * ld;
+    const int shift = (int)(b0 & 31);  // 0, or 16 when PB == 16
+    constexpr int Q = 4;                // chunks per wave in flight
+    for (int cq = wave; cq <= nca; cq += PAIR_WAVES * Q) {
+        uint32_t idx[Q], word[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int p = (cq + q * PAIR_WAVES) * 64 + lane;
+            idx[q] = (p < na) ? ordA[p] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) word[q] = (idx[q] != 0xFFFFFFFFu) ? (presw[idx[q]] >> shift) : 0u;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int c = cq + q * PAIR_WAVES;
+            if (c > nca) break;
+            uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const uint64_t m = __ballot((word[q] >> j) & 1u);
+                lo = (lane == j) ? (uint32_t)m : lo;
+                hi = (lane == j) ? (uint32_t)(m >> 32) : hi;
+            }
+            if (lane < PB) KA[(size_t)lane * ncmax + c] = ((uint64_t)hi << 32) | lo;
+        }
+    }
+    __syncthreads();
+    for (int j = wave; j < PB; j += PAIR_WAVES) {
+        uint32_t run = 0;
+        for (int c0 = 0; c0 <= nca; c0 += 64) {
+            const int c = c0 + lane;
+            const uint32_t v = (c <= nca) ? (uint32_t)__popcll(KA[(size_t)j * ncmax + c]) : 0u;
+            const uint32_t incl = wave_incl_scan_u32(v);
+            if (c <= nca) PA[(size_t)j * ncmax + c] = (uint16_t)(run + incl - v);
+            run += __shfl(incl, 63, 64);
+        }
+    }
+    __syncthreads();
+
+    // ---- step 2: one walk of each partner's sorted order ---------------------
+    for (int j = wave; j < PB; j += PAIR_WAVES) {
+        const int64_t b = b0 + j;
+        if (b >= F) break;
+        if (dbg ? (b != po.dbg_b) : (b < a)) continue;
         const int nbv = bs.ncol[b];
         const int tB = bs.hasties[b];
         const uint16_t* ordB = bs.ord + b * ld;
         const uint32_t* runsB = bs.runs + b * ld;
-        const int ncb = (nbv + 63) >> 6;
-
-        for (int w = lane; w <= nwa; w += 64) KA[w] = 0u;
-        wave_sync_lds();
-
-        // walk 1: b's presence mask along b's order, a-side bitmap
-        uint32_t carry = 0;
-        for (int c = 0; c < ncb; ++c) {
-            const int k = c * 64 + lane;
-            const bool valid = k < nbv;
-            const uint32_t i = valid ? ordB[k] : 0u;
-            const uint32_t p = valid ? posA[i] : 0xFFFFu;
-            const bool kept = p != 0xFFFFu;
-            const uint64_t mask = __ballot(kept);
-            if (lane == 0) {
-                KB[c] = mask;
-                PB[c] = carry;
-            }
-            carry += (uint32_t)__popcll(mask);
-            if (kept) atomicOr(&KA[p >> 5], 1u << (p & 31));
+        const uint64_t* tbB = bs.tbits + b * nwd;
+        const uint64_t* KAj = KA + (size_t)j * ncmax;
+        const uint16_t* PAj = PA + (size_t)j * ncmax;
+        WalkSums w;
+        if (tA) {
+            if (tB) pair_walk<true, true>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            else pair_walk<true, false>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+        } else {
+            if (tB) pair_walk<false, true>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            else pair_walk<false, false>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
         }
-        if (lane == 0) {
-            KB[ncb] = 0ull;
-            PB[ncb] = carry;
-        }
-        const uint32_t n = carry;
-        wave_sync_lds();
-
-        // prefix over the a-side bitmap words (one extra word past the end)
-        uint32_t run = 0;
-        for (int w0 = 0; w0 <= nwa; w0 += 64) {
-            const int w = w0 + lane;
-            const uint32_t v = (w <= nwa) ? (uint32_t)__popc(KA[w]) : 0u;
-            const uint32_t incl = wave_incl_scan_u32(v);
-            if (w <= nwa) PA[w] = run + incl - v;
-            run += __shfl(incl, 63, 64);
-        }
-        wave_sync_lds();
-
-        // walk 2: doubled ranks and sums
-        double sA = 0.0, sBa = 0.0, sBb = 0.0;
-        for (int c = 0; c < ncb; ++c) {
-            const int k = c * 64 + lane;
-            const bool valid = k < nbv;
-            const uint32_t i = valid ? ordB[k] : 0u;
-            const uint32_t p = valid ? posA[i] : 0xFFFFu;
-            const bool kept = p != 0xFFFFu;
-            const uint64_t mask = KB[c];
-            const uint32_t cb = PB[c] + mbcnt64(mask);
-            if (kept) {
-                uint32_t Rb;
-                if (tB) {
-                    const uint32_t rr = runsB[k];
-                    const uint32_t x0 = rr & 0xFFFFu, x1 = rr >> 16;
-                    const uint32_t c0 = PB[x0 >> 6] + (uint32_t)__popcll(KB[x0 >> 6] & ((1ull << (x0 & 63)) - 1ull));
-                    const uint32_t c1 = PB[x1 >> 6] + (uint32_t)__popcll(KB[x1 >> 6] & ((1ull << (x1 & 63)) - 1ull));
-                    Rb = c0 + c1 + 1u;
-                } else {
-                    Rb = 2u * cb + 2u;
-                }
-                uint32_t Ra;
-                if (tA) {
-                    const uint32_t rr = runsA[p];
-                    const uint32_t x0 = rr & 0xFFFFu, x1 = rr >> 16;
-                    const uint32_t c0 = PA[x0 >> 5] + (uint32_t)__popc(KA[x0 >> 5] & ((1u << (x0 & 31)) - 1u));
-                    const uint32_t c1 = PA[x1 >> 5] + (uint32_t)__popc(KA[x1 >> 5] & ((1u << (x1 & 31)) - 1u));
-                    Ra = c0 + c1 + 1u;
-                } else {
-                    const uint32_t ca = PA[p >> 5] + (uint32_t)__popc(KA[p >> 5] & ((1u << (p & 31)) - 1u));
-                    Ra = 2u * ca + 2u;
-                }
-                sA += (double)(Ra * Rb);
-                if (tA) sBa += (double)(Ra * Ra);
-                if (tB) sBb += (double)(Rb * Rb);
-                if (dbg) {
-                    po.dbg_ra[i] = (int32_t)Ra;
-                    po.dbg_rb[i] = (int32_t)Rb;
-                }
-            }
-        }
-        sA = wave_sum_f64(sA);
-        sBa = wave_sum_f64(sBa);
-        sBb = wave_sum_f64(sBb);
+        const uint64_t sA = wave_sum_u64(w.A) + w.A_u;
+        const uint64_t sBa = tA ? wave_sum_u64(w.Ba) : 0ull;
+        const uint64_t sBb = tB ? wave_sum_u64(w.Bb) + w.Bb_u : 0ull;
         if (lane == 0 && !dbg) {
-            const int64_t nn = (int64_t)n;
-            const double Ba = tA ? sBa : (double)sum_sq_doubled_untied(nn);
-            const double Bb = tB ? sBb : (double)sum_sq_doubled_untied(nn);
+            const int64_t nn = (int64_t)w.n;
+            const double Ba = tA ? (double)sBa : (double)sum_sq_doubled_untied(nn);
+            const double Bb = tB ? (double)sBb : (double)sum_sq_doubled_untied(nn);
             const int64_t pid = pair_index(a, b, F);
-            po.sums[pid] = make_double4((double)nn, sA, Ba, Bb);
+            po.sums[pid] = make_double4((double)nn, (double)sA, Ba, Bb);
             po.ab[pid] = make_int2((int)a, (int)b);
         }
-        wave_sync_lds();
     }
 }
 
@@ -550,7 +749,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
     uint16_t* qord = q.ord + (int64_t)qc * q.ld;
     uint16_t* qpos = q.pos + (int64_t)qc * q.ld;
     uint32_t* qruns = q.runs + (int64_t)qc * q.ld;
-    for (int64_t j = t; j < Sq; j += SORT_THREADS) qpos[j] = 0xFFFF;
+    for (int64_t j = t; j < q.ld; j += SORT_THREADS) qpos[j] = 0xFFFF;
     __syncthreads();
     uint32_t carry = 0;
     for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
@@ -575,6 +774,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
         __syncthreads();
     }
     if (t == 0) P[nc] = (uint16_t)carry;
+    for (int64_t k = carry + t; k < q.ld; k += SORT_THREADS) qord[k] = (uint16_t)Sq;
+    if (qc == (int)gridDim.x - 1)
+        for (int64_t k = t; k < ORD_TAIL; k += SORT_THREADS) qord[q.ld + k] = (uint16_t)Sq;
     __syncthreads();
     int tie = 0;
     for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
@@ -599,21 +801,28 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static size_t pair_smem_bytes(int64_t S)
+static int pair_block(int64_t S) { (void)S; return 16; }
+
+static size_t pair_smem_bytes(int64_t S, int PB)
 {
     const int64_t ld = spear_ld(S);
-    const int nwa_max = (int)ceil_div(S, 32) + 1;
-    const int ncb_max = (int)ceil_div(S, 64) + 1;
-    const size_t per_wave = round_up((size_t)nwa_max * 8 + (size_t)ncb_max * 12, 16);
-    return (size_t)round_up(ld * 2, 16) + per_wave * PAIR_WAVES;
+    const int64_t ncmax = ceil_div(S, 64) + 1;
+    size_t off = (size_t)round_up(ld * 2, 16);
+    off += (size_t)PB * ncmax * 8;  // KA
+    off += (size_t)PB * ncmax * 2;  // PA
+    off = (size_t)round_up((int64_t)off, 16);
+    off += (size_t)(ld / 64) * 8;  // tie bits of a
+    return off;
 }
 
-static int pairs_launch(const SpearBase& bs, int64_t S, int64_t F, PairOut po, hipStream_t st)
+template <int PB>
+static int pairs_launch_t(const SpearBase& bs, const uint32_t* pres, int64_t S, int64_t F, PairOut po,
+                          hipStream_t st)
 {
-    const size_t smem = pair_smem_bytes(S);
+    const size_t smem = pair_smem_bytes(S, PB);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_spearman_pairs,
+        hipError_t e = hipFuncSetAttribute((const void*)k_spearman_pairs<PB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_spearman_pairs)");
         attr_set = true;
@@ -622,17 +831,29 @@ static int pairs_launch(const SpearBase& bs, int64_t S, int64_t F, PairOut po, h
     if (po.dbg_ra) {
         grid = dim3(1, 1);
     } else {
-        // pad the partner-block count to a multiple of 8 so that a partner
-        // block always lands on the same XCD (its sorted orders stay in L2)
-        grid = dim3((unsigned)round_up(ceil_div(F, PAIR_BLOCK), 8), (unsigned)F);
+        // the partner-block count is padded to a multiple of 8 so that a
+        // partner block always lands on the same XCD (blocks are dealt to the
+        // XCDs round-robin), keeping its sorted orders in that XCD's L2
+        grid = dim3((unsigned)round_up(ceil_div(F, PB), 8), (unsigned)F);
     }
-    hipLaunchKernelGGL(k_spearman_pairs, grid, dim3(256), smem, st, bs, S, F, po);
+    hipLaunchKernelGGL(k_spearman_pairs<PB>, grid, dim3(PAIR_THREADS), smem, st, bs, pres, S, F, po);
     return check_launch("spearman_pairs");
+}
+
+static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t F, PairOut po, hipStream_t st)
+{
+    const int64_t nw = ceil_div(F, 32);
+    hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)nw), dim3(256), 0, st, bs, S, F,
+                       pres);
+    NAPY_TRY(check_launch("presence"));
+    if (pair_block(S) == 32) return pairs_launch_t<32>(bs, pres, S, F, po, st);
+    return pairs_launch_t<16>(bs, pres, S, F, po, st);
 }
 
 struct SpearWs {
     uint32_t* keys;
     SpearBase base;
+    uint32_t* pres;  // [ceil(F/32)][ld]
     double4* sums;
     int2* ab;
 };
@@ -642,6 +863,7 @@ static void spear_carve(Carver& c, int64_t S, int64_t F, SpearWs& w)
     const int64_t ld = spear_ld(S);
     w.keys = c.take<uint32_t>((size_t)F * ld);
     base_carve(c, S, F, w.base);
+    w.pres = c.take<uint32_t>((size_t)ceil_div(F, 32) * ld);
     const int64_t npairs = F * (F + 1) / 2;
     w.sums = c.take<double4>(npairs);
     w.ab = c.take<int2>(npairs);
@@ -654,7 +876,8 @@ static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us
     hipLaunchKernelGGL(k_sort_keys, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
     NAPY_TRY(check_launch("sort_keys"));
     hipLaunchKernelGGL(k_colsort, dim3((unsigned)F), dim3(SORT_THREADS), 0, st, keys, S, base.ld, base);
-    return check_launch("colsort");
+    NAPY_TRY(check_launch("colsort"));
+    return tiebits_launch(base, F, st);
 }
 
 static int final_launch(const SpearWs& w, int64_t F, double* r, double* p, int32_t* n, int64_t ldo,
@@ -684,7 +907,7 @@ int spearman_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, d
     NAPY_TRY(sort_launch(X, S, F, ldx, opt_use_sent(opts), opt_sent(opts), w.keys, w.base, st));
     NAPY_TRY(record_stage(ev, 1, st));
     PairOut po{w.sums, w.ab, nullptr, nullptr, 0, 0};
-    NAPY_TRY(pairs_launch(w.base, S, F, po, st));
+    NAPY_TRY(pairs_launch(w.base, w.pres, S, F, po, st));
     NAPY_TRY(record_stage(ev, 2, st));
     NAPY_TRY(final_launch(w, F, r, p, n, ldo, st));
     return record_stage(ev, 3, st);
@@ -708,7 +931,7 @@ int spearman_pair_ranks_run(const float* X, int64_t S, int64_t F, int64_t ldx, i
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, st, rh, S, -1);
     NAPY_TRY(check_launch("fill"));
     PairOut po{w.sums, w.ab, rg, rh, g, h};
-    return pairs_launch(w.base, S, F, po, st);
+    return pairs_launch(w.base, w.pres, S, F, po, st);
 }
 
 size_t spearman_base_bytes(int64_t S, int64_t F)
@@ -737,6 +960,7 @@ size_t spearman_subset_ws_bytes(int64_t S, int64_t Sq, int64_t Fq)
     c.take<int32_t>(S > 0 ? S : 1);
     SpearBase q;
     base_carve(c, Sq, Fq, q);
+    c.take<uint32_t>((size_t)ceil_div(Fq, 32) * spear_ld(Sq));
     const int64_t npairs = Fq * (Fq + 1) / 2;
     c.take<double4>(npairs);
     c.take<int2>(npairs);
@@ -754,6 +978,7 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
     int32_t* rowmap = c.take<int32_t>(S > 0 ? S : 1);
     SpearWs w;
     base_carve(c, Sq, Fq, w.base);
+    w.pres = c.take<uint32_t>((size_t)ceil_div(Fq, 32) * spear_ld(Sq));
     const int64_t npairs = Fq * (Fq + 1) / 2;
     w.sums = c.take<double4>(npairs);
     w.ab = c.take<int2>(npairs);
@@ -764,8 +989,9 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
     NAPY_TRY(check_launch("rowmap_set"));
     hipLaunchKernelGGL(k_compact, dim3((unsigned)Fq), dim3(SORT_THREADS), 0, st, b, cols, rowmap, Sq, w.base);
     NAPY_TRY(check_launch("compact"));
+    NAPY_TRY(tiebits_launch(w.base, Fq, st));
     PairOut po{w.sums, w.ab, nullptr, nullptr, 0, 0};
-    NAPY_TRY(pairs_launch(w.base, Sq, Fq, po, st));
+    NAPY_TRY(pairs_launch(w.base, w.pres, Sq, Fq, po, st));
     return final_launch(w, Fq, r, p, n, ldo, st);
 }
 

@@ -259,3 +259,46 @@ def test_headline_full_size(gpu_device, headline, method, precision):
     assert_counts_equal(n[gi, hi], no, where)
     worst = assert_r_close(r[gi, hi], ro, tol, where)
     assert_p_close(p[gi, hi], po, ro, no, max(worst, 1e-15), where)
+
+
+# ---------------------------------------------------------------------------
+# tie runs of every length and position relative to the 64-position chunks
+# ---------------------------------------------------------------------------
+
+def _tie_stress_matrix(S=3000, seed=21):
+    rng = np.random.default_rng(seed)
+    cols = []
+    cols.append(rng.integers(0, 3, S).astype(np.float32))             # 3 huge runs
+    cols.append(rng.integers(0, 40, S).astype(np.float32))            # runs ~75 long
+    x = rng.standard_normal(S).astype(np.float32)
+    dup = x.copy()
+    idx = rng.choice(S, 200, replace=False)
+    dup[idx] = dup[rng.choice(S, 200, replace=False)]                  # scattered pairs/triples
+    cols.append(dup)
+    cols.append(np.round(rng.standard_normal(S) * 4).astype(np.float32))  # ~30 levels
+    cols.append(x)                                                     # no ties
+    cols.append((rng.integers(0, 2, S) * 2 - 1).astype(np.float32) * 0.0)  # all (+-)0: one run
+    X = np.stack(cols, axis=1)
+    X[rng.random(X.shape) < 0.35] = np.nan
+    X[rng.random(S) < 0.5, 1] = np.nan                                 # sparse kept in column 1
+    return X
+
+
+def test_tie_runs_across_chunks(gpu_device):
+    X = _tie_stress_matrix()
+    _check_full("spearman", X, gpu_device, where="tie-stress")
+
+
+def test_tie_runs_ranks_bit_exact(gpu_device):
+    napy = _napy()
+    X = _tie_stress_matrix(S=1500, seed=5)
+    Xd = _to_dev(X, gpu_device)
+    F = X.shape[1]
+    for g in range(F):
+        for h in range(F):
+            rg, rh = napy.spearman_pair_ranks(Xd, g, h)
+            og, oh, n = orc.pair_ranks(X, g, h)
+            exp_g = np.where(np.isnan(og), -1, np.round(2 * np.nan_to_num(og))).astype(np.int64)
+            exp_h = np.where(np.isnan(oh), -1, np.round(2 * np.nan_to_num(oh))).astype(np.int64)
+            assert np.array_equal(_np(rg).astype(np.int64), exp_g), (g, h, "a side")
+            assert np.array_equal(_np(rh).astype(np.int64), exp_h), (g, h, "b side")
