@@ -50,6 +50,8 @@ struct SpearBase {
     uint64_t* tbits;   // [F][ld/64]: bit k set if sorted position k lies in a tie run
     int32_t* ncol;     // [F]
     int32_t* hasties;  // [F]
+    int32_t* tcount;   // [F] number of positions in tie runs
+    int32_t* perm;     // [F] processing order of the columns (see k_perm)
     int64_t ld;
 };
 
@@ -69,6 +71,8 @@ static void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
     b.tbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
     b.ncol = c.take<int32_t>(F);
     b.hasties = c.take<int32_t>(F);
+    b.tcount = c.take<int32_t>(F);
+    b.perm = c.take<int32_t>(F);
 }
 
 // ---------------------------------------------------------------------------
@@ -312,8 +316,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
             const int k = t * E + e;
             if (k < ncount) {
                 ordc[k] = idx[e];
-                posc[idx[e]] = (uint16_t)k;
-                runc[k] = (uint32_t)rs[e] | (END[rs[e]] << 16);
+                // bit 15 of a position flags a sample whose value is tied
+                const uint32_t run_end = END[rs[e]];
+                posc[idx[e]] = (uint16_t)(k | ((run_end - (uint32_t)rs[e] > 1u) ? 0x8000 : 0));
+                runc[k] = (uint32_t)rs[e] | (run_end << 16);
             } else if (idx[e] != 0xFFFF) {
                 posc[idx[e]] = 0xFFFF;  // missing sample
             }
@@ -367,16 +373,56 @@ __global__ __launch_bounds__(256) void k_tiebits(SpearBase bs)
         tie = (rr >> 16) - (rr & 0xFFFFu) > 1u;
     }
     const uint64_t m = __ballot(tie);
-    if ((threadIdx.x & 63) == 0 && k < bs.ld) bs.tbits[c * (bs.ld / 64) + (k >> 6)] = m;
+    if ((threadIdx.x & 63) == 0 && k < bs.ld) {
+        bs.tbits[c * (bs.ld / 64) + (k >> 6)] = m;
+        if (m) atomicAdd(&bs.tcount[c], (int32_t)__popcll(m));
+    }
+}
+
+__global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) a[i] = 0;
+}
+
+// Processing order of the columns: columns whose values are mostly tied
+// (more than 1/8 of the observed positions in tie runs) first, then the
+// others, each group by decreasing observed count.  Pairs are walked along
+// the later column of this order: the walked side is the shorter one, and a
+// densely tied column is (nearly always) the fixed side, whose tie runs are
+// looked up per sample, which is cheaper than resolving runs while streaming.
+__device__ __forceinline__ uint32_t perm_key(const SpearBase& bs, int64_t c)
+{
+    const int32_t n = bs.ncol[c];
+    const bool dense = bs.tcount[c] * 8 > n;
+    return ((dense ? 0u : 1u) << 20) | (uint32_t)(65535 - n);
+}
+
+__global__ __launch_bounds__(256) void k_perm(SpearBase bs, int64_t F)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= F) return;
+    const uint32_t kc = perm_key(bs, c);
+    int64_t rank = 0;
+    for (int64_t d = 0; d < F; ++d) {
+        const uint32_t kd = perm_key(bs, d);
+        rank += (kd < kc) || (kd == kc && d < c);
+    }
+    bs.perm[rank] = (int32_t)c;
 }
 
 static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
 {
+    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, bs.tcount, F);
+    NAPY_TRY(check_launch("fill"));
     hipLaunchKernelGGL(k_tiebits, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)F), dim3(256), 0, st, bs);
-    return check_launch("tiebits");
+    NAPY_TRY(check_launch("tiebits"));
+    hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, bs, F);
+    return check_launch("perm");
 }
 
-// Presence words: pres[w][i] bit j = sample i present in column 32 w + j.
+// Presence words in processing order: pres[w][i] bit j = sample i present in
+// column perm[32 w + j].
 __global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64_t F, uint32_t* __restrict__ pres)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -386,7 +432,10 @@ __global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64
     if (i < S) {
         const int64_t c0 = w * 32;
         const int nj = (int)min((int64_t)32, F - c0);
-        for (int j = 0; j < nj; ++j) word |= (uint32_t)(bs.pos[(c0 + j) * bs.ld + i] != 0xFFFF) << j;
+        for (int j = 0; j < nj; ++j) {
+            const int64_t col = bs.perm[c0 + j];
+            word |= (uint32_t)(bs.pos[col * bs.ld + i] != 0xFFFF) << j;
+        }
     }
     pres[w * bs.ld + i] = word;
 }
@@ -416,26 +465,30 @@ __device__ __forceinline__ uint64_t bits_below(uint64_t mask, uint32_t x)
 
 struct WalkSums {
     uint32_t n;
-    uint64_t A, Ba, Bb;  // per-lane partial sums (A, Ba, Bb) plus uniform extras
+    uint64_t A, Ba, Bb;  // per-lane partial sums
     uint64_t A_u, Bb_u;  // wave-uniform contributions (deferred tie runs of b)
 };
+
+constexpr uint32_t POS_TIED = 0x8000u;  // position flag: the sample's value is tied
+constexpr uint32_t POS_MASK = 0x7FFFu;
 
 // Walk of partner b's sorted order for the pair (a, b).  The complete
 // samples are those with an a-position; b's count of complete samples below
 // each position comes from ballot + mbcnt, a's from the partner bitmap KAj /
 // prefix PAj by popcount.  Doubled rank of a tied sample: C(start) + C(end) + 1
-// over its tie run.  On the a side tied positions (bit in tA) look their run
-// up.  On the b side a chunk of 64 positions with ties (bit word tbB[c] != 0)
-// resolves the runs inside the chunk from its ballot mask; the one run that
-// may continue into the next chunk is carried as wave-uniform state (its start
-// count, and the sum of a-ranks and count of its complete samples so far) and
-// settled where it ends.
+// over its tie run.  On the a side a tied position (flag bit of its stored
+// position) looks its run up.  On the b side a chunk of 64 positions with ties
+// (bit word tbB[c] != 0) resolves the runs inside the chunk from its ballot
+// mask; the one run that may continue into the next chunk is carried as
+// wave-uniform state (its start count, plus per lane the a-ranks of its
+// complete samples so far) and settled where it ends.  Groups of U chunks
+// without any tie take a branch-free path.
 template <bool TA, bool TB>
 __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
                                           const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ runsA,
-                                          int nbv, int na, const uint16_t* posA, const uint64_t* tA,
-                                          const uint64_t* KAj, const uint16_t* PAj, int lane, bool dbg,
-                                          int32_t* dbg_ra, int32_t* dbg_rb, WalkSums& ws)
+                                          int nbv, int na, const uint16_t* posA, const uint64_t* KAj,
+                                          const uint16_t* PAj, int lane, bool dbg, int32_t* dbg_ra,
+                                          int32_t* dbg_rb, WalkSums& ws)
 {
     auto cnt_a = [&](uint32_t x) -> uint32_t {
         const uint64_t m = KAj[x >> 6];
@@ -445,79 +498,108 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
     uint32_t carry = 0;
     uint64_t sA = 0, sBa = 0, sBb = 0;
     uint64_t uA = 0, uBb = 0;            // wave-uniform
-    uint32_t open_cs = 0, pend_sum = 0, pend_t = 0;
+    uint32_t open_cs = 0, pend_t = 0;
+    uint32_t pend_lane = 0;  // per lane: a-ranks of deferred samples of the open run
     bool open = false;
     constexpr int U = 4;
     for (int c0 = 0; c0 < ncb; c0 += U) {
         // all loads of the group are issued before any use: b's sorted order
-        // (global, coalesced), a-positions (LDS gather), a-side counts (LDS)
-        uint32_t iv[U], pv[U], ca[U];
-        uint64_t tbw[U];
-        // sorted positions past b's observed count hold a dummy sample whose
+        // (global, coalesced), stored a-positions (LDS gather), a-side counts
+        // (LDS); positions past b's observed count hold a dummy sample whose
         // a-position is "missing", and the rows are padded, so no bounds tests
+        uint32_t iv[U], pv[U], ra[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            iv[u] = ordB[(c0 + u) * 64 + lane];
-            if constexpr (TB) tbw[u] = (c0 + u < ncb) ? tbB[c0 + u] : 0ull;
+        for (int u = 0; u < U; ++u) iv[u] = ordB[(c0 + u) * 64 + lane];
+        bool dirty = false;
+        uint64_t tbw[U];
+        if constexpr (TB) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                tbw[u] = (c0 + u < ncb) ? tbB[c0 + u] : 0ull;
+                dirty |= tbw[u] != 0ull;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) pv[u] = posA[iv[u]];
 #pragma unroll
-        for (int u = 0; u < U; ++u) ca[u] = cnt_a(min(pv[u], (uint32_t)na));
+        for (int u = 0; u < U; ++u) {
+            const uint32_t v = pv[u];
+            const uint32_t p = v != 0xFFFFu ? (v & POS_MASK) : (uint32_t)na;
+            ra[u] = 2u * cnt_a(p) + 2u;
+        }
         if constexpr (TA) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t p = pv[u];
-                const bool kept = p != 0xFFFFu;
-                const uint32_t pp = kept ? p : 0u;
-                const bool tied = kept && ((tA[pp >> 6] >> (pp & 63)) & 1ull);
-                if (tied) {
-                    const uint32_t rr = runsA[pp];
-                    ca[u] = cnt_a(rr & 0xFFFFu) + cnt_a(rr >> 16) + 1u;  // doubled rank already
-                } else {
-                    ca[u] = 2u * ca[u] + 2u;
+                const uint32_t v = pv[u];
+                if (v != 0xFFFFu && (v & POS_TIED)) {
+                    const uint32_t rr = runsA[v & POS_MASK];
+                    ra[u] = cnt_a(rr & 0xFFFFu) + cnt_a(rr >> 16) + 1u;
                 }
             }
         }
+        if (!dirty) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = c0 + u;
-            if (c >= ncb) break;
-            const uint32_t p = pv[u];
-            const bool kept = p != 0xFFFFu;
-            const uint64_t mask = __ballot(kept);
-            const uint32_t cb = carry + mbcnt64(mask);
-            const uint32_t Ra = TA ? ca[u] : 2u * ca[u] + 2u;
-            uint32_t Rb = 2u * cb + 2u;
-            bool direct = kept;
-            if constexpr (TB) {
-                if (tbw[u] != 0ull || open) {
+            for (int u = 0; u < U; ++u) {
+                if (c0 + u >= ncb) break;
+                const bool kept = pv[u] != 0xFFFFu;
+                const uint64_t mask = __ballot(kept);
+                const uint32_t Rb = 2u * (carry + mbcnt64(mask)) + 2u;
+                carry += (uint32_t)__popcll(mask);
+                const uint32_t Ra = ra[u];
+                sA += kept ? __umul24(Ra, Rb) : 0u;
+                if constexpr (TA) sBa += kept ? __umul24(Ra, Ra) : 0u;
+                if constexpr (TB) sBb += kept ? __umul24(Rb, Rb) : 0u;
+                if (dbg && kept) {
+                    dbg_ra[iv[u]] = (int32_t)Ra;
+                    dbg_rb[iv[u]] = (int32_t)Rb;
+                }
+            }
+            continue;
+        }
+        if constexpr (TB) {
+            uint32_t rb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = (c0 + u) * 64 + lane;
+                rb[u] = (tbw[u] != 0ull && k < nbv) ? runsB[k] : ((uint32_t)k | ((uint32_t)(k + 1) << 16));
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + u;
+                if (c >= ncb) break;
+                const bool kept = pv[u] != 0xFFFFu;
+                const uint64_t mask = __ballot(kept);
+                const uint32_t Ra = ra[u];
+                uint32_t Rb = 2u * (carry + mbcnt64(mask)) + 2u;
+                bool direct = kept;
+                if (tbw[u] != 0ull) {
+                    // a tie run can only cross into or out of a chunk that holds
+                    // tied positions
                     const uint32_t lo = (uint32_t)c * 64u;
-                    const int k = c * 64 + lane;
-                    const uint32_t rr = (k < nbv) ? runsB[k] : ((uint32_t)k | ((uint32_t)(k + 1) << 16));
-                    const uint32_t rs = rr & 0xFFFFu, re = rr >> 16;
+                    const uint32_t rs = rb[u] & 0xFFFFu, re = rb[u] >> 16;
                     const uint32_t cs = (rs >= lo) ? carry + (uint32_t)__popcll(bits_below(mask, rs - lo)) : open_cs;
                     const bool ends = re <= lo + 64u;
                     const uint32_t ce = carry + (uint32_t)__popcll(bits_below(mask, ends ? re - lo : 64u));
                     Rb = cs + ce + 1u;
-                    // settle the run carried in from the previous chunk (lane 0
+                    // settle the run carried in from earlier chunks (lane 0
                     // belongs to it) if it ends here
                     if (open) {
-                        const uint32_t e0 = __shfl(re, 0, 64);
+                        const uint32_t e0 = __builtin_amdgcn_readlane(re, 0);
                         if (e0 <= lo + 64u) {
-                            const uint32_t r_open = __shfl(Rb, 0, 64);
+                            const uint32_t r_open = __builtin_amdgcn_readlane(Rb, 0);
+                            const uint32_t pend_sum = wave_sum_u32(pend_lane);
                             uA += (uint64_t)r_open * pend_sum;
                             uBb += (uint64_t)pend_t * r_open * r_open;
                             if (dbg) {
                                 // test hook only: report the settled rank of every
                                 // complete sample of the run
-                                const uint32_t s0 = __shfl(rs, 0, 64);
+                                const uint32_t s0 = __builtin_amdgcn_readlane(rs, 0);
                                 for (uint32_t kk = s0 + (uint32_t)lane; kk < e0; kk += 64u) {
                                     const uint32_t ii = ordB[kk];
                                     if (posA[ii] != 0xFFFFu) dbg_rb[ii] = (int32_t)r_open;
                                 }
                             }
-                            pend_sum = 0;
+                            pend_lane = 0;
                             pend_t = 0;
                             open = false;
                         }
@@ -526,32 +608,28 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                     direct = kept && ends;
                     const uint64_t dm = __ballot(defer);
                     if (dm) {
-                        pend_sum += wave_sum_u32(defer ? Ra : 0u);
+                        pend_lane += defer ? Ra : 0u;
                         pend_t += (uint32_t)__popcll(dm);
                         open = true;
-                        open_cs = __shfl(cs, 63, 64);
+                        open_cs = __builtin_amdgcn_readlane(cs, 63);
                     } else if (!open) {
                         // a run can also continue with no complete sample yet
-                        const uint32_t e63 = __shfl(re, 63, 64);
+                        const uint32_t e63 = __builtin_amdgcn_readlane(re, 63);
                         const bool v63 = (c * 64 + 63) < nbv;
                         if (v63 && e63 > lo + 64u) {
                             open = true;
-                            open_cs = __shfl(cs, 63, 64);
+                            open_cs = __builtin_amdgcn_readlane(cs, 63);
                         }
                     }
                 }
-            }
-            carry += (uint32_t)__popcll(mask);
-            if (direct) {
-                sA += __umul24(Ra, Rb);
-                if constexpr (TB) sBb += __umul24(Rb, Rb);
-            }
-            if constexpr (TA) {
-                if (kept) sBa += __umul24(Ra, Ra);
-            }
-            if (dbg && kept) {
-                dbg_ra[iv[u]] = (int32_t)Ra;
-                if (direct) dbg_rb[iv[u]] = (int32_t)Rb;
+                carry += (uint32_t)__popcll(mask);
+                sA += direct ? __umul24(Ra, Rb) : 0u;
+                sBb += direct ? __umul24(Rb, Rb) : 0u;
+                if constexpr (TA) sBa += kept ? __umul24(Ra, Ra) : 0u;
+                if (dbg && kept) {
+                    dbg_ra[iv[u]] = (int32_t)Ra;
+                    if (direct) dbg_rb[iv[u]] = (int32_t)Rb;
+                }
             }
         }
     }
@@ -563,11 +641,11 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
     ws.Bb_u = uBb;
 }
 
-// One workgroup per (column a, block of PB partner columns).  Step 1 builds,
-// for all PB partners at once, the bitmap "partner present" along a's sorted
-// order (one presence-word gather per position, one ballot per partner) and
-// its per-64 prefix counts.  Step 2 walks each partner's sorted order once
-// (pair_walk).
+// One workgroup per (column a, block of PB partner columns), both in the
+// processing order perm (k_perm).  Step 1 builds, for all PB partners at
+// once, the bitmap "partner present" along a's sorted order (one
+// presence-word gather per position, one ballot per partner) and its per-64
+// prefix counts.  Step 2 walks each partner's sorted order once (pair_walk).
 template <int PB>
 __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint32_t* __restrict__ pres,
                                                                  int64_t S, int64_t F, PairOut po)
@@ -575,22 +653,19 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool dbg = po.dbg_ra != nullptr;
-    const int64_t a = dbg ? po.dbg_a : (int64_t)blockIdx.y;
-    const int64_t blk = dbg ? po.dbg_b / PB : (int64_t)blockIdx.x;
-    const int64_t b0 = blk * PB;
-    if (a >= F || b0 >= F) return;
-    if (!dbg && b0 + PB - 1 < a) return;
+    // logical indices (processing order); dbg: one pair of physical columns
+    const int64_t la = dbg ? 0 : (int64_t)blockIdx.y;
+    const int64_t b0 = dbg ? 0 : (int64_t)blockIdx.x * PB;
+    if (!dbg && (la >= F || b0 >= F || b0 + PB - 1 < la)) return;
+    const int64_t a = dbg ? po.dbg_a : bs.perm[la];
 
     const int64_t ld = bs.ld;
-    const int64_t nwd = ld / 64;  // tie-bit words per column
     const int ncmax = (int)ceil_div(S, 64) + 1;
     const size_t off_ka = (size_t)round_up(ld * 2, 16);
     const size_t off_pa = off_ka + (size_t)PB * ncmax * 8;
-    const size_t off_ta = (size_t)round_up((int64_t)(off_pa + (size_t)PB * ncmax * 2), 16);
     uint16_t* posA = (uint16_t*)smem_raw;
     uint64_t* KA = (uint64_t*)(smem_raw + off_ka);  // [PB][ncmax]
     uint16_t* PA = (uint16_t*)(smem_raw + off_pa);  // [PB][ncmax]
-    uint64_t* TAb = (uint64_t*)(smem_raw + off_ta); // [nwd] tie bits of a
 
     const int na = bs.ncol[a];
     const int tA = bs.hasties[a];
@@ -601,13 +676,12 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         const uint32_t* src = (const uint32_t*)(bs.pos + a * ld);
         uint32_t* dst = (uint32_t*)posA;
         for (int64_t w = threadIdx.x; w < ld / 2; w += PAIR_THREADS) dst[w] = src[w];
-        if (tA)
-            for (int64_t w = threadIdx.x; w < nwd; w += PAIR_THREADS) TAb[w] = bs.tbits[a * nwd + w];
     }
 
     // ---- step 1: partner presence along a's order, PB partners at once -----
     const uint32_t* presw = pres + (b0 >> 5) * ld;
     const int shift = (int)(b0 & 31);  // 0, or 16 when PB == 16
+    const uint16_t* posDbg = bs.pos + (int64_t)po.dbg_b * ld;
     constexpr int Q = 4;                // chunks per wave in flight
     for (int cq = wave; cq <= nca; cq += PAIR_WAVES * Q) {
         uint32_t idx[Q], word[Q];
@@ -617,7 +691,12 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             idx[q] = (p < na) ? ordA[p] : 0xFFFFFFFFu;
         }
 #pragma unroll
-        for (int q = 0; q < Q; ++q) word[q] = (idx[q] != 0xFFFFFFFFu) ? (presw[idx[q]] >> shift) : 0u;
+        for (int q = 0; q < Q; ++q) {
+            if (dbg)  // test hook: the single partner's presence, from its positions
+                word[q] = (idx[q] != 0xFFFFFFFFu) ? (uint32_t)(posDbg[idx[q]] != 0xFFFF) : 0u;
+            else
+                word[q] = (idx[q] != 0xFFFFFFFFu) ? (presw[idx[q]] >> shift) : 0u;
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int c = cq + q * PAIR_WAVES;
@@ -646,24 +725,24 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     __syncthreads();
 
     // ---- step 2: one walk of each partner's sorted order ---------------------
-    for (int j = wave; j < PB; j += PAIR_WAVES) {
-        const int64_t b = b0 + j;
-        if (b >= F) break;
-        if (dbg ? (b != po.dbg_b) : (b < a)) continue;
+    for (int j = wave; j < (dbg ? 1 : PB); j += PAIR_WAVES) {
+        const int64_t lb = b0 + j;
+        if (!dbg && (lb >= F || lb < la)) continue;
+        const int64_t b = dbg ? po.dbg_b : bs.perm[lb];
         const int nbv = bs.ncol[b];
         const int tB = bs.hasties[b];
         const uint16_t* ordB = bs.ord + b * ld;
         const uint32_t* runsB = bs.runs + b * ld;
-        const uint64_t* tbB = bs.tbits + b * nwd;
+        const uint64_t* tbB = bs.tbits + b * (ld / 64);
         const uint64_t* KAj = KA + (size_t)j * ncmax;
         const uint16_t* PAj = PA + (size_t)j * ncmax;
         WalkSums w;
         if (tA) {
-            if (tB) pair_walk<true, true>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
-            else pair_walk<true, false>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            if (tB) pair_walk<true, true>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            else pair_walk<true, false>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
         } else {
-            if (tB) pair_walk<false, true>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
-            else pair_walk<false, false>(ordB, runsB, tbB, runsA, nbv, na, posA, TAb, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            if (tB) pair_walk<false, true>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            else pair_walk<false, false>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
         }
         const uint64_t sA = wave_sum_u64(w.A) + w.A_u;
         const uint64_t sBa = tA ? wave_sum_u64(w.Ba) : 0ull;
@@ -672,7 +751,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             const int64_t nn = (int64_t)w.n;
             const double Ba = tA ? (double)sBa : (double)sum_sq_doubled_untied(nn);
             const double Bb = tB ? (double)sBb : (double)sum_sq_doubled_untied(nn);
-            const int64_t pid = pair_index(a, b, F);
+            const int64_t g = a < b ? a : b, h = a < b ? b : a;
+            const int64_t pid = pair_index(g, h, F);
             po.sums[pid] = make_double4((double)nn, (double)sA, Ba, Bb);
             po.ab[pid] = make_int2((int)a, (int)b);
         }
@@ -788,6 +868,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
                 const uint32_t s0 = P[rr & 0xFFFFu], e0 = P[rr >> 16];
                 qruns[P[k]] = s0 | (e0 << 16);
                 tie |= (e0 - s0) > 1u;
+                qpos[nr] = (uint16_t)(P[k] | ((e0 - s0 > 1u) ? 0x8000 : 0));
             }
         }
     }
@@ -810,9 +891,7 @@ static size_t pair_smem_bytes(int64_t S, int PB)
     size_t off = (size_t)round_up(ld * 2, 16);
     off += (size_t)PB * ncmax * 8;  // KA
     off += (size_t)PB * ncmax * 2;  // PA
-    off = (size_t)round_up((int64_t)off, 16);
-    off += (size_t)(ld / 64) * 8;  // tie bits of a
-    return off;
+    return (size_t)round_up((int64_t)off, 16);
 }
 
 template <int PB>
