@@ -149,9 +149,27 @@ def pair_ranks(X: np.ndarray, g: int, h: int, missing: Optional[float] = None):
     return rg, rh, int(n)
 
 
+def beta_tail(a, ar) -> np.ndarray:
+    """I_{1-r^2}(a, 1/2) for |r| = ar in [0, 1], through scipy's betainc.
+
+    1 - r^2 rounds to 1 in FP64 once r^2 is below the machine epsilon, which
+    would give p = 1 where the true p is 1 - O(|r| sqrt(a)).  So where p > 1/2
+    the same quantity is taken through the symmetry I_x(a, b) = 1 - I_{1-x}(b, a)
+    as 1 - I_{r^2}(1/2, a), and elsewhere directly.  There 1 - r^2 is formed
+    as 1 - r*r for |r| < 1/2 (within an ulp of 1) and as (1 - |r|)(1 + |r|)
+    above, where 1 - |r| is exact: p at large a amplifies a relative error of
+    1 - r^2 about a-fold."""
+    from scipy import special
+    a = np.asarray(a, dtype=np.float64)
+    ar = np.clip(np.abs(np.asarray(ar, dtype=np.float64)), 0.0, 1.0)
+    x = np.where(ar < 0.5, 1.0 - ar * ar, (1.0 - ar) * (1.0 + ar))
+    direct = special.betainc(a, 0.5, x)
+    comp = 1.0 - special.betainc(0.5, a, ar * ar)
+    return np.where(comp > 0.5, comp, direct)
+
+
 def pvalue(r, n, method: str) -> np.ndarray:
     """Two-sided p = I_{1-r^2}((n-2)/2, 1/2) with the paper's undefined cases."""
-    from scipy import special
     r = np.asarray(r, dtype=np.float64)
     n = np.asarray(n, dtype=np.int64)
     p = np.full(np.broadcast(r, n).shape, np.nan, dtype=np.float64)
@@ -159,8 +177,7 @@ def pvalue(r, n, method: str) -> np.ndarray:
     n_b = np.broadcast_to(n, p.shape)
     ok = (n_b >= 3) & np.isfinite(r_b)
     a = (n_b[ok] - 2).astype(np.float64) / 2.0
-    x = 1.0 - r_b[ok] * r_b[ok]
-    p[ok] = special.betainc(a, 0.5, np.clip(x, 0.0, 1.0))
+    p[ok] = beta_tail(a, r_b[ok])
     if method == "pearson":
         two = (n_b == 2) & np.isfinite(r_b)
         p[two] = PEARSON_P_AT_N2
@@ -172,8 +189,14 @@ def pvalue_mp(r: float, n: int, dps: int = 50) -> float:
     import mpmath
     with mpmath.workdps(dps):
         a = mpmath.mpf(int(n) - 2) / 2
-        x = 1 - mpmath.mpf(float(r)) ** 2
-        return float(mpmath.betainc(a, mpmath.mpf(1) / 2, 0, x, regularized=True))
+        y = mpmath.mpf(float(r)) ** 2
+        # the same value through I_x(a, b) = 1 - I_{1-x}(b, a) while that keeps
+        # at least half of the working digits: mpmath's series for I_x(a, 1/2)
+        # stalls for x near 1 and large a
+        comp = 1 - mpmath.betainc(mpmath.mpf(1) / 2, a, 0, y, regularized=True)
+        if comp > mpmath.mpf(10) ** (-(dps // 2)):
+            return float(comp)
+        return float(mpmath.betainc(a, mpmath.mpf(1) / 2, 0, 1 - y, regularized=True))
 
 
 def pearson(X: np.ndarray, missing: Optional[float] = None, nthreads: int = 0):

@@ -41,7 +41,7 @@ def assert_p_close(p_gpu, p_orc, r_orc, n, dr_max, where=""):
     is within d of the oracle's gives a p between the values at |r| + d and
     |r| - d (d = 2 dr_max plus rounding); 1e-9 relative slack covers the
     p routine's own error.  n = 2 (Pearson p = 1) must match exactly."""
-    from scipy import special
+    from oracle.oracle import beta_tail
     p_gpu = np.asarray(p_gpu, dtype=np.float64).ravel()
     p_orc = np.asarray(p_orc, dtype=np.float64).ravel()
     r = np.asarray(r_orc, dtype=np.float64).ravel()
@@ -60,8 +60,8 @@ def assert_p_close(p_gpu, p_orc, r_orc, n, dr_max, where=""):
     ar = np.abs(r[m])
     r_hi = np.clip(ar + d, 0.0, 1.0)
     r_lo = np.clip(ar - d, 0.0, 1.0)
-    p_min = special.betainc(a, 0.5, np.clip(1.0 - r_hi * r_hi, 0.0, 1.0))
-    p_max = special.betainc(a, 0.5, np.clip(1.0 - r_lo * r_lo, 0.0, 1.0))
+    p_min = beta_tail(a, r_hi)
+    p_max = beta_tail(a, r_lo)
     pg = p_gpu[m]
     ok_lo = pg >= p_min * (1 - 1e-9) - 1e-300
     ok_hi = pg <= p_max * (1 + 1e-9) + 1e-300

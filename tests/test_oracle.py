@@ -211,6 +211,25 @@ def test_pvalue_against_mpmath():
         assert abs(p - ref) <= 1e-12 * max(ref, 1e-300), (n, r, p, ref)
 
 
+@pytest.mark.parametrize("r", [1e-12, -3e-9, 2e-8, 1e-6])
+def test_pvalue_tiny_r(r):
+    """1 - r^2 rounds to 1 in FP64 for these r; p must still fall below 1 by
+    the right amount.  n = 3, 4: the closed forms; large n: the leading term
+    of I_y(1/2, a) as y -> 0, which is 2 sqrt(y) / B(1/2, a), so
+    1 - p = 2|r| / B(1/2, a) up to a relative O(a r^2) correction."""
+    p3 = orc.pvalue(np.array([r]), np.array([3]), "pearson")[0]
+    p4 = orc.pvalue(np.array([r]), np.array([4]), "pearson")[0]
+    assert abs((1 - p3) - 2 / math.pi * math.asin(abs(r))) <= 1e-15
+    assert abs((1 - p4) - abs(r)) <= 1e-15
+    for n in (1000, 28000):
+        a = (n - 2) / 2
+        lnB = math.lgamma(0.5) + math.lgamma(a) - math.lgamma(a + 0.5)
+        q = 2 * abs(r) / math.exp(lnB)
+        p = orc.pvalue(np.array([r]), np.array([n]), "pearson")[0]
+        assert abs((1 - p) - q) <= 2e-15 + 1e-6 * q, (n, r, 1 - p, q)
+        assert abs(p - orc.pvalue_mp(r, n)) <= 1e-15
+
+
 def test_pvalue_equals_student_t_tail():
     from scipy import stats
     for n in (3, 4, 5, 10, 1000):
