@@ -14,7 +14,15 @@ the roofline of the dominant kernel (the Spearman re-ranking scan), the
 accuracy of both Pearson precisions on sampled pairs against the FP64 oracle,
 and the oracle's own throughput on the host cores (cpu_baseline).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Two further forms print their own JSON line:
+  --form precision  50,000 x 4,000 (column means U(1e3, 1e5), sd 1, 25% MCAR):
+                    FP32 vs BF16x3 contractions, time and error per output
+                    against the FP64 oracle on sampled pairs;
+  --form serving    continuous-batching server on a resident 20,000 x 2,000
+                    base with a Poisson query stream at 200 queries/s:
+                    p50/p99 latency and pairs/s.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form headline|precision|serving]
 """
 
 from __future__ import annotations
@@ -102,6 +110,13 @@ def main() -> int:
                     help="pairs in the oracle's timed sample (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--form", default="headline", choices=["headline", "precision", "serving"])
+    ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
+    ap.add_argument("--warmup-queries", type=int, default=100, help="serving: warm-up queries")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent queries (HIP streams)")
+    ap.add_argument("--arena-gib", type=float, default=6.0, help="serving: device memory for queries")
+    ap.add_argument("--acc-pairs", type=int, default=20000, help="precision: sampled pairs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -111,6 +126,11 @@ def main() -> int:
     if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
         print("bench.py is single-process, single-GPU", file=sys.stderr)
         return 2
+
+    if args.form == "serving":
+        return run_serving(args)
+    if args.form == "precision":
+        return run_precision(args)
 
     import numpy as np
     import torch
@@ -285,6 +305,184 @@ def main() -> int:
         res["cpu_baseline"] = {"value": v, "unit": "var-pairs/s", "cores": cores, "kind": "oracle",
                                "sample": f"{npairs} random pairs of the same 10,000 x 1,000 matrix, "
                                          f"Pearson + Spearman with p-values, {dt:.1f} s"}
+    print(json.dumps(res))
+    return 0
+
+
+def _pct(a, q):
+    import numpy as np
+    return float(np.percentile(a, q)) if len(a) else float("nan")
+
+
+def run_serving(args) -> int:
+    """Continuous batching on a resident 20,000 x 2,000 base: warm-up queries,
+    then the measured stream replayed in real time."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_00448_amd.serve import Request, Server
+
+    dev = torch.device("cuda:0")
+    X = synth.cfg_serving_base()
+    S, F = X.shape
+    Xd = torch.from_numpy(X).to(dev)
+    total = args.warmup_queries + args.queries
+    qs = synth.serving_queries(total, S, F, rate=args.rate)
+    reqs = [Request(i, q.method, q.rows, q.cols, q.arrival_s) for i, q in enumerate(qs)]
+    srv = Server(Xd, slots=args.slots, capacity=int(args.arena_gib * (1 << 30)), precision=args.precision)
+    warm = reqs[:args.warmup_queries]
+    if warm:
+        t0 = warm[0].arrival
+        srv.serve([Request(q.qid, q.method, q.rows, q.cols, q.arrival - t0) for q in warm])
+    meas = reqs[args.warmup_queries:]
+    t0 = meas[0].arrival
+    meas = [Request(q.qid, q.method, q.rows, q.cols, q.arrival - t0) for q in meas]
+    comps = []
+    print(f"[serving] {len(meas)} queries over {meas[-1].arrival:.1f} s of arrivals", file=sys.stderr, flush=True)
+    stats = srv.serve(meas, on_done=comps.append)
+    per = {}
+    for m in ("pearson", "spearman"):
+        lat = np.array([c.latency for c in comps if c.method == m]) * 1e3
+        per[m] = {"queries": int(len(lat)), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                  "pairs": int(sum(c.pairs for c in comps if c.method == m))}
+    wait = np.array([c.admitted - c.arrival for c in comps]) * 1e3
+    res = {
+        "metric": "serving: pairs/s with p50/p99 latency, Poisson query stream on a resident base",
+        "value": stats["pairs_per_s"], "unit": "var-pairs/s", "n_gpus": 1,
+        "higher_is_better": True, "form": "serving", "dtype": f"{args.precision} (Pearson) + int (Spearman)",
+        "data": "synthetic",
+        "config": {"workload": "base 20,000 samples x 2,000 variables (rank-20 factor model, 30% MCAR); "
+                               f"Poisson arrivals at {args.rate:g}/s; rows U(10%, 90%), variables "
+                               "U{50..2000}, Pearson or Spearman with probability 1/2",
+                   "queries": len(meas), "warmup_queries": len(warm), "slots": args.slots,
+                   "arena_bytes": int(args.arena_gib * (1 << 30))},
+        "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"],
+        "max_ms": stats["max_ms"], "queue_wait_p50_ms": _pct(wait, 50), "queue_wait_p99_ms": _pct(wait, 99),
+        "per_method": per, "wall_s": stats["wall_s"], "arrival_span_s": meas[-1].arrival,
+        "max_concurrent": stats["max_concurrent"], "arena_peak_bytes": stats["arena_peak_bytes"],
+        "device_busy_frac": stats.get("device_busy_frac"),
+    }
+    print(json.dumps(res))
+    return 0
+
+
+def run_precision(args) -> int:
+    """FP32 vs BF16x3 contractions at 50,000 x 4,000: time of each and the
+    error of r, n and p against the FP64 oracle on sampled pairs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import oracle as orc
+    from paper_2505_00448_amd import _lib
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    X = synth.cfg_precision()
+    S, F = X.shape
+    Xd = torch.from_numpy(X).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    r = torch.empty((F, F), dtype=torch.float64, device=dev)
+    p = torch.empty((F, F), dtype=torch.float64, device=dev)
+    n = torch.empty((F, F), dtype=torch.int32, device=dev)
+    hip = HipEvents()
+    ev = [hip.new() for _ in range(4)]
+    ev_arr = (ctypes.c_void_p * 4)(*[e.value for e in ev])
+    flops = 12.0 * S * F * (F + 1) / 2
+    rng = np.random.default_rng(11)
+    k = args.acc_pairs
+    g = rng.integers(0, F, k)
+    h = rng.integers(0, F, k)
+    off = g != h
+    g, h = g[off], h[off]
+    # two full 64 x 64 diagonal tiles (upper triangles incl. the diagonal)
+    tg, th = [], []
+    for t0 in (0, (F // 2) // 64 * 64):
+        a, b = np.triu_indices(64)
+        tg.append(a + t0)
+        th.append(b + t0)
+    dg = np.arange(F)
+    G = np.concatenate([g] + tg + [dg])
+    H = np.concatenate([h] + th + [dg])
+    kind = np.concatenate([np.zeros(len(g), int)] + [np.where(a == b, 1, 0) for a, b in zip(tg, th)]
+                          + [np.ones(F, int)])
+    print(f"[precision] oracle on {len(G)} pairs", file=sys.stderr, flush=True)
+    ro, po, no = orc.pearson_pairs(X, G, H)
+    # duplicated columns: 64 columns next to exact copies of themselves
+    Xdup = np.ascontiguousarray(np.concatenate([X[:, :64], X[:, :64]], axis=1))
+    Xdupd = torch.from_numpy(Xdup).to(dev)
+    rdup = torch.empty((128, 128), dtype=torch.float64, device=dev)
+    res_prec = {}
+    for prec in ("fp32", "bf16x3"):
+        opts = _lib.make_opts(prec)
+        need = lib.napy_pearson_workspace(S, F, ctypes.byref(opts))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+        def call():
+            st = lib.napy_pearson_profiled(P(Xd), S, F, F, P(r), P(p), P(n), F, P(ws), need,
+                                           ctypes.byref(opts), sh, ev_arr)
+            _lib.check(st, "napy_pearson_profiled")
+
+        for _ in range(args.warmup):
+            call()
+        steps = max(3, min(args.steps, 10))
+        tot, con = [], []
+        for _ in range(steps):
+            call()
+            torch.cuda.synchronize(dev)
+            tot.append(hip.ms(ev[0], ev[3]))
+            con.append(hip.ms(ev[1], ev[2]))
+        tot_ms, con_ms = float(np.median(tot)), float(np.median(con))
+        Gd = torch.from_numpy(G).to(dev)
+        Hd = torch.from_numpy(H).to(dev)
+        rg = r[Gd, Hd].cpu().numpy()
+        pg = p[Gd, Hd].cpu().numpy()
+        ng = n[Gd, Hd].cpu().numpy()
+        ok = np.isfinite(ro) & np.isfinite(rg)
+        dr = np.abs(rg - ro)
+        rep = {"call_ms": tot_ms, "contract_ms": con_ms,
+               "contract_tflops_fp32_equiv": flops / con_ms / 1e9,
+               "n_mismatches": int(np.sum(ng != no)),
+               "nan_mismatches": int(np.sum(np.isnan(rg) != np.isnan(ro)))}
+        for name, sel in (("offdiag", kind == 0), ("diag", kind == 1)):
+            d = dr[sel & ok]
+            rep[f"max_abs_dr_{name}"] = float(d.max()) if len(d) else None
+            rep[f"p999_abs_dr_{name}"] = _pct(d, 99.9)
+        # p function at the GPU's own (r, n), against the oracle's betainc
+        pf = orc.pvalue(rg, ng.astype(np.int64), "pearson")
+        big = np.isfinite(pf) & (pf > 1e-300) & np.isfinite(pg)
+        rep["max_rel_err_p_function"] = float(np.max(np.abs(pg[big] - pf[big]) / pf[big])) if big.any() else None
+        # duplicated-column pairs: r must be 1
+        wsd = torch.empty(lib.napy_pearson_workspace(S, 128, ctypes.byref(opts)), dtype=torch.uint8, device=dev)
+        st = lib.napy_pearson(P(Xdupd), S, 128, 128, P(rdup), None, None, 128, P(wsd), wsd.numel(),
+                              ctypes.byref(opts), sh)
+        _lib.check(st, "napy_pearson")
+        rd = rdup.cpu().numpy()
+        rep["max_abs_dr_duplicated"] = float(np.max(np.abs(rd[np.arange(64), np.arange(64) + 64] - 1.0)))
+        if prec == "fp32":
+            rep["mfma_frac"] = flops / con_ms / 1e9 / (FP32_MFMA_PEAK_FLOPS / 1e12)
+        else:
+            # 19 bf16 products per pair-sample are executed (two flop each)
+            rep["mfma_frac"] = 19 * 2.0 * S * F * (F + 1) / 2 / con_ms / 1e9 / (BF16_PEAK_FLOPS / 1e12)
+        res_prec[prec] = rep
+        del ws
+    hip.close()
+    b, f = res_prec["bf16x3"], res_prec["fp32"]
+    worst_b = max(b["max_abs_dr_offdiag"], b["max_abs_dr_diag"], b["max_abs_dr_duplicated"])
+    res = {
+        "metric": "precision form: Pearson contraction time and |dr| vs FP64, FP32 vs BF16x3",
+        "value": b["contract_tflops_fp32_equiv"], "unit": "TFLOP/s (FP32-equivalent, 12 flop per pair-sample)",
+        "n_gpus": 1, "higher_is_better": True, "form": "precision", "data": "synthetic",
+        "config": {"workload": "50,000 samples x 4,000 variables, column means U(1e3, 1e5), sd 1, "
+                               "rank-5 factor model, 25% MCAR", "samples": S, "variables": F,
+                   "sampled_pairs": int(len(G)), "diag_pairs": F, "duplicated_pairs": 64},
+        "bf16x3": b, "fp32": f,
+        "bf16x3_speedup_vs_fp32": f["contract_ms"] / b["contract_ms"],
+        "bf16x3_within_1e-6": bool(worst_b <= 1e-6),
+    }
     print(json.dumps(res))
     return 0
 

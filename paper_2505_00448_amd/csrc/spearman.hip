@@ -1062,10 +1062,14 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
     w.sums = c.take<double4>(npairs);
     w.ab = c.take<int2>(npairs);
     w.keys = nullptr;
-    hipLaunchKernelGGL(k_rowmap, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, st, rows, Sq, S, rowmap);
-    NAPY_TRY(check_launch("rowmap"));
-    hipLaunchKernelGGL(k_rowmap_set, dim3((unsigned)ceil_div(Sq, 256)), dim3(256), 0, st, rows, Sq, rowmap);
-    NAPY_TRY(check_launch("rowmap_set"));
+    if (S > 0) {
+        hipLaunchKernelGGL(k_rowmap, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, st, rows, Sq, S, rowmap);
+        NAPY_TRY(check_launch("rowmap"));
+    }
+    if (Sq > 0) {
+        hipLaunchKernelGGL(k_rowmap_set, dim3((unsigned)ceil_div(Sq, 256)), dim3(256), 0, st, rows, Sq, rowmap);
+        NAPY_TRY(check_launch("rowmap_set"));
+    }
     hipLaunchKernelGGL(k_compact, dim3((unsigned)Fq), dim3(SORT_THREADS), 0, st, b, cols, rowmap, Sq, w.base);
     NAPY_TRY(check_launch("compact"));
     NAPY_TRY(tiebits_launch(w.base, Fq, st));

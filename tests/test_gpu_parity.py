@@ -262,6 +262,35 @@ def test_headline_full_size(gpu_device, headline, method, precision):
 
 
 # ---------------------------------------------------------------------------
+# precision form at full size (50,000 x 4,000, column means up to 1e5)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def precision_case():
+    X = synth.cfg_precision()
+    M = (~np.isnan(X)).astype(np.float32)
+    # 0/1 products summed in float32 stay exact below 2**24
+    N = (M.T @ M).astype(np.int64)
+    return X, N
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_precision_form_full_size(gpu_device, precision_case, precision):
+    X, N = precision_case
+    S, F = X.shape
+    print(f"[precision-form] {S}x{F} {precision}", flush=True)
+    r, p, n = _run("pearson", X, gpu_device, precision)
+    where = f"precision-form-{precision}"
+    assert_counts_equal(n, N, where + "-full-n")
+    assert np.array_equal(r, r.T, equal_nan=True)
+    assert np.nanmax(np.abs(r)) <= 1.0
+    gi, hi = _sample_pairs(F, 1500, 29)
+    ro, po, no = orc.pearson_pairs(X, gi, hi)
+    worst = assert_r_close(r[gi, hi], ro, 1e-6, where)
+    assert_p_close(p[gi, hi], po, ro, no, max(worst, 1e-15), where)
+
+
+# ---------------------------------------------------------------------------
 # tie runs of every length and position relative to the 64-position chunks
 # ---------------------------------------------------------------------------
 
