@@ -1,7 +1,7 @@
 """Continuous-batching query server for the interactive-explorer use case.
 
 The paper motivates fast all-pairs association on the fly in an interactive
-explorer over a cohort (NApy, Section 1 and Section 5): a user picks a subset
+explorer over a cohort (NApy, Sections 1 and 6): a user picks a subset
 of the samples and a subset of the variables and wants the correlation
 matrices back at once.  Here that becomes a request loop on one GPU:
 
