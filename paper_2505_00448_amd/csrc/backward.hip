@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const float* __restrict__ X, i
 {
     __shared__ __attribute__((aligned(16))) float sx[BT * LDH];      // x0 with NaN for missing: [i][h]
     __shared__ __attribute__((aligned(16))) float sc[3][BT * LDH];   // coefficients: [g][h]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t i0 = (int64_t)blockIdx.x * BT, g0 = (int64_t)blockIdx.y * BT;
     // centring must match the forward's: float mean for FP32/BF16X3, double

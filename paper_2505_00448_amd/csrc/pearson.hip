@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
     tile_coords(t, T, tg, th);
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
     const int wm = wave >> 1, wn = wave & 1;
 
     const int64_t kbeg = (int64_t)split * ksplit;

@@ -25,14 +25,16 @@
 //                    a has-ties flag.
 //   k_presence       presence words: bit j of pres[w][i] = sample i present
 //                    in column 32 w + j.
-//   k_spearman_pairs one workgroup per (column a, block of 16 partners b).  pos_a lives in LDS.  Step 1 builds
-//                    the "partner present" bitmaps along a's sorted order for
-//                    all partners at once (one presence-word gather per
-//                    position, one ballot per partner) plus per-64 prefix
-//                    counts.  Step 2: each wave walks one partner's sorted
-//                    order once; b's count of complete samples below each
-//                    position comes from ballot + mbcnt, a's from the bitmap
-//                    by popcount; both doubled ranks and the sums follow.
+//   k_spearman_pairs one workgroup per (column a, block of 8 partners b).  pos_a
+//                    lives in LDS.  Step 1 builds, for all 8 partners at
+//                    once, a table along a's sorted order: the partner's
+//                    presence bits per 32 positions and the count before
+//                    them (one presence-word gather per position, one ballot
+//                    per partner), plus the tie defects of a's runs.  Step 2:
+//                    each wave walks one partner's sorted order once; b's
+//                    count of complete samples below each position comes from
+//                    ballot + mbcnt, a's from the table by popcount; the
+//                    rank products and b's tie defects follow.
 //   k_spearman_final one thread per pair: rho, p, n into both triangles.
 #include "napy_internal.hpp"
 #include "pvalue.hpp"
@@ -48,6 +50,7 @@ struct SpearBase {
     uint16_t* pos;     // [F][ld]
     uint32_t* runs;    // [F][ld]
     uint64_t* tbits;   // [F][ld/64]: bit k set if sorted position k lies in a tie run
+    uint64_t* rsbits;  // [F][ld/64]: bit k set if a tie run starts at sorted position k
     int32_t* ncol;     // [F]
     int32_t* hasties;  // [F]
     int32_t* tcount;   // [F] number of positions in tie runs
@@ -56,9 +59,10 @@ struct SpearBase {
 };
 
 // Row stride of the per-column arrays: room for every sample plus one dummy
-// sample index S whose position is always "missing", so sorted-order reads
-// past a column's observed count need no bounds test.
-static inline int64_t spear_ld(int64_t S) { return round_up(S + 1, 64); }
+// sample index S whose position is always "missing", padded to whole groups
+// of four 64-position chunks, so sorted-order reads past a column's observed
+// count need no bounds test.
+static inline int64_t spear_ld(int64_t S) { return round_up(S + 1, 256); }
 // sorted orders may be read up to this many entries past the last row
 constexpr int64_t ORD_TAIL = 512;
 
@@ -69,6 +73,7 @@ static void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
     b.pos = c.take<uint16_t>((size_t)F * b.ld);
     b.runs = c.take<uint32_t>((size_t)F * b.ld);
     b.tbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
+    b.rsbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
     b.ncol = c.take<int32_t>(F);
     b.hasties = c.take<int32_t>(F);
     b.tcount = c.take<int32_t>(F);
@@ -367,14 +372,17 @@ __global__ __launch_bounds__(256) void k_tiebits(SpearBase bs)
     const int64_t c = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int nc = bs.ncol[c];
-    bool tie = false;
+    bool tie = false, start = false;
     if (k < nc) {
         const uint32_t rr = bs.runs[c * bs.ld + k];
         tie = (rr >> 16) - (rr & 0xFFFFu) > 1u;
+        start = tie && (rr & 0xFFFFu) == (uint32_t)k;
     }
     const uint64_t m = __ballot(tie);
+    const uint64_t ms = __ballot(start);
     if ((threadIdx.x & 63) == 0 && k < bs.ld) {
         bs.tbits[c * (bs.ld / 64) + (k >> 6)] = m;
+        bs.rsbits[c * (bs.ld / 64) + (k >> 6)] = ms;
         if (m) atomicAdd(&bs.tcount[c], (int32_t)__popcll(m));
     }
 }
@@ -463,97 +471,131 @@ __device__ __forceinline__ uint64_t bits_below(uint64_t mask, uint32_t x)
     return x >= 64u ? mask : (mask & ((1ull << x) - 1ull));
 }
 
-struct WalkSums {
-    uint32_t n;
-    uint64_t A, Ba, Bb;  // per-lane partial sums
-    uint64_t A_u, Bb_u;  // wave-uniform contributions (deferred tie runs of b)
-};
-
 constexpr uint32_t POS_TIED = 0x8000u;  // position flag: the sample's value is tied
 constexpr uint32_t POS_MASK = 0x7FFFu;
 
+// Partner table of one partner along column a's sorted order, one entry per
+// 32 positions: x = presence bits of the partner at positions 32w..32w+31,
+// y = 1 + number of partner-present positions before 32w.  Entry NW (just
+// past the words covering positions 0..n_a) is {0, 0}: looking up any
+// position >= 32 NW gives 0.
+__device__ __forceinline__ uint32_t cnt1(const uint2* tab, uint32_t x)
+{
+    const uint2 e = *(const uint2*)((const char*)tab + ((x >> 5) << 3));
+    // the field width of the bit-field extract is taken modulo 32 by the
+    // hardware: the low x mod 32 bits
+    return e.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(e.x, 0u, x));
+}
+
+// doubled average rank of a tied a-position: C(s) + C(e) + 1 over its run
+__device__ __forceinline__ uint32_t ra_tied(const uint2* tab, const uint32_t* __restrict__ runsA, uint32_t pos)
+{
+    const uint32_t rr = runsA[pos];
+    return cnt1(tab, rr & 0xFFFFu) + cnt1(tab, rr >> 16) - 1u;
+}
+
+// t^3 - t: a tie run of t complete samples lowers the sum of squared doubled
+// ranks by (t^3 - t) / 3 relative to untied ranks 2, 4, ..., 2n; the sums of
+// t^3 - t are divided by 3 once (each term is a multiple of 3)
+__device__ __forceinline__ uint64_t cube_minus(uint32_t t)
+{
+    return (uint64_t)(t * t) * t - t;
+}
+
+struct WalkSums {
+    uint32_t n;
+    uint64_t A4;   // per lane: sum of C1_a * C1_b over untied complete samples
+    uint64_t Af;   // per lane: sum of R_a * R_b over the other complete samples
+    uint64_t d3B;  // per lane: sum of t^3 - t over b's tie runs
+    uint64_t Au;   // wave-uniform: deferred tie runs of b
+};
+
+constexpr int WALK_U = 4;  // chunks of 64 positions per group; rows are padded to 64 * WALK_U
+
+// One chunk of 64 positions of b's sorted order without tied b-positions.
+// b's C1 = carry1 + (complete samples at lower lanes) by mbcnt; a's C1 from
+// the partner table, 0 for missing or tied a-positions (both map to the
+// table's zero entry), whose products are added separately.
+template <bool TA, bool DBG>
+__device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, const uint2* tab, uint32_t XS,
+                                                  const uint32_t* __restrict__ runsA, uint32_t& carry1,
+                                                  uint32_t& t32, uint64_t& sAf, int32_t* dbg_ra, int32_t* dbg_rb)
+{
+    const bool kept = pv != 0xFFFFu;
+    const uint64_t mask = __ballot(kept);
+    const uint32_t ca1 = cnt1(tab, min(pv, XS));
+    const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, carry1));
+    t32 += __umul24(ca1, cb1);
+    bool tied = false;
+    if constexpr (TA) {
+        tied = kept && (pv & POS_TIED);
+        if (tied) sAf += (uint64_t)ra_tied(tab, runsA, pv & POS_MASK) * (2u * cb1);
+    }
+    if constexpr (DBG) {
+        if (kept) {
+            dbg_ra[iv] = (int32_t)(tied ? ra_tied(tab, runsA, pv & POS_MASK) : 2u * ca1);
+            dbg_rb[iv] = (int32_t)(2u * cb1);
+        }
+    }
+    carry1 += (uint32_t)__popcll(mask);
+}
+
 // Walk of partner b's sorted order for the pair (a, b).  The complete
-// samples are those with an a-position; b's count of complete samples below
-// each position comes from ballot + mbcnt, a's from the partner bitmap KAj /
-// prefix PAj by popcount.  Doubled rank of a tied sample: C(start) + C(end) + 1
-// over its tie run.  On the a side a tied position (flag bit of its stored
-// position) looks its run up.  On the b side a chunk of 64 positions with ties
-// (bit word tbB[c] != 0) resolves the runs inside the chunk from its ballot
-// mask; the one run that may continue into the next chunk is carried as
-// wave-uniform state (its start count, plus per lane the a-ranks of its
-// complete samples so far) and settled where it ends.  Groups of U chunks
-// without any tie take a branch-free path.
-template <bool TA, bool TB>
+// samples are those with an a-position.  With C1 = 1 + (complete samples at
+// earlier positions), an untied complete sample has doubled ranks 2 C1 on
+// each side; the products C1_a C1_b of four chunks are summed in 32 bits
+// (each is below 2^30) before entering a 64-bit sum.  Tied a-positions (flag
+// bit in the stored position) are added with their run's average rank.  A
+// chunk holding tied b-positions (tbB bit word nonzero) resolves the runs
+// inside it from its ballot mask; the one run that may continue into the
+// next chunk is carried as wave-uniform state (its start count, plus per
+// lane the a-ranks of its complete samples so far) and settled where it
+// ends, and the lane at each run's last position records t^3 - t for it.
+template <bool TA, bool TB, bool DBG>
 __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
                                           const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ runsA,
-                                          int nbv, int na, const uint16_t* posA, const uint64_t* KAj,
-                                          const uint16_t* PAj, int lane, bool dbg, int32_t* dbg_ra,
-                                          int32_t* dbg_rb, WalkSums& ws)
+                                          int nbv, const uint16_t* posA, const uint2* tab, uint32_t XS, int lane,
+                                          int32_t* dbg_ra, int32_t* dbg_rb, WalkSums& ws)
 {
-    auto cnt_a = [&](uint32_t x) -> uint32_t {
-        const uint64_t m = KAj[x >> 6];
-        return (uint32_t)PAj[x >> 6] + (uint32_t)__popcll(m & ((1ull << (x & 63)) - 1ull));
-    };
+    constexpr int U = WALK_U;
     const int ncb = (nbv + 63) >> 6;
-    uint32_t carry = 0;
-    uint64_t sA = 0, sBa = 0, sBb = 0;
-    uint64_t uA = 0, uBb = 0;            // wave-uniform
-    uint32_t open_cs = 0, pend_t = 0;
-    uint32_t pend_lane = 0;  // per lane: a-ranks of deferred samples of the open run
+    const int ngrp = (ncb + U - 1) / U;
+    uint32_t carry1 = 1;  // wave-uniform
+    uint64_t sA4 = 0, sAf = 0, d3B = 0, uA = 0;
+    uint32_t open_cs = 0, pend_lane = 0;
     bool open = false;
-    constexpr int U = 4;
-    for (int c0 = 0; c0 < ncb; c0 += U) {
-        // all loads of the group are issued before any use: b's sorted order
-        // (global, coalesced), stored a-positions (LDS gather), a-side counts
-        // (LDS); positions past b's observed count hold a dummy sample whose
-        // a-position is "missing", and the rows are padded, so no bounds tests
-        uint32_t iv[U], pv[U], ra[U];
+    uint32_t ivn[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) iv[u] = ordB[(c0 + u) * 64 + lane];
+    for (int u = 0; u < U; ++u) ivn[u] = ngrp > 0 ? ordB[u * 64 + lane] : 0u;
+    for (int g = 0; g < ngrp; ++g) {
+        const int c0 = g * U;
+        uint32_t iv[U], pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) iv[u] = ivn[u];
+        // prefetch the next group's sample indices (rows are padded, so a
+        // whole group is always inside the row)
+        if (g + 1 < ngrp) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) ivn[u] = ordB[(c0 + U + u) * 64 + lane];
+        }
         bool dirty = false;
         uint64_t tbw[U];
         if constexpr (TB) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                tbw[u] = (c0 + u < ncb) ? tbB[c0 + u] : 0ull;
+                tbw[u] = tbB[c0 + u];
                 dirty |= tbw[u] != 0ull;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) pv[u] = posA[iv[u]];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t v = pv[u];
-            const uint32_t p = v != 0xFFFFu ? (v & POS_MASK) : (uint32_t)na;
-            ra[u] = 2u * cnt_a(p) + 2u;
-        }
-        if constexpr (TA) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t v = pv[u];
-                if (v != 0xFFFFu && (v & POS_TIED)) {
-                    const uint32_t rr = runsA[v & POS_MASK];
-                    ra[u] = cnt_a(rr & 0xFFFFu) + cnt_a(rr >> 16) + 1u;
-                }
-            }
-        }
+        uint32_t t32 = 0;
         if (!dirty) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (c0 + u >= ncb) break;
-                const bool kept = pv[u] != 0xFFFFu;
-                const uint64_t mask = __ballot(kept);
-                const uint32_t Rb = 2u * (carry + mbcnt64(mask)) + 2u;
-                carry += (uint32_t)__popcll(mask);
-                const uint32_t Ra = ra[u];
-                sA += kept ? __umul24(Ra, Rb) : 0u;
-                if constexpr (TA) sBa += kept ? __umul24(Ra, Ra) : 0u;
-                if constexpr (TB) sBb += kept ? __umul24(Rb, Rb) : 0u;
-                if (dbg && kept) {
-                    dbg_ra[iv[u]] = (int32_t)Ra;
-                    dbg_rb[iv[u]] = (int32_t)Rb;
-                }
-            }
+            for (int u = 0; u < U; ++u)
+                walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, runsA, carry1, t32, sAf, dbg_ra, dbg_rb);
+            sA4 += t32;
             continue;
         }
         if constexpr (TB) {
@@ -565,125 +607,191 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                if (tbw[u] == 0ull) {
+                    // no tied b-position here, and no run crosses into this chunk
+                    walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, runsA, carry1, t32, sAf, dbg_ra, dbg_rb);
+                    continue;
+                }
                 const int c = c0 + u;
-                if (c >= ncb) break;
+                const uint32_t k = (uint32_t)(c * 64 + lane);
                 const bool kept = pv[u] != 0xFFFFu;
                 const uint64_t mask = __ballot(kept);
-                const uint32_t Ra = ra[u];
-                uint32_t Rb = 2u * (carry + mbcnt64(mask)) + 2u;
-                bool direct = kept;
-                if (tbw[u] != 0ull) {
-                    // a tie run can only cross into or out of a chunk that holds
-                    // tied positions
-                    const uint32_t lo = (uint32_t)c * 64u;
-                    const uint32_t rs = rb[u] & 0xFFFFu, re = rb[u] >> 16;
-                    const uint32_t cs = (rs >= lo) ? carry + (uint32_t)__popcll(bits_below(mask, rs - lo)) : open_cs;
-                    const bool ends = re <= lo + 64u;
-                    const uint32_t ce = carry + (uint32_t)__popcll(bits_below(mask, ends ? re - lo : 64u));
-                    Rb = cs + ce + 1u;
-                    // settle the run carried in from earlier chunks (lane 0
-                    // belongs to it) if it ends here
-                    if (open) {
-                        const uint32_t e0 = __builtin_amdgcn_readlane(re, 0);
-                        if (e0 <= lo + 64u) {
-                            const uint32_t r_open = __builtin_amdgcn_readlane(Rb, 0);
-                            const uint32_t pend_sum = wave_sum_u32(pend_lane);
-                            uA += (uint64_t)r_open * pend_sum;
-                            uBb += (uint64_t)pend_t * r_open * r_open;
-                            if (dbg) {
-                                // test hook only: report the settled rank of every
-                                // complete sample of the run
-                                const uint32_t s0 = __builtin_amdgcn_readlane(rs, 0);
-                                for (uint32_t kk = s0 + (uint32_t)lane; kk < e0; kk += 64u) {
-                                    const uint32_t ii = ordB[kk];
-                                    if (posA[ii] != 0xFFFFu) dbg_rb[ii] = (int32_t)r_open;
-                                }
+                const uint32_t carry = carry1 - 1u;
+                uint32_t Ra = 2u * cnt1(tab, min(pv[u], XS));
+                if constexpr (TA) {
+                    if (kept && (pv[u] & POS_TIED)) Ra = ra_tied(tab, runsA, pv[u] & POS_MASK);
+                }
+                const uint32_t lo = (uint32_t)c * 64u;
+                const uint32_t rs = rb[u] & 0xFFFFu, re = rb[u] >> 16;
+                const uint32_t cs = (rs >= lo) ? carry + (uint32_t)__popcll(bits_below(mask, rs - lo)) : open_cs;
+                const bool ends = re <= lo + 64u;
+                const uint32_t ce = carry + (uint32_t)__popcll(bits_below(mask, ends ? re - lo : 64u));
+                const uint32_t Rb = cs + ce + 1u;
+                if (ends && k + 1u == re && re - rs > 1u) d3B += cube_minus(ce - cs);
+                // settle the run carried in from earlier chunks (lane 0
+                // belongs to it) if it ends here
+                if (open) {
+                    const uint32_t e0 = __builtin_amdgcn_readlane(re, 0);
+                    if (e0 <= lo + 64u) {
+                        const uint32_t r_open = __builtin_amdgcn_readlane(Rb, 0);
+                        uA += (uint64_t)r_open * wave_sum_u32(pend_lane);
+                        if constexpr (DBG) {
+                            // report the settled rank of every complete sample of the run
+                            const uint32_t s0 = __builtin_amdgcn_readlane(rs, 0);
+                            for (uint32_t kk = s0 + (uint32_t)lane; kk < e0; kk += 64u) {
+                                const uint32_t ii = ordB[kk];
+                                if (posA[ii] != 0xFFFFu) dbg_rb[ii] = (int32_t)r_open;
                             }
-                            pend_lane = 0;
-                            pend_t = 0;
-                            open = false;
                         }
+                        pend_lane = 0;
+                        open = false;
                     }
-                    const bool defer = kept && !ends;
-                    direct = kept && ends;
-                    const uint64_t dm = __ballot(defer);
-                    if (dm) {
-                        pend_lane += defer ? Ra : 0u;
-                        pend_t += (uint32_t)__popcll(dm);
+                }
+                const bool defer = kept && !ends;
+                const bool direct = kept && ends;
+                const uint64_t dm = __ballot(defer);
+                if (dm) {
+                    pend_lane += defer ? Ra : 0u;
+                    open = true;
+                    open_cs = __builtin_amdgcn_readlane(cs, 63);
+                } else if (!open) {
+                    // a run can also continue with no complete sample yet
+                    const uint32_t e63 = __builtin_amdgcn_readlane(re, 63);
+                    const bool v63 = (c * 64 + 63) < nbv;
+                    if (v63 && e63 > lo + 64u) {
                         open = true;
                         open_cs = __builtin_amdgcn_readlane(cs, 63);
-                    } else if (!open) {
-                        // a run can also continue with no complete sample yet
-                        const uint32_t e63 = __builtin_amdgcn_readlane(re, 63);
-                        const bool v63 = (c * 64 + 63) < nbv;
-                        if (v63 && e63 > lo + 64u) {
-                            open = true;
-                            open_cs = __builtin_amdgcn_readlane(cs, 63);
-                        }
                     }
                 }
-                carry += (uint32_t)__popcll(mask);
-                sA += direct ? __umul24(Ra, Rb) : 0u;
-                sBb += direct ? __umul24(Rb, Rb) : 0u;
-                if constexpr (TA) sBa += kept ? __umul24(Ra, Ra) : 0u;
-                if (dbg && kept) {
-                    dbg_ra[iv[u]] = (int32_t)Ra;
-                    if (direct) dbg_rb[iv[u]] = (int32_t)Rb;
+                carry1 += (uint32_t)__popcll(mask);
+                if (direct) sAf += (uint64_t)Ra * Rb;
+                if constexpr (DBG) {
+                    if (kept) {
+                        dbg_ra[iv[u]] = (int32_t)Ra;
+                        if (direct) dbg_rb[iv[u]] = (int32_t)Rb;
+                    }
                 }
             }
+            sA4 += t32;
         }
     }
-    ws.n = carry;
-    ws.A = sA;
-    ws.Ba = sBa;
-    ws.Bb = sBb;
-    ws.A_u = uA;
-    ws.Bb_u = uBb;
+    ws.n = carry1 - 1u;
+    ws.A4 = sA4;
+    ws.Af = sAf;
+    ws.d3B = d3B;
+    ws.Au = uA;
+}
+
+// LDS layout of the pair kernel for S samples and PB partners
+struct PairSmem {
+    size_t off_tab, off_corr, bytes;
+    int nwp;  // table entries per partner
+};
+
+__host__ __device__ inline PairSmem pair_smem(int64_t ld, int64_t S, int PB)
+{
+    PairSmem m;
+    m.nwp = (int)((S + 1 + 31) / 32) + 1;
+    m.off_tab = (size_t)round_up(ld * 2, 16);
+    m.off_corr = m.off_tab + (size_t)PB * m.nwp * 8;
+    m.bytes = m.off_corr + (size_t)PB * 8;
+    return m;
 }
 
 // One workgroup per (column a, block of PB partner columns), both in the
 // processing order perm (k_perm).  Step 1 builds, for all PB partners at
-// once, the bitmap "partner present" along a's sorted order (one
-// presence-word gather per position, one ballot per partner) and its per-64
-// prefix counts.  Step 2 walks each partner's sorted order once (pair_walk).
-template <int PB>
+// once, the partner table along a's sorted order (one presence-word gather
+// per position, one ballot per partner) and, when a has ties, the tie
+// defects of a's runs for every partner.  Step 2 walks each partner's sorted
+// order once (pair_walk).  DBG: one pair (dbg_a, dbg_b) of physical columns,
+// reporting the doubled ranks of every complete sample.
+// Work list of the pair kernel.  Rows la of the processing order come in
+// bands of 8 PB rows; band g holds partner blocks 8g .. nbp-1 (nbp = number of
+// partner blocks padded to a multiple of 8), which covers every block that
+// pairs with a row of the band (block q pairs with row la when q >= la / PB).
+// Each band's row length is a multiple of 8, so a workgroup index and its
+// partner block are congruent mod 8: a partner block always runs on the same
+// XCD (workgroups are dealt to the 8 XCDs round-robin) and its sorted orders
+// stay in that XCD's L2.
+__host__ __device__ inline int64_t pair_band_start(int64_t g, int64_t nbp, int PB)
+{
+    return 8 * (int64_t)PB * (g * nbp - 4 * g * (g - 1));
+}
+
+__host__ inline int64_t pair_grid_size(int64_t F, int64_t nbp, int PB)
+{
+    const int64_t rows = 8 * (int64_t)PB;
+    const int64_t G = ceil_div(F, rows);
+    return pair_band_start(G - 1, nbp, PB) + (F - rows * (G - 1)) * (nbp - 8 * (G - 1));
+}
+
+template <int PB, bool DBG>
 __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint32_t* __restrict__ pres,
-                                                                 int64_t S, int64_t F, PairOut po)
+                                                                 int64_t S, int64_t F, int64_t nbp, PairOut po)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool dbg = po.dbg_ra != nullptr;
-    // logical indices (processing order); dbg: one pair of physical columns
-    const int64_t la = dbg ? 0 : (int64_t)blockIdx.y;
-    const int64_t b0 = dbg ? 0 : (int64_t)blockIdx.x * PB;
-    if (!dbg && (la >= F || b0 >= F || b0 + PB - 1 < la)) return;
-    const int64_t a = dbg ? po.dbg_a : bs.perm[la];
+    // the wave index is the same in every lane: readfirstlane lets the
+    // compiler keep everything derived from it in scalar registers
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t la = 0, b0 = 0;
+    if constexpr (!DBG) {
+        const int64_t id = (int64_t)blockIdx.x;
+        // band g: pair_band_start(g) <= id < pair_band_start(g + 1)
+        const double A = (double)(nbp + 4);
+        const double disc = A * A - 16.0 * (double)id / (8.0 * PB);
+        int64_t g = (int64_t)((A - sqrt(disc > 0.0 ? disc : 0.0)) / 8.0);
+        if (g < 0) g = 0;
+        while (g > 0 && pair_band_start(g, nbp, PB) > id) --g;
+        while (pair_band_start(g + 1, nbp, PB) <= id && 8 * (g + 1) < nbp) ++g;
+        const int64_t r = id - pair_band_start(g, nbp, PB);
+        const int64_t len = nbp - 8 * g;
+        la = 8 * (int64_t)PB * g + r / len;
+        b0 = (8 * g + r % len) * PB;
+        if (la >= F || b0 >= F || b0 + PB - 1 < la) return;
+    }
+    const int64_t a = DBG ? po.dbg_a : bs.perm[la];
 
     const int64_t ld = bs.ld;
-    const int ncmax = (int)ceil_div(S, 64) + 1;
-    const size_t off_ka = (size_t)round_up(ld * 2, 16);
-    const size_t off_pa = off_ka + (size_t)PB * ncmax * 8;
+    const PairSmem L = pair_smem(ld, S, PB);
     uint16_t* posA = (uint16_t*)smem_raw;
-    uint64_t* KA = (uint64_t*)(smem_raw + off_ka);  // [PB][ncmax]
-    uint16_t* PA = (uint16_t*)(smem_raw + off_pa);  // [PB][ncmax]
+    uint2* tab = (uint2*)(smem_raw + L.off_tab);                    // [PB][nwp]
+    unsigned long long* corrA = (unsigned long long*)(smem_raw + L.off_corr);  // [PB]
 
     const int na = bs.ncol[a];
     const int tA = bs.hasties[a];
     const uint16_t* ordA = bs.ord + a * ld;
     const uint32_t* runsA = bs.runs + a * ld;
-    const int nca = (na + 63) >> 6;
+    const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
+    const int nc64 = (NW + 1) >> 1;
     {
-        const uint32_t* src = (const uint32_t*)(bs.pos + a * ld);
-        uint32_t* dst = (uint32_t*)posA;
-        for (int64_t w = threadIdx.x; w < ld / 2; w += PAIR_THREADS) dst[w] = src[w];
+        // rows are whole multiples of 512 bytes: 16-byte copies, every load
+        // of a thread issued before its stores
+        const uint4* src = (const uint4*)(bs.pos + a * ld);
+        uint4* dst = (uint4*)posA;
+        const int n16 = (int)(ld / 8);
+        constexpr int CU = 8;
+        for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
+            uint4 v[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
+                if (w < n16) v[u] = src[w];
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
+                if (w < n16) dst[w] = v[u];
+            }
+        }
     }
+    if (threadIdx.x < PB) corrA[threadIdx.x] = 0ull;
 
-    // ---- step 1: partner presence along a's order, PB partners at once -----
+    // ---- step 1: partner tables along a's order, PB partners at once --------
     const uint32_t* presw = pres + (b0 >> 5) * ld;
-    const int shift = (int)(b0 & 31);  // 0, or 16 when PB == 16
+    const int shift = (int)(b0 & 31);  // partner blocks are aligned to PB within a 32-column word
     const uint16_t* posDbg = bs.pos + (int64_t)po.dbg_b * ld;
-    constexpr int Q = 4;                // chunks per wave in flight
-    for (int cq = wave; cq <= nca; cq += PAIR_WAVES * Q) {
+    constexpr int Q = 16;  // chunks per wave in flight
+    for (int cq = wave; cq < nc64; cq += PAIR_WAVES * Q) {
         uint32_t idx[Q], word[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -692,7 +800,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            if (dbg)  // test hook: the single partner's presence, from its positions
+            if constexpr (DBG)  // the single partner's presence, from its positions
                 word[q] = (idx[q] != 0xFFFFFFFFu) ? (uint32_t)(posDbg[idx[q]] != 0xFFFF) : 0u;
             else
                 word[q] = (idx[q] != 0xFFFFFFFFu) ? (presw[idx[q]] >> shift) : 0u;
@@ -700,7 +808,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int c = cq + q * PAIR_WAVES;
-            if (c > nca) break;
+            if (c >= nc64) break;
             uint32_t lo = 0u, hi = 0u;
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
@@ -708,49 +816,76 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
                 lo = (lane == j) ? (uint32_t)m : lo;
                 hi = (lane == j) ? (uint32_t)(m >> 32) : hi;
             }
-            if (lane < PB) KA[(size_t)lane * ncmax + c] = ((uint64_t)hi << 32) | lo;
+            if (lane < PB) {
+                tab[(size_t)lane * L.nwp + 2 * c].x = lo;
+                if (2 * c + 1 < NW) tab[(size_t)lane * L.nwp + 2 * c + 1].x = hi;
+            }
         }
     }
     __syncthreads();
     for (int j = wave; j < PB; j += PAIR_WAVES) {
-        uint32_t run = 0;
-        for (int c0 = 0; c0 <= nca; c0 += 64) {
-            const int c = c0 + lane;
-            const uint32_t v = (c <= nca) ? (uint32_t)__popcll(KA[(size_t)j * ncmax + c]) : 0u;
+        uint2* tj = tab + (size_t)j * L.nwp;
+        uint32_t run = 1;
+        for (int w0 = 0; w0 < NW; w0 += 64) {
+            const int w = w0 + lane;
+            const uint32_t v = (w < NW) ? (uint32_t)__popc(tj[w].x) : 0u;
             const uint32_t incl = wave_incl_scan_u32(v);
-            if (c <= nca) PA[(size_t)j * ncmax + c] = (uint16_t)(run + incl - v);
+            if (w < NW) tj[w].y = run + incl - v;
             run += __shfl(incl, 63, 64);
         }
+        if (lane == 0) tj[NW] = make_uint2(0u, 0u);
     }
     __syncthreads();
+    if (tA) {
+        // tie defects of a's runs, per partner: a run [s, e) holds
+        // C(e) - C(s) complete samples; run starts come from the run-start bits
+        const int nj = DBG ? 1 : PB;
+        const uint64_t* rsA = bs.rsbits + a * (ld / 64);
+        const int nwords = (na + 63) >> 6;
+        for (int w = threadIdx.x; w < nwords; w += PAIR_THREADS) {
+            uint64_t m = rsA[w];
+            while (m) {
+                const uint32_t k = (uint32_t)w * 64u + (uint32_t)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const uint32_t rr = runsA[k];
+                const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
+                for (int j = 0; j < nj; ++j) {
+                    const uint2* tj = tab + (size_t)j * L.nwp;
+                    const uint32_t t = cnt1(tj, e) - cnt1(tj, s);
+                    if (t > 1u) atomicAdd(&corrA[j], (unsigned long long)cube_minus(t));
+                }
+            }
+        }
+        __syncthreads();
+    }
 
     // ---- step 2: one walk of each partner's sorted order ---------------------
-    for (int j = wave; j < (dbg ? 1 : PB); j += PAIR_WAVES) {
+    const uint32_t XS = 32u * (uint32_t)NW;
+    for (int j = wave; j < (DBG ? 1 : PB); j += PAIR_WAVES) {
         const int64_t lb = b0 + j;
-        if (!dbg && (lb >= F || lb < la)) continue;
-        const int64_t b = dbg ? po.dbg_b : bs.perm[lb];
+        if (!DBG && (lb >= F || lb < la)) continue;
+        const int64_t b = DBG ? po.dbg_b : bs.perm[lb];
         const int nbv = bs.ncol[b];
         const int tB = bs.hasties[b];
         const uint16_t* ordB = bs.ord + b * ld;
         const uint32_t* runsB = bs.runs + b * ld;
         const uint64_t* tbB = bs.tbits + b * (ld / 64);
-        const uint64_t* KAj = KA + (size_t)j * ncmax;
-        const uint16_t* PAj = PA + (size_t)j * ncmax;
+        const uint2* tj = tab + (size_t)j * L.nwp;
         WalkSums w;
         if (tA) {
-            if (tB) pair_walk<true, true>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
-            else pair_walk<true, false>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            if (tB) pair_walk<true, true, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
+            else pair_walk<true, false, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
         } else {
-            if (tB) pair_walk<false, true>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
-            else pair_walk<false, false>(ordB, runsB, tbB, runsA, nbv, na, posA, KAj, PAj, lane, dbg, po.dbg_ra, po.dbg_rb, w);
+            if (tB) pair_walk<false, true, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
+            else pair_walk<false, false, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
         }
-        const uint64_t sA = wave_sum_u64(w.A) + w.A_u;
-        const uint64_t sBa = tA ? wave_sum_u64(w.Ba) : 0ull;
-        const uint64_t sBb = tB ? wave_sum_u64(w.Bb) + w.Bb_u : 0ull;
-        if (lane == 0 && !dbg) {
+        const uint64_t sA = 4ull * wave_sum_u64(w.A4) + wave_sum_u64(w.Af) + w.Au;
+        const uint64_t d3B = tB ? wave_sum_u64(w.d3B) : 0ull;
+        if (lane == 0 && !DBG) {
             const int64_t nn = (int64_t)w.n;
-            const double Ba = tA ? (double)sBa : (double)sum_sq_doubled_untied(nn);
-            const double Bb = tB ? (double)sBb : (double)sum_sq_doubled_untied(nn);
+            const int64_t closed = sum_sq_doubled_untied(nn);
+            const double Ba = (double)(closed - (int64_t)((tA ? corrA[j] : 0ull) / 3u));
+            const double Bb = (double)(closed - (int64_t)(d3B / 3u));
             const int64_t g = a < b ? a : b, h = a < b ? b : a;
             const int64_t pid = pair_index(g, h, F);
             po.sums[pid] = make_double4((double)nn, (double)sA, Ba, Bb);
@@ -882,40 +1017,30 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static int pair_block(int64_t S) { (void)S; return 16; }
+// partners per workgroup, one per wave: 8 keeps a workgroup's LDS (a's
+// positions plus 8 partner tables) near 40 KB, so four workgroups (32 waves)
+// share a CU
+constexpr int PAIR_PB = 8;
+static_assert(PAIR_PB * 64 == PAIR_THREADS, "one partner per wave");
 
-static size_t pair_smem_bytes(int64_t S, int PB)
-{
-    const int64_t ld = spear_ld(S);
-    const int64_t ncmax = ceil_div(S, 64) + 1;
-    size_t off = (size_t)round_up(ld * 2, 16);
-    off += (size_t)PB * ncmax * 8;  // KA
-    off += (size_t)PB * ncmax * 2;  // PA
-    return (size_t)round_up((int64_t)off, 16);
-}
-
-template <int PB>
+template <bool DBG>
 static int pairs_launch_t(const SpearBase& bs, const uint32_t* pres, int64_t S, int64_t F, PairOut po,
                           hipStream_t st)
 {
-    const size_t smem = pair_smem_bytes(S, PB);
+    const size_t smem = pair_smem(bs.ld, S, PAIR_PB).bytes;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_spearman_pairs<PB>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_spearman_pairs<PAIR_PB, DBG>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_spearman_pairs)");
         attr_set = true;
     }
-    dim3 grid;
-    if (po.dbg_ra) {
-        grid = dim3(1, 1);
-    } else {
-        // the partner-block count is padded to a multiple of 8 so that a
-        // partner block always lands on the same XCD (blocks are dealt to the
-        // XCDs round-robin), keeping its sorted orders in that XCD's L2
-        grid = dim3((unsigned)round_up(ceil_div(F, PB), 8), (unsigned)F);
-    }
-    hipLaunchKernelGGL(k_spearman_pairs<PB>, grid, dim3(PAIR_THREADS), smem, st, bs, pres, S, F, po);
+    if (smem > 160 * 1024) return NAPY_E_UNSUPPORTED;
+    const int64_t nbp = round_up(ceil_div(F, PAIR_PB), 8);
+    const int64_t nblk = DBG ? 1 : pair_grid_size(F, nbp, PAIR_PB);
+    if (nblk > 0x7FFFFFFFLL) return NAPY_E_UNSUPPORTED;
+    hipLaunchKernelGGL((k_spearman_pairs<PAIR_PB, DBG>), dim3((unsigned)nblk), dim3(PAIR_THREADS), smem, st, bs,
+                       pres, S, F, nbp, po);
     return check_launch("spearman_pairs");
 }
 
@@ -925,8 +1050,8 @@ static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t 
     hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)nw), dim3(256), 0, st, bs, S, F,
                        pres);
     NAPY_TRY(check_launch("presence"));
-    if (pair_block(S) == 32) return pairs_launch_t<32>(bs, pres, S, F, po, st);
-    return pairs_launch_t<16>(bs, pres, S, F, po, st);
+    if (po.dbg_ra) return pairs_launch_t<true>(bs, pres, S, F, po, st);
+    return pairs_launch_t<false>(bs, pres, S, F, po, st);
 }
 
 struct SpearWs {
