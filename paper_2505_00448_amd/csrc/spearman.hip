@@ -41,9 +41,12 @@
 
 namespace napy {
 
-constexpr int SORT_THREADS = 1024;
-constexpr int SORT_EPT = 24;  // elements per thread
-constexpr int SPEARMAN_MAX_S = SORT_THREADS * SORT_EPT;  // 24576
+constexpr int SORT_THREADS = 1024;  // subset compaction
+constexpr int SPEARMAN_MAX_S = 24576;
+// column sort: 512 threads (8 waves) and up to CS_EPT_MAX keys per thread
+constexpr int CS_THREADS = 512;
+constexpr int CS_WAVES = CS_THREADS / 64;
+constexpr int CS_EPT_MAX = SPEARMAN_MAX_S / CS_THREADS;  // 48
 
 struct SpearBase {
     uint16_t* ord;     // [F][ld]
@@ -113,57 +116,91 @@ __global__ __launch_bounds__(256) void k_sort_keys(const float* __restrict__ X, 
 // ---------------------------------------------------------------------------
 // per-column sort
 // ---------------------------------------------------------------------------
+// LDS of the column sort, sized by the samples per thread E: keys and
+// sample indices of CS_THREADS * E slots, then the small scan arrays
 struct SortSmem {
-    uint32_t key[SPEARMAN_MAX_S];
-    uint16_t idx[SPEARMAN_MAX_S];
-    uint32_t wtot[16][8];   // per-wave totals of the packed digit counts
-    uint32_t dbase[16];     // exclusive offset of each digit
-    int32_t red[16];
+    uint32_t* key;
+    uint16_t* idx;
+    uint32_t (*wtot)[8];  // [16][8] per-wave totals of the packed digit counts
+    uint32_t* dbase;      // [16] exclusive offset of each digit
+    int32_t* red;         // [16]
 };
 
-// 16 digit counters packed as 8-bit fields in four words.
-__device__ __forceinline__ uint32_t cnt_get(const uint32_t c[4], uint32_t d)
+__host__ __device__ inline size_t sort_smem_bytes(int E)
 {
-    const uint32_t w = (d >> 2) == 0 ? c[0] : (d >> 2) == 1 ? c[1] : (d >> 2) == 2 ? c[2] : c[3];
+    const size_t cap = (size_t)CS_THREADS * (size_t)E;
+    return round_up((int64_t)(cap * 6), 16) + 16 * 8 * 4 + 16 * 4 + 16 * 4;
+}
+
+__device__ inline SortSmem sort_smem(unsigned char* raw, int E)
+{
+    const size_t cap = (size_t)CS_THREADS * (size_t)E;
+    SortSmem m;
+    m.key = (uint32_t*)raw;
+    m.idx = (uint16_t*)(raw + cap * 4);
+    unsigned char* p = raw + round_up((int64_t)(cap * 6), 16);
+    m.wtot = (uint32_t(*)[8])p;
+    m.dbase = (uint32_t*)(p + 16 * 8 * 4);
+    m.red = (int32_t*)(p + 16 * 8 * 4 + 16 * 4);
+    return m;
+}
+
+// The digit counters and the packed prefix words are vector values, picked
+// by select trees over constant lanes: a local array read with a runtime
+// index would be placed in scratch memory.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+// 16 digit counters packed as 8-bit fields in four words.
+__device__ __forceinline__ uint32_t cnt_get(u32x4 c, uint32_t d)
+{
+    const uint32_t q = d >> 2;
+    const uint32_t lo = (q & 1) ? c.y : c.x;
+    const uint32_t hi = (q & 1) ? c.w : c.z;
+    const uint32_t w = (q & 2) ? hi : lo;
     return (w >> (8 * (d & 3))) & 0xFFu;
 }
-__device__ __forceinline__ void cnt_inc(uint32_t c[4], uint32_t d)
+__device__ __forceinline__ void cnt_inc(u32x4& c, uint32_t d)
 {
     const uint32_t inc = 1u << (8 * (d & 3));
     const uint32_t q = d >> 2;
-    c[0] += q == 0 ? inc : 0u;
-    c[1] += q == 1 ? inc : 0u;
-    c[2] += q == 2 ? inc : 0u;
-    c[3] += q == 3 ? inc : 0u;
+    c.x += q == 0 ? inc : 0u;
+    c.y += q == 1 ? inc : 0u;
+    c.z += q == 2 ? inc : 0u;
+    c.w += q == 3 ? inc : 0u;
 }
 
-__device__ __forceinline__ uint32_t sel8(const uint32_t w[8], uint32_t q)
+__device__ __forceinline__ uint32_t sel8(u32x8 w, uint32_t q)
 {
-    const uint32_t a = (q & 1) ? w[1] : w[0];
-    const uint32_t b = (q & 1) ? w[3] : w[2];
-    const uint32_t c = (q & 1) ? w[5] : w[4];
-    const uint32_t d = (q & 1) ? w[7] : w[6];
+    const uint32_t a = (q & 1) ? w.s1 : w.s0;
+    const uint32_t b = (q & 1) ? w.s3 : w.s2;
+    const uint32_t c = (q & 1) ? w.s5 : w.s4;
+    const uint32_t d = (q & 1) ? w.s7 : w.s6;
     const uint32_t ab = (q & 2) ? b : a;
     const uint32_t cd = (q & 2) ? d : c;
     return (q & 4) ? cd : ab;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __restrict__ keys, int64_t S,
+// EPT elements per thread (CS_THREADS * EPT >= S); slots past S hold the
+// "missing" key and sort last
+template <int EPT>
+__global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restrict__ keys, int64_t S,
                                                           int64_t ld, SpearBase out)
 {
-    __shared__ SortSmem sm;
+    extern __shared__ __attribute__((aligned(16))) unsigned char sort_raw[];
     const int col = blockIdx.x;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int E = (int)ceil_div(S, SORT_THREADS);  // <= SORT_EPT
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    constexpr int E = EPT;
+    const SortSmem sm = sort_smem(sort_raw, E);
     const uint32_t* kc = keys + (int64_t)col * ld;
 
-    uint32_t key[SORT_EPT];
-    uint16_t idx[SORT_EPT];
+    uint32_t key[EPT];
+    uint16_t idx[EPT];
     int present = 0;
 #pragma unroll
-    for (int e = 0; e < SORT_EPT; ++e) {
+    for (int e = 0; e < EPT; ++e) {
         if (e < E) {
-            const int64_t j = (int64_t)e * SORT_THREADS + t;  // striped load, coalesced
+            const int64_t j = (int64_t)e * CS_THREADS + t;  // striped load, coalesced
             key[e] = j < S ? kc[j] : 0xFFFFFFFFu;
             idx[e] = (uint16_t)(j < S ? j : 0xFFFF);
             present += key[e] != 0xFFFFFFFFu;
@@ -179,17 +216,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
     __syncthreads();
     int ncount = 0;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) ncount += sm.red[w];
+    for (int w = 0; w < CS_WAVES; ++w) ncount += sm.red[w];
 
     // The initial order is arbitrary (order among equal keys does not affect
     // average ranks); each pass below is stable with respect to the sequence
     // in which thread t holds positions t*E .. t*E+E-1.
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 4 * pass;
-        uint32_t c[4] = {0u, 0u, 0u, 0u};
-        uint8_t lr[SORT_EPT];
+        u32x4 c = {0u, 0u, 0u, 0u};
+        uint8_t lr[EPT];
 #pragma unroll
-        for (int e = 0; e < SORT_EPT; ++e) {
+        for (int e = 0; e < EPT; ++e) {
             if (e < E) {
                 const uint32_t d = (key[e] >> shift) & 15u;
                 lr[e] = (uint8_t)cnt_get(c, d);
@@ -215,7 +252,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
         if (t < 16) {
             // digit totals -> exclusive digit bases
             uint32_t tot = 0;
-            for (int ww = 0; ww < 16; ++ww) tot += (sm.wtot[ww][t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+            for (int ww = 0; ww < CS_WAVES; ++ww) tot += (sm.wtot[ww][t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
             sm.red[t] = (int32_t)tot;
         }
         __syncthreads();
@@ -226,7 +263,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
                 run += (uint32_t)sm.red[d];
             }
         }
-        uint32_t wpre[8];
+        u32x8 wpre;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             uint32_t s = 0;
@@ -235,7 +272,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < SORT_EPT; ++e) {
+        for (int e = 0; e < EPT; ++e) {
             if (e < E) {
                 const uint32_t d = (key[e] >> shift) & 15u;
                 const uint32_t pw = sel8(wpre, d >> 1);
@@ -247,7 +284,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < SORT_EPT; ++e) {
+        for (int e = 0; e < EPT; ++e) {
             if (e < E) {
                 key[e] = sm.key[t * E + e];
                 idx[e] = sm.idx[t * E + e];
@@ -263,9 +300,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
     // run starts: s(k) = max{j <= k : j == 0 or key[j] != key[j-1]}; the
     // sorted keys are still in sm.key
     int last = -1;
-    int rs[SORT_EPT];
+    int rs[EPT];
 #pragma unroll
-    for (int e = 0; e < SORT_EPT; ++e) {
+    for (int e = 0; e < EPT; ++e) {
         if (e < E) {
             const int k = t * E + e;
             const bool start = (k == 0) || (k < ncount && key[e] != sm.key[k - 1]);
@@ -289,7 +326,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
     if (lane == 0) excl = -1;
     before = max(before, excl);
 #pragma unroll
-    for (int e = 0; e < SORT_EPT; ++e)
+    for (int e = 0; e < EPT; ++e)
         if (e < E && rs[e] < 0) rs[e] = before;
     __syncthreads();
     uint32_t* END = sm.key;  // reused: END[run start] = run end
@@ -300,9 +337,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
     __syncthreads();
     if (lane == 0) sm.red[wave] = rs[0];
     __syncthreads();
-    if (lane == 63) rs_next_first = (wave + 1 < 16) ? sm.red[wave + 1] : -2;
+    if (lane == 63) rs_next_first = (wave + 1 < CS_WAVES) ? sm.red[wave + 1] : -2;
 #pragma unroll
-    for (int e = 0; e < SORT_EPT; ++e) {
+    for (int e = 0; e < EPT; ++e) {
         if (e < E) {
             const int k = t * E + e;
             if (k < ncount) {
@@ -316,7 +353,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < SORT_EPT; ++e) {
+    for (int e = 0; e < EPT; ++e) {
         if (e < E) {
             const int k = t * E + e;
             if (k < ncount) {
@@ -332,10 +369,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_colsort(const uint32_t* __rest
     }
     // padding: sorted positions past the observed count hold the dummy
     // sample S, whose position is "missing"
-    for (int64_t k = ncount + t; k < ld; k += SORT_THREADS) ordc[k] = (uint16_t)S;
-    for (int64_t i = S + t; i < ld; i += SORT_THREADS) posc[i] = 0xFFFF;
+    for (int64_t k = ncount + t; k < ld; k += CS_THREADS) ordc[k] = (uint16_t)S;
+    for (int64_t i = S + t; i < ld; i += CS_THREADS) posc[i] = 0xFFFF;
     if (col == (int)gridDim.x - 1)
-        for (int64_t k = t; k < ORD_TAIL; k += SORT_THREADS) ordc[ld + k] = (uint16_t)S;
+        for (int64_t k = t; k < ORD_TAIL; k += CS_THREADS) ordc[ld + k] = (uint16_t)S;
     const int anytie = __syncthreads_or(tie_here ? 1 : 0);
     if (t == 0) {
         out.ncol[col] = ncount;
@@ -406,17 +443,32 @@ __device__ __forceinline__ uint32_t perm_key(const SpearBase& bs, int64_t c)
     return ((dense ? 0u : 1u) << 20) | (uint32_t)(65535 - n);
 }
 
+// rank of each column's key (ties by column index): 64 columns per
+// workgroup, four threads per column over the other keys, staged in LDS
 __global__ __launch_bounds__(256) void k_perm(SpearBase bs, int64_t F)
 {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= F) return;
-    const uint32_t kc = perm_key(bs, c);
-    int64_t rank = 0;
-    for (int64_t d = 0; d < F; ++d) {
-        const uint32_t kd = perm_key(bs, d);
-        rank += (kd < kc) || (kd == kc && d < c);
+    __shared__ uint32_t kd_s[1024];
+    __shared__ uint32_t part[4][64];
+    const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+    const uint32_t kc = c < F ? perm_key(bs, c) : 0u;
+    uint32_t rank = 0;
+    for (int64_t d0 = 0; d0 < F; d0 += 1024) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 1024; i += 256) {
+            const int64_t d = d0 + i;
+            kd_s[i] = d < F ? perm_key(bs, d) : 0u;
+        }
+        __syncthreads();
+        const int nd = (int)min((int64_t)1024, F - d0);
+        for (int i = q; i < nd; i += 4) {
+            const uint32_t kd = kd_s[i];
+            rank += (kd < kc) || (kd == kc && d0 + i < c);
+        }
     }
-    bs.perm[rank] = (int32_t)c;
+    part[q][cl] = rank;
+    __syncthreads();
+    if (q == 0 && c < F) bs.perm[part[0][cl] + part[1][cl] + part[2][cl] + part[3][cl]] = (int32_t)c;
 }
 
 static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
@@ -425,7 +477,7 @@ static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
     NAPY_TRY(check_launch("fill"));
     hipLaunchKernelGGL(k_tiebits, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)F), dim3(256), 0, st, bs);
     NAPY_TRY(check_launch("tiebits"));
-    hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, bs, F);
+    hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 64)), dim3(256), 0, st, bs, F);
     return check_launch("perm");
 }
 
@@ -771,11 +823,13 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         const int n16 = (int)(ld / 8);
         constexpr int CU = 8;
         for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
+            // loads from a clamped index (always inside the row) keep v in
+            // registers; only the stores are predicated
             uint4 v[CU];
 #pragma unroll
             for (int u = 0; u < CU; ++u) {
                 const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
-                if (w < n16) v[u] = src[w];
+                v[u] = src[w < n16 ? w : n16 - 1];
             }
 #pragma unroll
             for (int u = 0; u < CU; ++u) {
@@ -1073,14 +1127,34 @@ static void spear_carve(Carver& c, int64_t S, int64_t F, SpearWs& w)
     w.ab = c.take<int2>(npairs);
 }
 
+template <int EPT>
+static int colsort_launch(const uint32_t* keys, int64_t S, int64_t F, const SpearBase& base, hipStream_t st)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_colsort<EPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sort_smem_bytes(EPT));
+        if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_colsort)");
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_colsort<EPT>, dim3((unsigned)F), dim3(CS_THREADS), sort_smem_bytes(EPT), st, keys, S,
+                       base.ld, base);
+    return check_launch("colsort");
+}
+
 static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us, float sv,
                        uint32_t* keys, const SpearBase& base, hipStream_t st)
 {
     dim3 gk((unsigned)ceil_div(F, 64), (unsigned)ceil_div(base.ld, 64));
     hipLaunchKernelGGL(k_sort_keys, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
     NAPY_TRY(check_launch("sort_keys"));
-    hipLaunchKernelGGL(k_colsort, dim3((unsigned)F), dim3(SORT_THREADS), 0, st, keys, S, base.ld, base);
-    NAPY_TRY(check_launch("colsort"));
+    const int64_t E = ceil_div(S, CS_THREADS);
+    if (E <= 8) NAPY_TRY(colsort_launch<8>(keys, S, F, base, st));
+    else if (E <= 16) NAPY_TRY(colsort_launch<16>(keys, S, F, base, st));
+    else if (E <= 20) NAPY_TRY(colsort_launch<20>(keys, S, F, base, st));
+    else if (E <= 24) NAPY_TRY(colsort_launch<24>(keys, S, F, base, st));
+    else if (E <= 32) NAPY_TRY(colsort_launch<32>(keys, S, F, base, st));
+    else NAPY_TRY(colsort_launch<CS_EPT_MAX>(keys, S, F, base, st));
     return tiebits_launch(base, F, st);
 }
 
