@@ -566,6 +566,208 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
 }
 
 // ---------------------------------------------------------------------------
+// K2, split-BF16 form.  One 64 x 64 output tile over one range of samples,
+// 256 threads (four waves, each a 32 x 32 block), slabs of 16 samples = one
+// v_mfma_f32_32x32x16_bf16 step, double-buffered in LDS (57 KB, two
+// workgroups per CU).  Nine FP32 accumulators stay in place across the loop:
+// n; Sx and Sy (all three pieces each); Sxx, Syy, Sxy as a main accumulator
+// for the leading piece products and a low one for the trailing ones (the
+// matrix cores add each block into the accumulator with one rounding toward
+// zero, so tiny trailing products are kept away from the large leading
+// sums).  Every 1024 samples the Sxx, Syy and Sxy accumulators are added into
+// the workgroup's FP64 partial sums in the workspace and cleared; the sums
+// of centred values Sx, Sy stay small and are written once at the end.
+// ---------------------------------------------------------------------------
+namespace bf3 {
+constexpr int BK = 16;
+constexpr int NPL = 7;                  // xh, xm, xl, qh, qm, ql, m
+constexpr int PLANE = TILE * BK;        // bf16 per plane
+constexpr int BUF = 2 * NPL * PLANE;    // one slab, both sides
+constexpr int FLUSH_SLABS = 1024 / BK;
+}  // namespace bf3
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 2) void k_pearson_bf16(
+    const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+    const float* __restrict__ mu32, int T, int ntiles, int nsplit, int64_t ksplit, double* __restrict__ part)
+{
+    using namespace bf3;
+    const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
+    const int t = lb / nsplit, split = lb % nsplit;
+    int tg, th;
+    tile_coords(t, T, tg, th);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t kbeg = (int64_t)split * ksplit;
+    int64_t kend = kbeg + ksplit;
+    if (kend > S) kend = S;
+    const int nslab = kend > kbeg ? (int)ceil_div(kend - kbeg, BK) : 0;
+
+    // staging: column sc of both panels, samples 4 kq .. 4 kq + 3 of the slab
+    const int sc = tid & 63, kq = tid >> 6;
+    const int64_t colG = (int64_t)tg * TILE + sc, colH = (int64_t)th * TILE + sc;
+    const bool okG = colG < F, okH = colH < F;
+    const float muG = okG ? mu32[colG] : 0.0f, muH = okH ? mu32[colH] : 0.0f;
+
+    __shared__ __attribute__((aligned(16))) __bf16 lds[2 * BUF];
+    float rawG[4], rawH[4];
+    auto load_raw = [&](int slab) {
+        const int64_t i0 = kbeg + (int64_t)slab * BK + kq * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j;
+            const bool in = i < kend;
+            rawG[j] = (in && okG) ? X[i * ldx + colG] : __builtin_nanf("");
+            rawH[j] = (in && okH) ? X[i * ldx + colH] : __builtin_nanf("");
+        }
+    };
+    auto store_lds = [&](int buf) {
+        __bf16* base = lds + buf * BUF;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            bf16x4 pl[NPL];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float raw = side ? rawH[j] : rawG[j];
+                const bool miss = is_missing(raw, use_sent, sent);
+                const float x = miss ? 0.0f : raw - (side ? muH : muG);
+                // x = xh + xm + xl and q = qh + qm + ql exactly
+                const __bf16 xh = to_bf16(x);
+                const float x1 = x - from_bf16(xh);
+                const __bf16 xm = to_bf16(x1);
+                const __bf16 xl = to_bf16(x1 - from_bf16(xm));
+                const float q = x * x;
+                const __bf16 qh = to_bf16(q);
+                const float q1 = q - from_bf16(qh);
+                const __bf16 qm = to_bf16(q1);
+                const __bf16 ql = to_bf16(q1 - from_bf16(qm));
+                pl[0][j] = xh;
+                pl[1][j] = xm;
+                pl[2][j] = xl;
+                pl[3][j] = qh;
+                pl[4][j] = qm;
+                pl[5][j] = ql;
+                pl[6][j] = miss ? to_bf16(0.0f) : to_bf16(1.0f);
+            }
+#pragma unroll
+            for (int pp = 0; pp < NPL; ++pp)
+                *(bf16x4*)(base + ((side * NPL + pp) * TILE + sc) * BK + kq * 4) = pl[pp];
+        }
+    };
+
+    f32x16 aN, aSx, aSy, aSxx, aSxxL, aSyy, aSyyL, aSxy, aSxyL;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        aN[r] = 0.f; aSx[r] = 0.f; aSy[r] = 0.f;
+        aSxx[r] = 0.f; aSxxL[r] = 0.f; aSyy[r] = 0.f; aSyyL[r] = 0.f; aSxy[r] = 0.f; aSxyL[r] = 0.f;
+    }
+    auto compute = [&](int buf) {
+        const __bf16* base = lds + buf * BUF;
+        const int rr = lane & 31, kk = (lane >> 5) * 8;
+        // all seven planes of the G side; the H side's planes one at a time
+        bf16x8 a[NPL];
+#pragma unroll
+        for (int pp = 0; pp < NPL; ++pp)
+            a[pp] = *(const bf16x8*)(base + ((0 * NPL + pp) * TILE + wm * 32 + rr) * BK + kk);
+        auto bpl = [&](int pp) -> bf16x8 {
+            return *(const bf16x8*)(base + ((1 * NPL + pp) * TILE + wn * 32 + rr) * BK + kk);
+        };
+        // planes: 0 xh, 1 xm, 2 xl, 3 qh, 4 qm, 5 ql, 6 m
+#define NAPY_MF(acc, x, y) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0)
+        {
+            const bf16x8 b = bpl(6);
+            NAPY_MF(aN, a[6], b);
+            NAPY_MF(aSx, a[0], b);
+            NAPY_MF(aSxx, a[3], b);
+            NAPY_MF(aSx, a[1], b);
+            NAPY_MF(aSxxL, a[4], b);
+            NAPY_MF(aSx, a[2], b);
+            NAPY_MF(aSxxL, a[5], b);
+        }
+        {
+            const bf16x8 b = bpl(0);
+            NAPY_MF(aSy, a[6], b);
+            NAPY_MF(aSxy, a[0], b);
+            NAPY_MF(aSxyL, a[1], b);
+            NAPY_MF(aSxyL, a[2], b);
+        }
+        {
+            const bf16x8 b = bpl(1);
+            NAPY_MF(aSy, a[6], b);
+            NAPY_MF(aSxyL, a[0], b);
+            NAPY_MF(aSxyL, a[1], b);
+        }
+        {
+            const bf16x8 b = bpl(2);
+            NAPY_MF(aSy, a[6], b);
+            NAPY_MF(aSxyL, a[0], b);
+        }
+        NAPY_MF(aSyy, a[6], bpl(3));
+        NAPY_MF(aSyyL, a[6], bpl(4));
+        NAPY_MF(aSyyL, a[6], bpl(5));
+#undef NAPY_MF
+    };
+
+    // output element of accumulator register r (32 x 32 block layout): the
+    // lane's base element plus a constant offset per register
+    const int ebase = (wm * 32 + 4 * (lane >> 5)) * TILE + wn * 32 + (lane & 31);
+    auto eoff = [](int r) -> int { return (8 * (r >> 2) + (r & 3)) * TILE; };
+    auto slice = [&](int s) -> double* {
+        return part + (((int64_t)split * NSTAT + s) * ntiles + t) * TILE_ELEMS + ebase;
+    };
+    bool flushed = false;
+    auto flush = [&]() {
+        double* d3 = slice(3);
+        double* d4 = slice(4);
+        double* d5 = slice(5);
+        // keep the addresses from being computed ahead of the loop (they
+        // would occupy registers for its whole length)
+        asm volatile("" : "+v"(d3), "+v"(d4), "+v"(d5));
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int e = eoff(r);
+            const double v3 = (double)aSxx[r] + (double)aSxxL[r];
+            const double v4 = (double)aSyy[r] + (double)aSyyL[r];
+            const double v5 = (double)aSxy[r] + (double)aSxyL[r];
+            d3[e] = flushed ? d3[e] + v3 : v3;
+            d4[e] = flushed ? d4[e] + v4 : v4;
+            d5[e] = flushed ? d5[e] + v5 : v5;
+            aSxx[r] = 0.f; aSxxL[r] = 0.f; aSyy[r] = 0.f; aSyyL[r] = 0.f; aSxy[r] = 0.f; aSxyL[r] = 0.f;
+        }
+        flushed = true;
+    };
+
+    // main loop: one barrier per slab; staging of slab s+1 overlaps the
+    // contractions of slab s
+    if (nslab > 0) {
+        load_raw(0);
+        store_lds(0);
+        __syncthreads();
+        for (int sl = 0; sl < nslab; ++sl) {
+            const bool more = sl + 1 < nslab;
+            if (more) load_raw(sl + 1);
+            compute(sl & 1);
+            if (more) store_lds((sl + 1) & 1);
+            if ((sl + 1) % FLUSH_SLABS == 0 && more) flush();
+            __syncthreads();
+        }
+    }
+    flush();
+    double* d0 = slice(0);
+    double* d1 = slice(1);
+    double* d2 = slice(2);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int e = eoff(r);
+        d0[e] = (double)aN[r];
+        d1[e] = (double)aSx[r];
+        d2[e] = (double)aSy[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // K3: combine split-K partials, r, p, n; both triangles
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pearson_combine(
@@ -638,6 +840,27 @@ static PearsonPlan pearson_plan(int64_t S, int64_t F, int prec)
     PearsonPlan pl;
     pl.T = (int)ceil_div(F, TILE);
     pl.ntiles = pl.T * (pl.T + 1) / 2;
+    if (prec == NAPY_PREC_BF16X3) {
+        // 512 workgroup slots (two per CU): the smallest number of full
+        // rounds of workgroups that is at least 90% occupied
+        const int64_t BK = bf3::BK;
+        int64_t want = 1;
+        if (pl.ntiles < 512) {
+            for (int64_t w = 1; w <= 4; ++w) {
+                want = (512 * w) / pl.ntiles;
+                if (want >= 1 && (double)(want * pl.ntiles) >= 0.9 * 512.0 * (double)w) break;
+            }
+        }
+        int64_t maxs = S / 512;
+        if (maxs < 1) maxs = 1;
+        if (want > maxs) want = maxs;
+        if (want < 1) want = 1;
+        pl.ksplit = round_up(ceil_div(S, want), BK);
+        if (pl.ksplit < BK) pl.ksplit = BK;
+        pl.nsplit = (int)ceil_div(S, pl.ksplit);
+        if (pl.nsplit < 1) pl.nsplit = 1;
+        return pl;
+    }
     const int BK = (prec == NAPY_PREC_FP64) ? 16 : 32;
     int64_t want = ceil_div(512, pl.ntiles);
     int64_t maxs = S / 512;
@@ -691,8 +914,8 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
                            cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
         break;
     case NAPY_PREC_BF16X3:
-        hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_BF16X3>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us,
-                           sv, cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
+        hipLaunchKernelGGL(k_pearson_bf16, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T,
+                           pl.ntiles, pl.nsplit, pl.ksplit, part);
         break;
     default:
         hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_FP64>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv,
