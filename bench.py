@@ -21,7 +21,8 @@ Two further forms print their own JSON line:
                     p over the whole matrix against the library's FP64 mode;
   --form serving    continuous-batching server on a resident 20,000 x 2,000
                     base with a Poisson query stream at 200 queries/s:
-                    p50/p99 latency and pairs/s.
+                    p50/p99 latency and pairs/s;
+  --form copy       a 256 MiB device copy, calibrating the HBM byte counters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form headline|precision|serving]
 """
@@ -49,6 +50,36 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9          # 32-bit lane operations per second
 HBM_PEAK_BPS = 8.0e12
 BF16_PEAK_FLOPS = 2.5e15
 FP32_MFMA_PEAK_FLOPS = 157.3e12
+
+# HBM bytes per launch of the Spearman scan kernel on the headline workload:
+# rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE (KiB per dispatch), each scaled
+# by what the same counter reads for a 256 MiB device copy (--form copy:
+# FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).  The
+# figures belong to one version of the kernel source: for any other version
+# the traffic is reported as unknown.
+SCAN_TRAFFIC = {
+    "source_sha256": "872a8cf9334bd2c7327d9c8762bfd0c5113029478445f8cec877aec72f80c6ae",
+    "fetch_kib": 161512.2,
+    "write_kib": 35006.3,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+
+
+def scan_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("spearman.hip", "napy_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2505_00448_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def scan_traffic_bytes():
+    t = SCAN_TRAFFIC
+    if t["source_sha256"] is None or t["source_sha256"] != scan_source_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 class HipEvents:
@@ -111,7 +142,7 @@ def main() -> int:
                     help="pairs in the oracle's timed sample (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--form", default="headline", choices=["headline", "precision", "serving"])
+    ap.add_argument("--form", default="headline", choices=["headline", "precision", "serving", "copy"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
     ap.add_argument("--warmup-queries", type=int, default=100, help="serving: warm-up queries")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -130,6 +161,8 @@ def main() -> int:
 
     if args.form == "serving":
         return run_serving(args)
+    if args.form == "copy":
+        return run_copy(args)
     if args.form == "precision":
         return run_precision(args)
 
@@ -272,7 +305,7 @@ def main() -> int:
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": None,
+            "traffic": scan_traffic_bytes(),
             "work": f"{rank_steps:.4g} rank-steps x 4 ops per launch",
         },
         "roofline_hbm_model": {
@@ -313,6 +346,20 @@ def main() -> int:
 def _pct(a, q):
     import numpy as np
     return float(np.percentile(a, q)) if len(a) else float("nan")
+
+
+def run_copy(args) -> int:
+    """Calibration for the HBM byte counters: a 256 MiB device-to-device copy,
+    three times."""
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"form": "copy", "bytes_per_copy": n * 4, "copies": 3}))
+    return 0
 
 
 def run_serving(args) -> int:
