@@ -22,6 +22,9 @@ Two further forms print their own JSON line:
   --form serving    continuous-batching server on a resident 20,000 x 2,000
                     base with a Poisson query stream at 200 queries/s:
                     p50/p99 latency and pairs/s;
+  --form differentiation  8,192 x 512 (15% MCAR): the forward that saves the
+                    six sums and the hand-written backward dL/dX for
+                    L = sum W o R, time and FP32-equivalent TFLOP/s of each;
   --form copy       a 256 MiB device copy, calibrating the HBM byte counters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form headline|precision|serving]
@@ -142,7 +145,8 @@ def main() -> int:
                     help="pairs in the oracle's timed sample (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--form", default="headline", choices=["headline", "precision", "serving", "copy"])
+    ap.add_argument("--form", default="headline",
+                    choices=["headline", "precision", "serving", "differentiation", "copy"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
     ap.add_argument("--warmup-queries", type=int, default=100, help="serving: warm-up queries")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -163,6 +167,8 @@ def main() -> int:
         return run_serving(args)
     if args.form == "copy":
         return run_copy(args)
+    if args.form == "differentiation":
+        return run_differentiation(args)
     if args.form == "precision":
         return run_precision(args)
 
@@ -346,6 +352,77 @@ def main() -> int:
 def _pct(a, q):
     import numpy as np
     return float(np.percentile(a, q)) if len(a) else float("nan")
+
+
+def run_differentiation(args) -> int:
+    """Forward (with the six saved sums) and backward of the masked-Pearson
+    matrix at 8,192 x 512."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_00448_amd import _lib
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    case = synth.cfg_differentiation()
+    X = case.X
+    S, F = X.shape
+    Xd = torch.from_numpy(X).to(dev)
+    dR = torch.from_numpy(case.W.astype(np.float32)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    hip = HipEvents()
+    e0, e1, e2 = hip.new(), hip.new(), hip.new()
+    hip.rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    out = {}
+    for prec in ("fp32", "bf16x3"):
+        opts = _lib.make_opts(prec)
+        wsf = torch.empty(lib.napy_pearson_workspace(S, F, ctypes.byref(opts)), dtype=torch.uint8, device=dev)
+        wsb = torch.empty(lib.napy_pearson_backward_workspace(S, F, ctypes.byref(opts)), dtype=torch.uint8,
+                          device=dev)
+        r = torch.empty((F, F), dtype=torch.float64, device=dev)
+        saved = torch.empty((6, F, F), dtype=torch.float64, device=dev)
+        dX = torch.empty((S, F), dtype=torch.float32, device=dev)
+
+        def step():
+            hip.rt.hipEventRecord(e0, sh)
+            st = lib.napy_pearson_fwd(P(Xd), S, F, F, P(r), None, None, F, P(saved), P(wsf), wsf.numel(),
+                                      ctypes.byref(opts), sh)
+            _lib.check(st, "napy_pearson_fwd")
+            hip.rt.hipEventRecord(e1, sh)
+            st = lib.napy_pearson_backward(P(Xd), S, F, F, P(saved), P(dR), F, P(dX), F, P(wsb), wsb.numel(),
+                                           ctypes.byref(opts), sh)
+            _lib.check(st, "napy_pearson_backward")
+            hip.rt.hipEventRecord(e2, sh)
+
+        for _ in range(args.warmup):
+            step()
+        fw, bw = [], []
+        for _ in range(max(args.steps, 5)):
+            step()
+            torch.cuda.synchronize(dev)
+            fw.append(hip.ms(e0, e1))
+            bw.append(hip.ms(e1, e2))
+        f_ms, b_ms = float(np.median(fw)), float(np.median(bw))
+        fwd_flop = 12.0 * S * F * (F + 1) / 2       # six multiply-adds per pair-sample
+        bwd_flop = 3 * 2.0 * S * F * F              # X0 A', M B', M Q': three [S x F] x [F x F] products
+        out[prec] = {"forward_ms": f_ms, "backward_ms": b_ms,
+                     "forward_tflops_fp32_equiv": fwd_flop / f_ms / 1e9,
+                     "backward_tflops": bwd_flop / b_ms / 1e9,
+                     "backward_fp32_mfma_frac": bwd_flop / b_ms / 1e9 / (FP32_MFMA_PEAK_FLOPS / 1e12)}
+    hip.close()
+    res = {
+        "metric": "differentiation form: masked-Pearson forward + backward (dL/dX) time",
+        "value": out["fp32"]["forward_ms"] + out["fp32"]["backward_ms"], "unit": "ms per forward+backward",
+        "n_gpus": 1, "higher_is_better": False, "form": "differentiation", "data": "synthetic",
+        "config": {"workload": "8,192 samples x 512 variables, rank-10 factor model, 15% MCAR; "
+                               "L = sum W o R with W symmetric N(0,1)", "samples": S, "variables": F},
+        "fp32": out["fp32"], "bf16x3": out["bf16x3"],
+    }
+    print(json.dumps(res))
+    return 0
 
 
 def run_copy(args) -> int:

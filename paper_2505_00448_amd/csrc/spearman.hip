@@ -620,6 +620,17 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
     uint32_t ivn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) ivn[u] = ngrp > 0 ? ordB[u * 64 + lane] : 0u;
+    // chunks holding tied b-positions, 64 chunks per window: bit c of dmask
+    // for chunk 64 w + c of the current window w (wave-uniform), built by one
+    // ballot over the window's tie-bit words, the next window's words loaded
+    // one window ahead
+    const int nwords = ngrp * U;  // tie-bit words of b's row that the walk covers
+    uint64_t dmask = 0, tbnext = 0;
+    if constexpr (TB) {
+        const uint64_t w0 = lane < nwords ? tbB[lane] : 0ull;
+        dmask = __ballot(w0 != 0ull);
+        tbnext = 64 + lane < nwords ? tbB[64 + lane] : 0ull;
+    }
     for (int g = 0; g < ngrp; ++g) {
         const int c0 = g * U;
         uint32_t iv[U], pv[U];
@@ -631,15 +642,16 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
 #pragma unroll
             for (int u = 0; u < U; ++u) ivn[u] = ordB[(c0 + U + u) * 64 + lane];
         }
-        bool dirty = false;
-        uint64_t tbw[U];
+        uint32_t dbits = 0;  // bit u: chunk c0 + u holds tied b-positions
         if constexpr (TB) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                tbw[u] = tbB[c0 + u];
-                dirty |= tbw[u] != 0ull;
+            if ((c0 & 63) == 0 && c0 > 0) {
+                dmask = __ballot(tbnext != 0ull);
+                const int nw = c0 + 64 + lane;
+                tbnext = nw < nwords ? tbB[nw] : 0ull;
             }
+            dbits = (uint32_t)(dmask >> (c0 & 63)) & ((1u << U) - 1u);
         }
+        const bool dirty = dbits != 0u;
 #pragma unroll
         for (int u = 0; u < U; ++u) pv[u] = posA[iv[u]];
         uint32_t t32 = 0;
@@ -655,11 +667,11 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = (c0 + u) * 64 + lane;
-                rb[u] = (tbw[u] != 0ull && k < nbv) ? runsB[k] : ((uint32_t)k | ((uint32_t)(k + 1) << 16));
+                rb[u] = (((dbits >> u) & 1u) && k < nbv) ? runsB[k] : ((uint32_t)k | ((uint32_t)(k + 1) << 16));
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (tbw[u] == 0ull) {
+                if (((dbits >> u) & 1u) == 0u) {
                     // no tied b-position here, and no run crosses into this chunk
                     walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, runsA, carry1, t32, sAf, dbg_ra, dbg_rb);
                     continue;
