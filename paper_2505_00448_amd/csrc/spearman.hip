@@ -53,7 +53,8 @@ struct SpearBase {
     uint16_t* pos;     // [F][ld]
     uint32_t* runs;    // [F][ld]
     uint64_t* tbits;   // [F][ld/64]: bit k set if sorted position k lies in a tie run
-    uint64_t* rsbits;  // [F][ld/64]: bit k set if a tie run starts at sorted position k
+    uint32_t* rlist;   // [F][ld/2]: tie run r (length > 1) of the column as s | e << 16
+    int32_t* nruns;    // [F] number of tie runs
     int32_t* ncol;     // [F]
     int32_t* hasties;  // [F]
     int32_t* tcount;   // [F] number of positions in tie runs
@@ -76,7 +77,8 @@ static void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
     b.pos = c.take<uint16_t>((size_t)F * b.ld);
     b.runs = c.take<uint32_t>((size_t)F * b.ld);
     b.tbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
-    b.rsbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
+    b.rlist = c.take<uint32_t>((size_t)F * (b.ld / 2));
+    b.nruns = c.take<int32_t>(F);
     b.ncol = c.take<int32_t>(F);
     b.hasties = c.take<int32_t>(F);
     b.tcount = c.take<int32_t>(F);
@@ -352,15 +354,45 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
         }
     }
     __syncthreads();
+    // tie runs (length > 1) numbered in position order: a block scan of the
+    // run starts each thread holds
+    uint32_t nstart = 0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int k = t * E + e;
+        if (e < E && k < ncount && rs[e] == k && END[k] - (uint32_t)k > 1u) ++nstart;
+    }
+    const uint32_t sincl = wave_incl_scan_u32(nstart);
+    if (lane == 63) sm.red[wave] = (int32_t)sincl;
+    __syncthreads();
+    uint32_t rid = sincl - nstart, nrun = 0;
+    for (int ww = 0; ww < CS_WAVES; ++ww) {
+        rid += (ww < wave) ? (uint32_t)sm.red[ww] : 0u;
+        nrun += (uint32_t)sm.red[ww];
+    }
+    uint16_t* RID = sm.idx;  // reused: RID[run start] = run index
+    uint32_t* rlc = out.rlist + (int64_t)col * (ld / 2);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int k = t * E + e;
+        if (e < E && k < ncount && rs[e] == k && END[k] - (uint32_t)k > 1u) {
+            RID[k] = (uint16_t)rid;
+            rlc[rid] = (uint32_t)k | (END[k] << 16);
+            ++rid;
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         if (e < E) {
             const int k = t * E + e;
             if (k < ncount) {
                 ordc[k] = idx[e];
-                // bit 15 of a position flags a sample whose value is tied
+                // a tied sample's position entry holds the flag bit and its
+                // run index instead of the sorted position
                 const uint32_t run_end = END[rs[e]];
-                posc[idx[e]] = (uint16_t)(k | ((run_end - (uint32_t)rs[e] > 1u) ? 0x8000 : 0));
+                const bool tied = run_end - (uint32_t)rs[e] > 1u;
+                posc[idx[e]] = (uint16_t)(tied ? (0x8000u | RID[rs[e]]) : (uint32_t)k);
                 runc[k] = (uint32_t)rs[e] | (run_end << 16);
             } else if (idx[e] != 0xFFFF) {
                 posc[idx[e]] = 0xFFFF;  // missing sample
@@ -377,6 +409,7 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
     if (t == 0) {
         out.ncol[col] = ncount;
         out.hasties[col] = anytie ? 1 : 0;
+        out.nruns[col] = (int32_t)nrun;
     }
 }
 
@@ -409,17 +442,14 @@ __global__ __launch_bounds__(256) void k_tiebits(SpearBase bs)
     const int64_t c = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int nc = bs.ncol[c];
-    bool tie = false, start = false;
+    bool tie = false;
     if (k < nc) {
         const uint32_t rr = bs.runs[c * bs.ld + k];
         tie = (rr >> 16) - (rr & 0xFFFFu) > 1u;
-        start = tie && (rr & 0xFFFFu) == (uint32_t)k;
     }
     const uint64_t m = __ballot(tie);
-    const uint64_t ms = __ballot(start);
     if ((threadIdx.x & 63) == 0 && k < bs.ld) {
         bs.tbits[c * (bs.ld / 64) + (k >> 6)] = m;
-        bs.rsbits[c * (bs.ld / 64) + (k >> 6)] = ms;
         if (m) atomicAdd(&bs.tcount[c], (int32_t)__popcll(m));
     }
 }
@@ -539,10 +569,9 @@ __device__ __forceinline__ uint32_t cnt1(const uint2* tab, uint32_t x)
     return e.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(e.x, 0u, x));
 }
 
-// doubled average rank of a tied a-position: C(s) + C(e) + 1 over its run
-__device__ __forceinline__ uint32_t ra_tied(const uint2* tab, const uint32_t* __restrict__ runsA, uint32_t pos)
+// doubled average rank of a sample in a's tie run [s, e): C(s) + C(e) + 1
+__device__ __forceinline__ uint32_t ra_run(const uint2* tab, uint32_t rr)
 {
-    const uint32_t rr = runsA[pos];
     return cnt1(tab, rr & 0xFFFFu) + cnt1(tab, rr >> 16) - 1u;
 }
 
@@ -557,21 +586,41 @@ __device__ __forceinline__ uint64_t cube_minus(uint32_t t)
 struct WalkSums {
     uint32_t n;
     uint64_t A4;   // per lane: sum of C1_a * C1_b over untied complete samples
-    uint64_t Af;   // per lane: sum of R_a * R_b over the other complete samples
+    uint64_t At;   // per lane: sum of R_a * C1_b over complete samples tied in a
+    uint64_t Af;   // per lane: sum of R_a * R_b over complete samples in b's tie runs
     uint64_t d3B;  // per lane: sum of t^3 - t over b's tie runs
     uint64_t Au;   // wave-uniform: deferred tie runs of b
 };
 
 constexpr int WALK_U = 4;  // chunks of 64 positions per group; rows are padded to 64 * WALK_U
 
+// How a's tied samples are ranked in the walk.  Their stored position is the
+// flag bit plus the index of their tie run in a's run list.
+//   TIES_NONE  a has no tie run;
+//   TIES_TABLE at most RUN_TABLE_MAX runs: each run's doubled average rank
+//              for this partner sits in LDS;
+//   TIES_RUNS  more runs: the rank comes from the run's bounds (run list,
+//              global) and two table lookups.
+constexpr int TIES_NONE = 0, TIES_TABLE = 1, TIES_RUNS = 2;
+constexpr int RUN_TABLE_MAX = 20;
+
+template <int TAM>
+__device__ __forceinline__ uint32_t ra_of_tied(const uint2* tab, const uint32_t* __restrict__ rlA,
+                                               const uint32_t* rrun, uint32_t pv)
+{
+    if constexpr (TAM == TIES_TABLE) return rrun[pv & POS_MASK];
+    else return ra_run(tab, rlA[pv & POS_MASK]);
+}
+
 // One chunk of 64 positions of b's sorted order without tied b-positions.
 // b's C1 = carry1 + (complete samples at lower lanes) by mbcnt; a's C1 from
 // the partner table, 0 for missing or tied a-positions (both map to the
 // table's zero entry), whose products are added separately.
-template <bool TA, bool DBG>
+template <int TAM, bool DBG>
 __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, const uint2* tab, uint32_t XS,
-                                                  const uint32_t* __restrict__ runsA, uint32_t& carry1,
-                                                  uint32_t& t32, uint64_t& sAf, int32_t* dbg_ra, int32_t* dbg_rb)
+                                                  const uint32_t* __restrict__ rlA, const uint32_t* rrun,
+                                                  uint32_t& carry1, uint32_t& t32, uint64_t& sAt,
+                                                  int32_t* dbg_ra, int32_t* dbg_rb)
 {
     const bool kept = pv != 0xFFFFu;
     const uint64_t mask = __ballot(kept);
@@ -580,13 +629,14 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, carry1));
     t32 += __umul24(ca1, cb1);
     bool tied = false;
-    if constexpr (TA) {
+    if constexpr (TAM != TIES_NONE) {
         tied = kept && (pv & POS_TIED);
-        if (tied) sAf += (uint64_t)ra_tied(tab, runsA, pv & POS_MASK) * (2u * cb1);
+        // R_a * C1_b < 2^31: one 32-bit product per sample
+        if (tied) sAt += __umul24(ra_of_tied<TAM>(tab, rlA, rrun, pv), cb1);
     }
     if constexpr (DBG) {
         if (kept) {
-            dbg_ra[iv] = (int32_t)(tied ? ra_tied(tab, runsA, pv & POS_MASK) : 2u * ca1);
+            dbg_ra[iv] = (int32_t)(tied ? ra_of_tied<TAM>(tab, rlA, rrun, pv) : 2u * ca1);
             dbg_rb[iv] = (int32_t)(2u * cb1);
         }
     }
@@ -604,17 +654,17 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
 // next chunk is carried as wave-uniform state (its start count, plus per
 // lane the a-ranks of its complete samples so far) and settled where it
 // ends, and the lane at each run's last position records t^3 - t for it.
-template <bool TA, bool TB, bool DBG>
+template <int TAM, bool TB, bool DBG>
 __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
-                                          const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ runsA,
-                                          int nbv, const uint16_t* posA, const uint2* tab, uint32_t XS, int lane,
-                                          int32_t* dbg_ra, int32_t* dbg_rb, WalkSums& ws)
+                                          const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ rlA,
+                                          int nbv, const uint16_t* posA, const uint2* tab, const uint32_t* rrun,
+                                          uint32_t XS, int lane, int32_t* dbg_ra, int32_t* dbg_rb, WalkSums& ws)
 {
     constexpr int U = WALK_U;
     const int ncb = (nbv + 63) >> 6;
     const int ngrp = (ncb + U - 1) / U;
     uint32_t carry1 = 1;  // wave-uniform
-    uint64_t sA4 = 0, sAf = 0, d3B = 0, uA = 0;
+    uint64_t sA4 = 0, sAt = 0, sAf = 0, d3B = 0, uA = 0;
     uint32_t open_cs = 0, pend_lane = 0;
     bool open = false;
     uint32_t ivn[U];
@@ -658,7 +708,7 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
         if (!dirty) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, runsA, carry1, t32, sAf, dbg_ra, dbg_rb);
+                walk_chunk_untied<TAM, DBG>(iv[u], pv[u], tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
             sA4 += t32;
             continue;
         }
@@ -673,7 +723,8 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
             for (int u = 0; u < U; ++u) {
                 if (((dbits >> u) & 1u) == 0u) {
                     // no tied b-position here, and no run crosses into this chunk
-                    walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, runsA, carry1, t32, sAf, dbg_ra, dbg_rb);
+                    walk_chunk_untied<TAM, DBG>(iv[u], pv[u], tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra,
+                                                dbg_rb);
                     continue;
                 }
                 const int c = c0 + u;
@@ -682,8 +733,8 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                 const uint64_t mask = __ballot(kept);
                 const uint32_t carry = carry1 - 1u;
                 uint32_t Ra = 2u * cnt1(tab, min(pv[u], XS));
-                if constexpr (TA) {
-                    if (kept && (pv[u] & POS_TIED)) Ra = ra_tied(tab, runsA, pv[u] & POS_MASK);
+                if constexpr (TAM != TIES_NONE) {
+                    if (kept && (pv[u] & POS_TIED)) Ra = ra_of_tied<TAM>(tab, rlA, rrun, pv[u]);
                 }
                 const uint32_t lo = (uint32_t)c * 64u;
                 const uint32_t rs = rb[u] & 0xFFFFu, re = rb[u] >> 16;
@@ -741,6 +792,7 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
     }
     ws.n = carry1 - 1u;
     ws.A4 = sA4;
+    ws.At = sAt;
     ws.Af = sAf;
     ws.d3B = d3B;
     ws.Au = uA;
@@ -748,27 +800,24 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
 
 // LDS layout of the pair kernel for S samples and PB partners
 struct PairSmem {
-    size_t off_tab, off_corr, bytes;
+    size_t off_tab, off_corr, off_rrun, bytes;
     int nwp;  // table entries per partner
 };
 
+// posA: positions of samples 0..S (S is the dummy); tab: PB partner tables;
+// corr: PB tie-defect sums; rrun: [PB][RUN_TABLE_MAX] run ranks
 __host__ __device__ inline PairSmem pair_smem(int64_t ld, int64_t S, int PB)
 {
+    (void)ld;
     PairSmem m;
     m.nwp = (int)((S + 1 + 31) / 32) + 1;
-    m.off_tab = (size_t)round_up(ld * 2, 16);
+    m.off_tab = (size_t)round_up(2 * (S + 1), 16);
     m.off_corr = m.off_tab + (size_t)PB * m.nwp * 8;
-    m.bytes = m.off_corr + (size_t)PB * 8;
+    m.off_rrun = m.off_corr + (size_t)PB * 8;
+    m.bytes = m.off_rrun + (size_t)PB * RUN_TABLE_MAX * 4;
     return m;
 }
 
-// One workgroup per (column a, block of PB partner columns), both in the
-// processing order perm (k_perm).  Step 1 builds, for all PB partners at
-// once, the partner table along a's sorted order (one presence-word gather
-// per position, one ballot per partner) and, when a has ties, the tie
-// defects of a's runs for every partner.  Step 2 walks each partner's sorted
-// order once (pair_walk).  DBG: one pair (dbg_a, dbg_b) of physical columns,
-// reporting the doubled ranks of every complete sample.
 // Work list of the pair kernel.  Rows la of the processing order come in
 // bands of 8 PB rows; band g holds partner blocks 8g .. nbp-1 (nbp = number of
 // partner blocks padded to a multiple of 8), which covers every block that
@@ -818,21 +867,24 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const int64_t ld = bs.ld;
     const PairSmem L = pair_smem(ld, S, PB);
     uint16_t* posA = (uint16_t*)smem_raw;
-    uint2* tab = (uint2*)(smem_raw + L.off_tab);                    // [PB][nwp]
+    uint2* tab = (uint2*)(smem_raw + L.off_tab);                               // [PB][nwp]
     unsigned long long* corrA = (unsigned long long*)(smem_raw + L.off_corr);  // [PB]
+    uint32_t* rrun = (uint32_t*)(smem_raw + L.off_rrun);                       // [PB][RUN_TABLE_MAX]
 
     const int na = bs.ncol[a];
     const int tA = bs.hasties[a];
     const uint16_t* ordA = bs.ord + a * ld;
-    const uint32_t* runsA = bs.runs + a * ld;
+    const uint32_t* rlA = bs.rlist + a * (ld / 2);
+    const int nra = tA ? bs.nruns[a] : 0;
+    const int tam = !tA ? TIES_NONE : (nra <= RUN_TABLE_MAX ? TIES_TABLE : TIES_RUNS);
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
     const int nc64 = (NW + 1) >> 1;
     {
-        // rows are whole multiples of 512 bytes: 16-byte copies, every load
-        // of a thread issued before its stores
+        // 16-byte copies of positions 0..S, every load of a thread issued
+        // before its stores
         const uint4* src = (const uint4*)(bs.pos + a * ld);
         uint4* dst = (uint4*)posA;
-        const int n16 = (int)(ld / 8);
+        const int n16 = (int)((S + 1 + 7) / 8);
         constexpr int CU = 8;
         for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
             // loads from a clamped index (always inside the row) keep v in
@@ -903,23 +955,19 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     }
     __syncthreads();
     if (tA) {
-        // tie defects of a's runs, per partner: a run [s, e) holds
-        // C(e) - C(s) complete samples; run starts come from the run-start bits
+        // per tie run [s, e) of a and partner: C(e) - C(s) complete samples
+        // (tie defect) with doubled average rank C(s) + C(e) + 1 (run-rank
+        // table)
         const int nj = DBG ? 1 : PB;
-        const uint64_t* rsA = bs.rsbits + a * (ld / 64);
-        const int nwords = (na + 63) >> 6;
-        for (int w = threadIdx.x; w < nwords; w += PAIR_THREADS) {
-            uint64_t m = rsA[w];
-            while (m) {
-                const uint32_t k = (uint32_t)w * 64u + (uint32_t)__builtin_ctzll(m);
-                m &= m - 1ull;
-                const uint32_t rr = runsA[k];
-                const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
-                for (int j = 0; j < nj; ++j) {
-                    const uint2* tj = tab + (size_t)j * L.nwp;
-                    const uint32_t t = cnt1(tj, e) - cnt1(tj, s);
-                    if (t > 1u) atomicAdd(&corrA[j], (unsigned long long)cube_minus(t));
-                }
+        for (int r = threadIdx.x; r < nra; r += PAIR_THREADS) {
+            const uint32_t rr = rlA[r];
+            const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
+            for (int j = 0; j < nj; ++j) {
+                const uint2* tj = tab + (size_t)j * L.nwp;
+                const uint32_t c1s = cnt1(tj, s), c1e = cnt1(tj, e);
+                if (tam == TIES_TABLE) rrun[j * RUN_TABLE_MAX + r] = c1s + c1e - 1u;
+                const uint32_t tt = c1e - c1s;
+                if (tt > 1u) atomicAdd(&corrA[j], (unsigned long long)cube_minus(tt));
             }
         }
         __syncthreads();
@@ -937,15 +985,21 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         const uint32_t* runsB = bs.runs + b * ld;
         const uint64_t* tbB = bs.tbits + b * (ld / 64);
         const uint2* tj = tab + (size_t)j * L.nwp;
+        const uint32_t* rj = rrun + j * RUN_TABLE_MAX;
         WalkSums w;
-        if (tA) {
-            if (tB) pair_walk<true, true, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
-            else pair_walk<true, false, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
+#define NAPY_WALK(M, T) pair_walk<M, T, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
+        if (tam == TIES_TABLE) {
+            if (tB) NAPY_WALK(TIES_TABLE, true);
+            else NAPY_WALK(TIES_TABLE, false);
+        } else if (tam == TIES_RUNS) {
+            if (tB) NAPY_WALK(TIES_RUNS, true);
+            else NAPY_WALK(TIES_RUNS, false);
         } else {
-            if (tB) pair_walk<false, true, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
-            else pair_walk<false, false, DBG>(ordB, runsB, tbB, runsA, nbv, posA, tj, XS, lane, po.dbg_ra, po.dbg_rb, w);
+            if (tB) NAPY_WALK(TIES_NONE, true);
+            else NAPY_WALK(TIES_NONE, false);
         }
-        const uint64_t sA = 4ull * wave_sum_u64(w.A4) + wave_sum_u64(w.Af) + w.Au;
+#undef NAPY_WALK
+        const uint64_t sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au;
         const uint64_t d3B = tB ? wave_sum_u64(w.d3B) : 0ull;
         if (lane == 0 && !DBG) {
             const int64_t nn = (int64_t)w.n;
@@ -1020,6 +1074,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
                                                           SpearBase q)
 {
     __shared__ uint16_t P[SPEARMAN_MAX_S + 1];  // kept positions below k
+    __shared__ uint16_t RQ[SPEARMAN_MAX_S];     // run index at a kept run's first position
+    __shared__ uint32_t nrun_sh;
     __shared__ uint32_t wsum[16];
     const int qc = blockIdx.x;
     const int64_t c = cols[qc];
@@ -1059,6 +1115,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
     if (qc == (int)gridDim.x - 1)
         for (int64_t k = t; k < ORD_TAIL; k += SORT_THREADS) qord[q.ld + k] = (uint16_t)Sq;
     __syncthreads();
+    // tie runs of the kept samples: each base run restricted to the kept
+    // positions; the ones still longer than 1 get run indices (in any order:
+    // every use of the index goes through the run list) and a list entry
+    uint32_t* qrl = q.rlist + (int64_t)qc * (q.ld / 2);
+    if (t == 0) nrun_sh = 0;
+    __syncthreads();
     int tie = 0;
     for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
         const int k = k0 + t;
@@ -1068,8 +1130,27 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
                 const uint32_t rr = runs[k];
                 const uint32_t s0 = P[rr & 0xFFFFu], e0 = P[rr >> 16];
                 qruns[P[k]] = s0 | (e0 << 16);
-                tie |= (e0 - s0) > 1u;
-                qpos[nr] = (uint16_t)(P[k] | ((e0 - s0 > 1u) ? 0x8000 : 0));
+                const bool tied = e0 - s0 > 1u;
+                tie |= tied;
+                if (!tied) {
+                    qpos[nr] = (uint16_t)P[k];
+                } else if (P[k] == s0) {
+                    const uint32_t rid = atomicAdd(&nrun_sh, 1u);
+                    RQ[s0] = (uint16_t)rid;
+                    qrl[rid] = s0 | (e0 << 16);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
+        const int k = k0 + t;
+        if (k < nc) {
+            const int32_t nr = rowmap[ord[k]];
+            if (nr >= 0) {
+                const uint32_t rr = runs[k];
+                const uint32_t s0 = P[rr & 0xFFFFu], e0 = P[rr >> 16];
+                if (e0 - s0 > 1u) qpos[nr] = (uint16_t)(POS_TIED | RQ[s0]);
             }
         }
     }
@@ -1077,6 +1158,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const 
     if (t == 0) {
         q.ncol[qc] = (int32_t)carry;
         q.hasties[qc] = anytie;
+        q.nruns[qc] = (int32_t)nrun_sh;
     }
 }
 
