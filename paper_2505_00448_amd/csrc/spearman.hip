@@ -594,29 +594,26 @@ struct WalkSums {
 
 constexpr int WALK_U = 4;  // chunks of 64 positions per group; rows are padded to 64 * WALK_U
 
-// How a's tied samples are ranked in the walk.  Their stored position is the
-// flag bit plus the index of their tie run in a's run list.
-//   TIES_NONE  a has no tie run;
-//   TIES_TABLE at most RUN_TABLE_MAX runs: each run's doubled average rank
-//              for this partner sits in LDS;
-//   TIES_RUNS  more runs: the rank comes from the run's bounds (run list,
-//              global) and two table lookups.
-constexpr int TIES_NONE = 0, TIES_TABLE = 1, TIES_RUNS = 2;
+// a's tied samples: their stored position is the flag bit plus the index of
+// their tie run in a's run list.  With at most RUN_TABLE_MAX runs each run's
+// doubled average rank for the partner sits in LDS; with more, it comes from
+// the run's bounds (run list, global) and two table lookups.
 constexpr int RUN_TABLE_MAX = 20;
 
-template <int TAM>
+// rank of a tied a-sample: from the run-rank table when a has at most
+// RUN_TABLE_MAX runs (rrun != nullptr), else from the run list
 __device__ __forceinline__ uint32_t ra_of_tied(const uint2* tab, const uint32_t* __restrict__ rlA,
                                                const uint32_t* rrun, uint32_t pv)
 {
-    if constexpr (TAM == TIES_TABLE) return rrun[pv & POS_MASK];
-    else return ra_run(tab, rlA[pv & POS_MASK]);
+    if (rrun) return rrun[pv & POS_MASK];
+    return ra_run(tab, rlA[pv & POS_MASK]);
 }
 
 // One chunk of 64 positions of b's sorted order without tied b-positions.
 // b's C1 = carry1 + (complete samples at lower lanes) by mbcnt; a's C1 from
 // the partner table, 0 for missing or tied a-positions (both map to the
 // table's zero entry), whose products are added separately.
-template <int TAM, bool DBG>
+template <bool TA, bool DBG>
 __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, const uint2* tab, uint32_t XS,
                                                   const uint32_t* __restrict__ rlA, const uint32_t* rrun,
                                                   uint32_t& carry1, uint32_t& t32, uint64_t& sAt,
@@ -629,14 +626,14 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, carry1));
     t32 += __umul24(ca1, cb1);
     bool tied = false;
-    if constexpr (TAM != TIES_NONE) {
+    if constexpr (TA) {
         tied = kept && (pv & POS_TIED);
         // R_a * C1_b < 2^31: one 32-bit product per sample
-        if (tied) sAt += __umul24(ra_of_tied<TAM>(tab, rlA, rrun, pv), cb1);
+        if (tied) sAt += __umul24(ra_of_tied(tab, rlA, rrun, pv), cb1);
     }
     if constexpr (DBG) {
         if (kept) {
-            dbg_ra[iv] = (int32_t)(tied ? ra_of_tied<TAM>(tab, rlA, rrun, pv) : 2u * ca1);
+            dbg_ra[iv] = (int32_t)(tied ? ra_of_tied(tab, rlA, rrun, pv) : 2u * ca1);
             dbg_rb[iv] = (int32_t)(2u * cb1);
         }
     }
@@ -654,7 +651,7 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
 // next chunk is carried as wave-uniform state (its start count, plus per
 // lane the a-ranks of its complete samples so far) and settled where it
 // ends, and the lane at each run's last position records t^3 - t for it.
-template <int TAM, bool TB, bool DBG>
+template <bool TA, bool TB, bool DBG>
 __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
                                           const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ rlA,
                                           int nbv, const uint16_t* posA, const uint2* tab, const uint32_t* rrun,
@@ -708,36 +705,34 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
         if (!dirty) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                walk_chunk_untied<TAM, DBG>(iv[u], pv[u], tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
+                walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
             sA4 += t32;
             continue;
         }
         if constexpr (TB) {
-            uint32_t rb[U];
-#pragma unroll
+            // a group with tied b-positions: one chunk at a time (the code of
+            // this rarely taken path exists once), sample indices reloaded
+#pragma unroll 1
             for (int u = 0; u < U; ++u) {
-                const int k = (c0 + u) * 64 + lane;
-                rb[u] = (((dbits >> u) & 1u) && k < nbv) ? runsB[k] : ((uint32_t)k | ((uint32_t)(k + 1) << 16));
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (((dbits >> u) & 1u) == 0u) {
-                    // no tied b-position here, and no run crosses into this chunk
-                    walk_chunk_untied<TAM, DBG>(iv[u], pv[u], tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra,
-                                                dbg_rb);
-                    continue;
-                }
                 const int c = c0 + u;
                 const uint32_t k = (uint32_t)(c * 64 + lane);
-                const bool kept = pv[u] != 0xFFFFu;
+                const uint32_t ivu = ordB[k];
+                const uint32_t pvu = posA[ivu];
+                if (((dbits >> u) & 1u) == 0u) {
+                    // no tied b-position here, and no run crosses into this chunk
+                    walk_chunk_untied<TA, DBG>(ivu, pvu, tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
+                    continue;
+                }
+                const uint32_t rb = ((int)k < nbv) ? runsB[k] : (k | ((k + 1u) << 16));
+                const bool kept = pvu != 0xFFFFu;
                 const uint64_t mask = __ballot(kept);
                 const uint32_t carry = carry1 - 1u;
-                uint32_t Ra = 2u * cnt1(tab, min(pv[u], XS));
-                if constexpr (TAM != TIES_NONE) {
-                    if (kept && (pv[u] & POS_TIED)) Ra = ra_of_tied<TAM>(tab, rlA, rrun, pv[u]);
+                uint32_t Ra = 2u * cnt1(tab, min(pvu, XS));
+                if constexpr (TA) {
+                    if (kept && (pvu & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pvu);
                 }
                 const uint32_t lo = (uint32_t)c * 64u;
-                const uint32_t rs = rb[u] & 0xFFFFu, re = rb[u] >> 16;
+                const uint32_t rs = rb & 0xFFFFu, re = rb >> 16;
                 const uint32_t cs = (rs >= lo) ? carry + (uint32_t)__popcll(bits_below(mask, rs - lo)) : open_cs;
                 const bool ends = re <= lo + 64u;
                 const uint32_t ce = carry + (uint32_t)__popcll(bits_below(mask, ends ? re - lo : 64u));
@@ -782,8 +777,8 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                 if (direct) sAf += (uint64_t)Ra * Rb;
                 if constexpr (DBG) {
                     if (kept) {
-                        dbg_ra[iv[u]] = (int32_t)Ra;
-                        if (direct) dbg_rb[iv[u]] = (int32_t)Rb;
+                        dbg_ra[ivu] = (int32_t)Ra;
+                        if (direct) dbg_rb[ivu] = (int32_t)Rb;
                     }
                 }
             }
@@ -876,7 +871,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const uint16_t* ordA = bs.ord + a * ld;
     const uint32_t* rlA = bs.rlist + a * (ld / 2);
     const int nra = tA ? bs.nruns[a] : 0;
-    const int tam = !tA ? TIES_NONE : (nra <= RUN_TABLE_MAX ? TIES_TABLE : TIES_RUNS);
+    const bool rtab = tA && nra <= RUN_TABLE_MAX;  // run-rank table in LDS
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
     const int nc64 = (NW + 1) >> 1;
     {
@@ -965,7 +960,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             for (int j = 0; j < nj; ++j) {
                 const uint2* tj = tab + (size_t)j * L.nwp;
                 const uint32_t c1s = cnt1(tj, s), c1e = cnt1(tj, e);
-                if (tam == TIES_TABLE) rrun[j * RUN_TABLE_MAX + r] = c1s + c1e - 1u;
+                if (rtab) rrun[j * RUN_TABLE_MAX + r] = c1s + c1e - 1u;
                 const uint32_t tt = c1e - c1s;
                 if (tt > 1u) atomicAdd(&corrA[j], (unsigned long long)cube_minus(tt));
             }
@@ -985,18 +980,15 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         const uint32_t* runsB = bs.runs + b * ld;
         const uint64_t* tbB = bs.tbits + b * (ld / 64);
         const uint2* tj = tab + (size_t)j * L.nwp;
-        const uint32_t* rj = rrun + j * RUN_TABLE_MAX;
+        const uint32_t* rj = rtab ? rrun + j * RUN_TABLE_MAX : nullptr;
         WalkSums w;
-#define NAPY_WALK(M, T) pair_walk<M, T, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
-        if (tam == TIES_TABLE) {
-            if (tB) NAPY_WALK(TIES_TABLE, true);
-            else NAPY_WALK(TIES_TABLE, false);
-        } else if (tam == TIES_RUNS) {
-            if (tB) NAPY_WALK(TIES_RUNS, true);
-            else NAPY_WALK(TIES_RUNS, false);
+#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
+        if (tA) {
+            if (tB) NAPY_WALK(true, true);
+            else NAPY_WALK(true, false);
         } else {
-            if (tB) NAPY_WALK(TIES_NONE, true);
-            else NAPY_WALK(TIES_NONE, false);
+            if (tB) NAPY_WALK(false, true);
+            else NAPY_WALK(false, false);
         }
 #undef NAPY_WALK
         const uint64_t sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au;
