@@ -23,14 +23,16 @@
 //                    (sorted position of sample i, 0xFFFF if missing),
 //                    runs[c][k] = s | e << 16 (tie run of position k), n_c and
 //                    a has-ties flag.
-//   k_presence       presence words: bit j of pres[w][i] = sample i present
-//                    in column 32 w + j.
-//   k_spearman_pairs one workgroup per (column a, block of 8 partners b).  pos_a
-//                    lives in LDS.  Step 1 builds, for all 8 partners at
-//                    once, a table along a's sorted order: the partner's
-//                    presence bits per 32 positions and the count before
-//                    them (one presence-word gather per position, one ballot
-//                    per partner), plus the tie defects of a's runs.  Step 2:
+//   k_presence       presence bytes: bit j of presb[q][i] = sample i present
+//                    in column 8 q + j of the processing order.
+//   k_spearman_pairs one workgroup per (column a, block of 8 partners b).
+//                    Step 1 copies the block's presence bytes to LDS and
+//                    builds, for all 8 partners at once, a table along a's
+//                    sorted order: the partner's presence bits per 32
+//                    positions and the count before them (one LDS byte
+//                    gather per position, one ballot per partner), plus the
+//                    tie defects of a's runs; pos_a then replaces the
+//                    presence bytes in LDS.  Step 2:
 //                    each wave walks one partner's sorted order once; b's
 //                    count of complete samples below each position comes from
 //                    ballot + mbcnt, a's from the table by popcount; the
@@ -511,23 +513,24 @@ static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
     return check_launch("perm");
 }
 
-// Presence words in processing order: pres[w][i] bit j = sample i present in
-// column perm[32 w + j].
-__global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64_t F, uint32_t* __restrict__ pres)
+// Presence bytes in processing order, one plane per block of 8 columns:
+// bit j of presb[q][i] = sample i present in column perm[8 q + j].  A pair
+// workgroup copies its partner block's plane (S bytes) into LDS.
+__global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64_t F, uint8_t* __restrict__ presb)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t w = blockIdx.y;
+    const int64_t q = blockIdx.y;
     if (i >= bs.ld) return;
-    uint32_t word = 0u;
+    uint32_t byte = 0u;
     if (i < S) {
-        const int64_t c0 = w * 32;
-        const int nj = (int)min((int64_t)32, F - c0);
+        const int64_t c0 = q * 8;
+        const int nj = (int)min((int64_t)8, F - c0);
         for (int j = 0; j < nj; ++j) {
             const int64_t col = bs.perm[c0 + j];
-            word |= (uint32_t)(bs.pos[col * bs.ld + i] != 0xFFFF) << j;
+            byte |= (uint32_t)(bs.pos[col * bs.ld + i] != 0xFFFF) << j;
         }
     }
-    pres[w * bs.ld + i] = word;
+    presb[q * bs.ld + i] = (uint8_t)byte;
 }
 
 constexpr int PAIR_THREADS = 512;
@@ -794,6 +797,55 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
 }
 
 // LDS layout of the pair kernel for S samples and PB partners
+// llvm.amdgcn.writelane: old with one lane replaced by a wave-uniform value
+// (v_writelane_b32).  Declared through the intrinsic so that the compiler
+// sees the instruction and inserts the wait states after the VALU write of
+// the scalar register it reads.
+extern "C" __device__ int napy_amdgcn_writelane(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+template <int LANE>
+__device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t v)
+{
+    return (uint32_t)napy_amdgcn_writelane((int)v, LANE, (int)old);
+}
+
+// lanes 2j and 2j + 1 of the result get the low and high halves of the
+// ballot of bit j of w, for j = J .. N - 1
+template <int J, int N>
+__device__ __forceinline__ uint32_t pack_ballots(uint32_t out, uint32_t w)
+{
+    if constexpr (J == N) {
+        return out;
+    } else {
+        const uint64_t m = __ballot((w >> J) & 1u);
+        out = write_lane<2 * J>(out, (uint32_t)m);
+        out = write_lane<2 * J + 1>(out, (uint32_t)(m >> 32));
+        return pack_ballots<J + 1, N>(out, w);
+    }
+}
+
+// Block-wide copy of n16 16-byte words from global memory to LDS, every load
+// of a thread issued before its stores.  Loads come from a clamped index
+// (always inside the source) so the words stay in registers; only the stores
+// are predicated.
+__device__ __forceinline__ void copy16_to_lds(uint4* dst, const uint4* __restrict__ src, int n16)
+{
+    constexpr int CU = 8;
+    for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
+        uint4 v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
+            v[u] = src[w < n16 ? w : n16 - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
+            if (w < n16) dst[w] = v[u];
+        }
+    }
+}
+
 struct PairSmem {
     size_t off_tab, off_corr, off_rrun, bytes;
     int nwp;  // table entries per partner
@@ -834,9 +886,10 @@ __host__ inline int64_t pair_grid_size(int64_t F, int64_t nbp, int PB)
 }
 
 template <int PB, bool DBG>
-__global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint32_t* __restrict__ pres,
+__global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint8_t* __restrict__ presb,
                                                                  int64_t S, int64_t F, int64_t nbp, PairOut po)
 {
+    static_assert(PB == 8, "a partner block is one plane of presence bytes");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     // the wave index is the same in every lane: readfirstlane lets the
     // compiler keep everything derived from it in scalar registers
@@ -874,68 +927,47 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const bool rtab = tA && nra <= RUN_TABLE_MAX;  // run-rank table in LDS
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
     const int nc64 = (NW + 1) >> 1;
-    {
-        // 16-byte copies of positions 0..S, every load of a thread issued
-        // before its stores
-        const uint4* src = (const uint4*)(bs.pos + a * ld);
-        uint4* dst = (uint4*)posA;
-        const int n16 = (int)((S + 1 + 7) / 8);
-        constexpr int CU = 8;
-        for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
-            // loads from a clamped index (always inside the row) keep v in
-            // registers; only the stores are predicated
-            uint4 v[CU];
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
-                v[u] = src[w < n16 ? w : n16 - 1];
-            }
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
-                if (w < n16) dst[w] = v[u];
-            }
-        }
-    }
+    // the partner block's presence bytes go where a's positions will be
+    // (they are needed only while the tables are built); lane-wise gathers
+    // from LDS instead of global memory
+    uint8_t* presL = (uint8_t*)smem_raw;
+    // bytes 0..S: byte S is zero (the sentinel sample of a's padded order)
+    if constexpr (!DBG) copy16_to_lds((uint4*)presL, (const uint4*)(presb + (b0 / PB) * ld), (int)((S + 16) / 16));
     if (threadIdx.x < PB) corrA[threadIdx.x] = 0ull;
+    __syncthreads();
 
     // ---- step 1: partner tables along a's order, PB partners at once --------
-    const uint32_t* presw = pres + (b0 >> 5) * ld;
-    const int shift = (int)(b0 & 31);  // partner blocks are aligned to PB within a 32-column word
+    // Positions p < 64 * nc64 stay inside a's padded order (nc64 * 64 <=
+    // round_up(na + 1, 64) <= ld) and positions from na on hold the sentinel
+    // S, whose presence byte is zero: no guard on the loads.  Partner j's
+    // 64 bits for a chunk are one ballot; lanes 2j and 2j + 1 take its halves
+    // and lanes 0..15 store the chunk's 16 table words at once.
     const uint16_t* posDbg = bs.pos + (int64_t)po.dbg_b * ld;
+    const int jw = lane >> 1, hw = lane & 1;
+    uint32_t* tword = (uint32_t*)(tab + (size_t)(jw < PB ? jw : 0) * L.nwp + hw);
     constexpr int Q = 16;  // chunks per wave in flight
     for (int cq = wave; cq < nc64; cq += PAIR_WAVES * Q) {
         uint32_t idx[Q], word[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int p = (cq + q * PAIR_WAVES) * 64 + lane;
-            idx[q] = (p < na) ? ordA[p] : 0xFFFFFFFFu;
-        }
+        for (int q = 0; q < Q; ++q) idx[q] = (ordA + (cq + q * PAIR_WAVES) * 64)[lane];  // wave-uniform base
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if constexpr (DBG)  // the single partner's presence, from its positions
-                word[q] = (idx[q] != 0xFFFFFFFFu) ? (uint32_t)(posDbg[idx[q]] != 0xFFFF) : 0u;
+                word[q] = ((cq + q * PAIR_WAVES) * 64 + lane < na) ? (uint32_t)(posDbg[idx[q]] != 0xFFFF) : 0u;
             else
-                word[q] = (idx[q] != 0xFFFFFFFFu) ? (presw[idx[q]] >> shift) : 0u;
+                word[q] = presL[idx[q]];
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int c = cq + q * PAIR_WAVES;
             if (c >= nc64) break;
-            uint32_t lo = 0u, hi = 0u;
-#pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                const uint64_t m = __ballot((word[q] >> j) & 1u);
-                lo = (lane == j) ? (uint32_t)m : lo;
-                hi = (lane == j) ? (uint32_t)(m >> 32) : hi;
-            }
-            if (lane < PB) {
-                tab[(size_t)lane * L.nwp + 2 * c].x = lo;
-                if (2 * c + 1 < NW) tab[(size_t)lane * L.nwp + 2 * c + 1].x = hi;
-            }
+            const uint32_t out = pack_ballots<0, PB>(0u, word[q]);
+            if (lane < 2 * PB && 2 * c + hw < NW) tword[4 * c] = out;
         }
     }
     __syncthreads();
+    // a's positions 0..S (S is the dummy) over the presence bytes
+    copy16_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8));
     for (int j = wave; j < PB; j += PAIR_WAVES) {
         uint2* tj = tab + (size_t)j * L.nwp;
         uint32_t run = 1;
@@ -1164,7 +1196,7 @@ constexpr int PAIR_PB = 8;
 static_assert(PAIR_PB * 64 == PAIR_THREADS, "one partner per wave");
 
 template <bool DBG>
-static int pairs_launch_t(const SpearBase& bs, const uint32_t* pres, int64_t S, int64_t F, PairOut po,
+static int pairs_launch_t(const SpearBase& bs, const uint8_t* presb, int64_t S, int64_t F, PairOut po,
                           hipStream_t st)
 {
     const size_t smem = pair_smem(bs.ld, S, PAIR_PB).bytes;
@@ -1180,24 +1212,26 @@ static int pairs_launch_t(const SpearBase& bs, const uint32_t* pres, int64_t S, 
     const int64_t nblk = DBG ? 1 : pair_grid_size(F, nbp, PAIR_PB);
     if (nblk > 0x7FFFFFFFLL) return NAPY_E_UNSUPPORTED;
     hipLaunchKernelGGL((k_spearman_pairs<PAIR_PB, DBG>), dim3((unsigned)nblk), dim3(PAIR_THREADS), smem, st, bs,
-                       pres, S, F, nbp, po);
+                       presb, S, F, nbp, po);
     return check_launch("spearman_pairs");
 }
 
+// pres: room for ceil(F / 8) planes of ld presence bytes
 static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t F, PairOut po, hipStream_t st)
 {
-    const int64_t nw = ceil_div(F, 32);
-    hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)nw), dim3(256), 0, st, bs, S, F,
-                       pres);
+    uint8_t* presb = (uint8_t*)pres;
+    const int64_t nq = ceil_div(F, 8);
+    hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)nq), dim3(256), 0, st, bs, S, F,
+                       presb);
     NAPY_TRY(check_launch("presence"));
-    if (po.dbg_ra) return pairs_launch_t<true>(bs, pres, S, F, po, st);
-    return pairs_launch_t<false>(bs, pres, S, F, po, st);
+    if (po.dbg_ra) return pairs_launch_t<true>(bs, presb, S, F, po, st);
+    return pairs_launch_t<false>(bs, presb, S, F, po, st);
 }
 
 struct SpearWs {
     uint32_t* keys;
     SpearBase base;
-    uint32_t* pres;  // [ceil(F/32)][ld]
+    uint32_t* pres;  // ceil(F/32) * ld words: ceil(F/8) planes of ld presence bytes
     double4* sums;
     int2* ab;
 };
