@@ -566,7 +566,11 @@ constexpr uint32_t POS_MASK = 0x7FFFu;
 // position >= 32 NW gives 0.
 __device__ __forceinline__ uint32_t cnt1(const uint2* tab, uint32_t x)
 {
-    const uint2 e = *(const uint2*)((const char*)tab + ((x >> 5) << 3));
+    // the word index is kept opaque so that its address is one shift-add
+    // (the compiler would otherwise rewrite (x >> 5) << 3 as shift + mask)
+    uint32_t w = x >> 5;
+    asm("" : "+v"(w));
+    const uint2 e = tab[w];
     // the field width of the bit-field extract is taken modulo 32 by the
     // hardware: the low x mod 32 bits
     return e.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(e.x, 0u, x));
@@ -683,11 +687,15 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
     }
     for (int g = 0; g < ngrp; ++g) {
         const int c0 = g * U;
-        uint32_t iv[U], pv[U];
+        uint32_t iv[U] = {}, pv[U];  // iv: sample indices, kept for the debug output only
 #pragma unroll
-        for (int u = 0; u < U; ++u) iv[u] = ivn[u];
-        // prefetch the next group's sample indices (rows are padded, so a
-        // whole group is always inside the row)
+        for (int u = 0; u < U; ++u) pv[u] = posA[ivn[u]];
+        if constexpr (DBG) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) iv[u] = ivn[u];
+        }
+        // prefetch the next group's sample indices into the same registers
+        // (rows are padded, so a whole group is always inside the row)
         if (g + 1 < ngrp) {
 #pragma unroll
             for (int u = 0; u < U; ++u) ivn[u] = ordB[(c0 + U + u) * 64 + lane];
@@ -702,8 +710,6 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
             dbits = (uint32_t)(dmask >> (c0 & 63)) & ((1u << U) - 1u);
         }
         const bool dirty = dbits != 0u;
-#pragma unroll
-        for (int u = 0; u < U; ++u) pv[u] = posA[iv[u]];
         uint32_t t32 = 0;
         if (!dirty) {
 #pragma unroll
