@@ -75,16 +75,34 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum within each row of 16 lanes (DPP row shifts; lanes
+// shifted in from outside the row read 0).
+__device__ __forceinline__ uint32_t row16_incl_scan_u32(uint32_t v)
+{
+    constexpr int ROW_SHR = 0x110;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 1, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 2, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 4, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 8, 0xF, 0xF, false);
+    return (uint32_t)x;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave, in DPP moves: shifts by
+// 1, 2, 4 and 8 lanes within each row of 16 (lanes shifted in from outside
+// the row read 0), then lane 15 of rows 0 and 2 added to rows 1 and 3 and
+// lane 31 added to rows 2 and 3 (row broadcasts of the GFX9 DPP set).
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (l >= d) v += t;
-    }
-    return v;
+    constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 1, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 2, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 4, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 8, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_BCAST15, 0xA, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, ROW_BCAST31, 0xC, 0xF, false);
+    return (uint32_t)x;
 }
 
 __device__ __forceinline__ double wave_sum_f64(double v)

@@ -45,10 +45,10 @@ namespace napy {
 
 constexpr int SORT_THREADS = 1024;  // subset compaction
 constexpr int SPEARMAN_MAX_S = 24576;
-// column sort: 512 threads (8 waves) and up to CS_EPT_MAX keys per thread
-constexpr int CS_THREADS = 512;
+// column sort: 1024 threads (16 waves) and up to CS_EPT_MAX keys per thread
+constexpr int CS_THREADS = 1024;
 constexpr int CS_WAVES = CS_THREADS / 64;
-constexpr int CS_EPT_MAX = SPEARMAN_MAX_S / CS_THREADS;  // 48
+constexpr int CS_EPT_MAX = SPEARMAN_MAX_S / CS_THREADS;  // 24
 
 struct SpearBase {
     uint16_t* ord;     // [F][ld]
@@ -120,20 +120,30 @@ __global__ __launch_bounds__(256) void k_sort_keys(const float* __restrict__ X, 
 // ---------------------------------------------------------------------------
 // per-column sort
 // ---------------------------------------------------------------------------
-// LDS of the column sort, sized by the samples per thread E: keys and
-// sample indices of CS_THREADS * E slots, then the small scan arrays
+// LDS of the column sort, sized by the samples per thread E.  The keys and
+// sample indices of CS_THREADS * E slots share their space with the digit
+// counters of a pass: cnt[k][t] holds thread t's counts of digits 2k (low 16
+// bits) and 2k + 1 (high 16 bits).  Then the per-wave digit totals and the
+// small scan arrays.
 struct SortSmem {
     uint32_t* key;
     uint16_t* idx;
-    uint32_t (*wtot)[8];  // [16][8] per-wave totals of the packed digit counts
-    uint32_t* dbase;      // [16] exclusive offset of each digit
-    int32_t* red;         // [16]
+    uint32_t* cnt;        // [8][CS_THREADS], over key/idx
+    uint32_t (*wtot)[8];  // [CS_WAVES][8] per-wave totals, then per-wave bases
+    int32_t* red;         // [CS_WAVES]
 };
+
+__host__ __device__ inline size_t sort_union_bytes(int E)
+{
+    const size_t cap = (size_t)CS_THREADS * (size_t)E;
+    const size_t kv = (size_t)round_up((int64_t)(cap * 6), 16);
+    const size_t cn = (size_t)8 * CS_THREADS * 4;
+    return kv > cn ? kv : cn;
+}
 
 __host__ __device__ inline size_t sort_smem_bytes(int E)
 {
-    const size_t cap = (size_t)CS_THREADS * (size_t)E;
-    return round_up((int64_t)(cap * 6), 16) + 16 * 8 * 4 + 16 * 4 + 16 * 4;
+    return sort_union_bytes(E) + (size_t)CS_WAVES * 8 * 4 + (size_t)CS_WAVES * 4;
 }
 
 __device__ inline SortSmem sort_smem(unsigned char* raw, int E)
@@ -142,51 +152,22 @@ __device__ inline SortSmem sort_smem(unsigned char* raw, int E)
     SortSmem m;
     m.key = (uint32_t*)raw;
     m.idx = (uint16_t*)(raw + cap * 4);
-    unsigned char* p = raw + round_up((int64_t)(cap * 6), 16);
+    m.cnt = (uint32_t*)raw;
+    unsigned char* p = raw + sort_union_bytes(E);
     m.wtot = (uint32_t(*)[8])p;
-    m.dbase = (uint32_t*)(p + 16 * 8 * 4);
-    m.red = (int32_t*)(p + 16 * 8 * 4 + 16 * 4);
+    m.red = (int32_t*)(p + (size_t)CS_WAVES * 8 * 4);
     return m;
 }
 
-// The digit counters and the packed prefix words are vector values, picked
-// by select trees over constant lanes: a local array read with a runtime
-// index would be placed in scratch memory.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
-
-// 16 digit counters packed as 8-bit fields in four words.
-__device__ __forceinline__ uint32_t cnt_get(u32x4 c, uint32_t d)
-{
-    const uint32_t q = d >> 2;
-    const uint32_t lo = (q & 1) ? c.y : c.x;
-    const uint32_t hi = (q & 1) ? c.w : c.z;
-    const uint32_t w = (q & 2) ? hi : lo;
-    return (w >> (8 * (d & 3))) & 0xFFu;
-}
-__device__ __forceinline__ void cnt_inc(u32x4& c, uint32_t d)
-{
-    const uint32_t inc = 1u << (8 * (d & 3));
-    const uint32_t q = d >> 2;
-    c.x += q == 0 ? inc : 0u;
-    c.y += q == 1 ? inc : 0u;
-    c.z += q == 2 ? inc : 0u;
-    c.w += q == 3 ? inc : 0u;
-}
-
-__device__ __forceinline__ uint32_t sel8(u32x8 w, uint32_t q)
-{
-    const uint32_t a = (q & 1) ? w.s1 : w.s0;
-    const uint32_t b = (q & 1) ? w.s3 : w.s2;
-    const uint32_t c = (q & 1) ? w.s5 : w.s4;
-    const uint32_t d = (q & 1) ? w.s7 : w.s6;
-    const uint32_t ab = (q & 2) ? b : a;
-    const uint32_t cd = (q & 2) ? d : c;
-    return (q & 4) ? cd : ab;
-}
-
-// EPT elements per thread (CS_THREADS * EPT >= S); slots past S hold the
-// "missing" key and sort last
+// One column per workgroup: an LSD radix sort of the keys (8 stable passes of
+// 4-bit digits) with the sample indices as payload, then the tie runs.
+// Thread t holds positions t*E .. t*E+E-1 of the current order (slots past S
+// hold the "missing" key and sort last).  A pass: each thread counts its
+// digits in its own LDS counters (the returned old count is the element's
+// rank among the thread's earlier elements of that digit), the counters are
+// scanned in (digit, thread) order (a wave scan per counter word, the
+// per-wave totals and digit bases by one wave), and each element moves to
+// digit base + count of its digit in earlier threads + its rank.
 template <int EPT>
 __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restrict__ keys, int64_t S,
                                                           int64_t ld, SpearBase out)
@@ -199,16 +180,14 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
     const uint32_t* kc = keys + (int64_t)col * ld;
 
     uint32_t key[EPT];
-    uint16_t idx[EPT];
+    uint32_t pk[EPT];  // sample index (low 16 bits) | rank or destination (high 16 bits)
     int present = 0;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        if (e < E) {
-            const int64_t j = (int64_t)e * CS_THREADS + t;  // striped load, coalesced
-            key[e] = j < S ? kc[j] : 0xFFFFFFFFu;
-            idx[e] = (uint16_t)(j < S ? j : 0xFFFF);
-            present += key[e] != 0xFFFFFFFFu;
-        }
+        const int64_t j = (int64_t)e * CS_THREADS + t;  // striped load, coalesced
+        key[e] = j < S ? kc[j] : 0xFFFFFFFFu;
+        pk[e] = (uint32_t)(j < S ? j : 0xFFFF);
+        present += key[e] != 0xFFFFFFFFu;
     }
     // n_c
     {
@@ -223,79 +202,88 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
     for (int w = 0; w < CS_WAVES; ++w) ncount += sm.red[w];
 
     // The initial order is arbitrary (order among equal keys does not affect
-    // average ranks); each pass below is stable with respect to the sequence
-    // in which thread t holds positions t*E .. t*E+E-1.
+    // average ranks); each pass below is stable with respect to the blocked
+    // order.
+    uint32_t* const mycnt = sm.cnt + t;  // word k at mycnt[k * CS_THREADS]
+    // Register pressure: the empty volatile asm statements below keep the
+    // compiler from hoisting per-element LDS addresses out of the pass loop
+    // and from keeping per-element temporaries alive across the barriers.
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 4 * pass;
-        u32x4 c = {0u, 0u, 0u, 0u};
-        uint8_t lr[EPT];
+        uint32_t tb = (uint32_t)t * E;  // first blocked slot of the thread
+        asm volatile("" : "+v"(tb));
+        // own counters: private to the thread until the scan
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = 0u;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (e < E) {
-                const uint32_t d = (key[e] >> shift) & 15u;
-                lr[e] = (uint8_t)cnt_get(c, d);
-                cnt_inc(c, d);
-            }
+            const uint32_t d = (key[e] >> shift) & 15u;
+            const uint32_t h = (d & 1u) << 4;
+            const uint32_t old = atomicAdd(&mycnt[(d >> 1) * CS_THREADS], 1u << h);
+            pk[e] = (pk[e] & 0xFFFFu) | (((old >> h) & 0xFFFFu) << 16);
+            asm volatile("" : "+v"(pk[e]));
         }
-        // pack into 16-bit fields: w[k] = count(2k) | count(2k+1) << 16
-        uint32_t w[8];
+        uint32_t excl[8];  // exclusive prefix over the wave's threads (packed)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const uint32_t lo = (c[k >> 1] >> (16 * (k & 1))) & 0xFFu;
-            const uint32_t hi = (c[k >> 1] >> (16 * (k & 1) + 8)) & 0xFFu;
-            w[k] = lo | (hi << 16);
-        }
-        uint32_t incl[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) incl[k] = wave_incl_scan_u32(w[k]);
-        if (lane == 63) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sm.wtot[wave][k] = incl[k];
+            const uint32_t own = mycnt[k * CS_THREADS];
+            const uint32_t incl = wave_incl_scan_u32(own);  // packed pairs: no field exceeds 16 bits
+            excl[k] = incl - own;
+            if (lane == 63) sm.wtot[wave][k] = incl;
         }
         __syncthreads();
-        if (t < 16) {
-            // digit totals -> exclusive digit bases
-            uint32_t tot = 0;
-            for (int ww = 0; ww < CS_WAVES; ++ww) tot += (sm.wtot[ww][t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
-            sm.red[t] = (int32_t)tot;
-        }
-        __syncthreads();
-        if (t == 0) {
+        if (wave == 0) {
+            // lane = 16 r + w (w: wave, r: word pair), words k = r and r + 4:
+            // inclusive prefix over the waves within rows of 16 lanes
+            const int w = lane & 15, r = lane >> 4;
+            const uint32_t v0 = sm.wtot[w][r], v1 = sm.wtot[w][r + 4];
+            const uint32_t s0 = row16_incl_scan_u32(v0), s1 = row16_incl_scan_u32(v1);
+            // word totals (last lane of each row), packed digit bases
+            uint32_t pb[8];
             uint32_t run = 0;
-            for (int d = 0; d < 16; ++d) {
-                sm.dbase[d] = run;
-                run += (uint32_t)sm.red[d];
-            }
-        }
-        u32x8 wpre;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            uint32_t s = 0;
-            for (int ww = 0; ww < wave; ++ww) s += sm.wtot[ww][k];
-            wpre[k] = s + incl[k] - w[k];  // exclusive prefix over threads, packed
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t tk = (uint32_t)__builtin_amdgcn_readlane((int)(k < 4 ? s0 : s1), ((k & 3) << 4) | 15);
+                const uint32_t lo = tk & 0xFFFFu, hi = tk >> 16;
+                pb[k] = run | ((run + lo) << 16);
+                run += lo + hi;
+            }
+            const uint32_t b0 = r == 0 ? pb[0] : r == 1 ? pb[1] : r == 2 ? pb[2] : pb[3];
+            const uint32_t b1 = r == 0 ? pb[4] : r == 1 ? pb[5] : r == 2 ? pb[6] : pb[7];
+            sm.wtot[w][r] = b0 + s0 - v0;
+            sm.wtot[w][r + 4] = b1 + s1 - v1;
+        }
+        __syncthreads();
+        // thread t's exclusive offsets per digit pair, into its own counters
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = sm.wtot[wave][k] + excl[k];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            uint32_t kk = key[e];
+            asm volatile("" : "+v"(kk));  // recompute the digit's address
+            const uint32_t d = (kk >> shift) & 15u;
+            const uint32_t off = (mycnt[(d >> 1) * CS_THREADS] >> ((d & 1u) << 4)) & 0xFFFFu;
+            pk[e] += off << 16;  // rank + offset: the destination
+        }
+        __syncthreads();  // counters (over the key slots) read
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const uint32_t dst = pk[e] >> 16;
+            sm.key[dst] = key[e];
+            sm.idx[dst] = (uint16_t)pk[e];
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (e < E) {
-                const uint32_t d = (key[e] >> shift) & 15u;
-                const uint32_t pw = sel8(wpre, d >> 1);
-                const uint32_t pre = (pw >> (16 * (d & 1))) & 0xFFFFu;
-                const uint32_t dst = sm.dbase[d] + pre + lr[e];
-                sm.key[dst] = key[e];
-                sm.idx[dst] = idx[e];
-            }
+            key[e] = sm.key[tb + e];
+            pk[e] = sm.idx[tb + e];
         }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            if (e < E) {
-                key[e] = sm.key[t * E + e];
-                idx[e] = sm.idx[t * E + e];
-            }
-        }
-        __syncthreads();
+        __syncthreads();  // key slots read before the next pass's counters
     }
+    // the sorted keys stay in sm.key (predecessor comparisons below)
+    uint16_t idx[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) idx[e] = (uint16_t)pk[e];
 
     // ---- outputs: positions are t*E + e (blocked), keys in registers ----------
     uint16_t* ordc = out.ord + (int64_t)col * ld;
@@ -1275,11 +1263,14 @@ static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us
     hipLaunchKernelGGL(k_sort_keys, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
     NAPY_TRY(check_launch("sort_keys"));
     const int64_t E = ceil_div(S, CS_THREADS);
-    if (E <= 8) NAPY_TRY(colsort_launch<8>(keys, S, F, base, st));
+    if (E <= 2) NAPY_TRY(colsort_launch<2>(keys, S, F, base, st));
+    else if (E <= 4) NAPY_TRY(colsort_launch<4>(keys, S, F, base, st));
+    else if (E <= 6) NAPY_TRY(colsort_launch<6>(keys, S, F, base, st));
+    else if (E <= 8) NAPY_TRY(colsort_launch<8>(keys, S, F, base, st));
+    else if (E <= 10) NAPY_TRY(colsort_launch<10>(keys, S, F, base, st));
+    else if (E <= 12) NAPY_TRY(colsort_launch<12>(keys, S, F, base, st));
     else if (E <= 16) NAPY_TRY(colsort_launch<16>(keys, S, F, base, st));
     else if (E <= 20) NAPY_TRY(colsort_launch<20>(keys, S, F, base, st));
-    else if (E <= 24) NAPY_TRY(colsort_launch<24>(keys, S, F, base, st));
-    else if (E <= 32) NAPY_TRY(colsort_launch<32>(keys, S, F, base, st));
     else NAPY_TRY(colsort_launch<CS_EPT_MAX>(keys, S, F, base, st));
     return tiebits_launch(base, F, st);
 }
