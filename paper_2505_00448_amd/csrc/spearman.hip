@@ -131,6 +131,7 @@ struct SortSmem {
     uint32_t* cnt;        // [8][CS_THREADS], over key/idx
     uint32_t (*wtot)[8];  // [CS_WAVES][8] per-wave totals, then per-wave bases
     int32_t* red;         // [CS_WAVES]
+    uint32_t* pbase;      // [8] packed digit bases
 };
 
 __host__ __device__ inline size_t sort_union_bytes(int E)
@@ -143,7 +144,7 @@ __host__ __device__ inline size_t sort_union_bytes(int E)
 
 __host__ __device__ inline size_t sort_smem_bytes(int E)
 {
-    return sort_union_bytes(E) + (size_t)CS_WAVES * 8 * 4 + (size_t)CS_WAVES * 4;
+    return sort_union_bytes(E) + (size_t)CS_WAVES * 8 * 4 + (size_t)CS_WAVES * 4 + 8 * 4;
 }
 
 __device__ inline SortSmem sort_smem(unsigned char* raw, int E)
@@ -156,6 +157,7 @@ __device__ inline SortSmem sort_smem(unsigned char* raw, int E)
     unsigned char* p = raw + sort_union_bytes(E);
     m.wtot = (uint32_t(*)[8])p;
     m.red = (int32_t*)(p + (size_t)CS_WAVES * 8 * 4);
+    m.pbase = (uint32_t*)(p + (size_t)CS_WAVES * 8 * 4 + (size_t)CS_WAVES * 4);
     return m;
 }
 
@@ -197,9 +199,8 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
         if (lane == 0) sm.red[wave] = v;
     }
     __syncthreads();
-    int ncount = 0;
-#pragma unroll
-    for (int w = 0; w < CS_WAVES; ++w) ncount += sm.red[w];
+    const int ncount = __builtin_amdgcn_readlane(
+        (int)wave_incl_scan_u32(lane < CS_WAVES ? (uint32_t)sm.red[lane] : 0u), CS_WAVES - 1);
 
     // The initial order is arbitrary (order among equal keys does not affect
     // average ranks); each pass below is stable with respect to the blocked
@@ -223,12 +224,13 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
             pk[e] = (pk[e] & 0xFFFFu) | (((old >> h) & 0xFFFFu) << 16);
             asm volatile("" : "+v"(pk[e]));
         }
-        uint32_t excl[8];  // exclusive prefix over the wave's threads (packed)
+        // own counters -> exclusive prefix over the wave's threads (packed
+        // pairs: no field exceeds 16 bits)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t own = mycnt[k * CS_THREADS];
-            const uint32_t incl = wave_incl_scan_u32(own);  // packed pairs: no field exceeds 16 bits
-            excl[k] = incl - own;
+            const uint32_t incl = wave_incl_scan_u32(own);
+            mycnt[k * CS_THREADS] = incl - own;
             if (lane == 63) sm.wtot[wave][k] = incl;
         }
         __syncthreads();
@@ -248,21 +250,24 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
                 pb[k] = run | ((run + lo) << 16);
                 run += lo + hi;
             }
-            const uint32_t b0 = r == 0 ? pb[0] : r == 1 ? pb[1] : r == 2 ? pb[2] : pb[3];
-            const uint32_t b1 = r == 0 ? pb[4] : r == 1 ? pb[5] : r == 2 ? pb[6] : pb[7];
-            sm.wtot[w][r] = b0 + s0 - v0;
-            sm.wtot[w][r + 4] = b1 + s1 - v1;
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sm.pbase[k] = pb[k];
+            }
+            // (the wave's own LDS accesses complete in order)
+            sm.wtot[w][r] = sm.pbase[r] + s0 - v0;
+            sm.wtot[w][r + 4] = sm.pbase[r + 4] + s1 - v1;
         }
         __syncthreads();
-        // thread t's exclusive offsets per digit pair, into its own counters
-#pragma unroll
-        for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = sm.wtot[wave][k] + excl[k];
+        // offset of digit d for thread t: digit base + earlier waves (wtot)
+        // + earlier threads of the wave (own counters)
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             uint32_t kk = key[e];
             asm volatile("" : "+v"(kk));  // recompute the digit's address
             const uint32_t d = (kk >> shift) & 15u;
-            const uint32_t off = (mycnt[(d >> 1) * CS_THREADS] >> ((d & 1u) << 4)) & 0xFFFFu;
+            const uint32_t pw = mycnt[(d >> 1) * CS_THREADS] + sm.wtot[wave][d >> 1];
+            const uint32_t off = (pw >> ((d & 1u) << 4)) & 0xFFFFu;
             pk[e] += off << 16;  // rank + offset: the destination
         }
         __syncthreads();  // counters (over the key slots) read
@@ -280,27 +285,21 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
         }
         __syncthreads();  // key slots read before the next pass's counters
     }
-    // the sorted keys stay in sm.key (predecessor comparisons below)
-    uint16_t idx[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) idx[e] = (uint16_t)pk[e];
-
-    // ---- outputs: positions are t*E + e (blocked), keys in registers ----------
+    // The sorted keys stay in sm.key (predecessor comparisons below).  From
+    // here pk[e] holds the sample index (low 16 bits) and 1 + the start of
+    // the element's tie run (high 16 bits; 0 while the start lies in an
+    // earlier thread).
     uint16_t* ordc = out.ord + (int64_t)col * ld;
     uint16_t* posc = out.pos + (int64_t)col * ld;
     uint32_t* runc = out.runs + (int64_t)col * ld;
-    // run starts: s(k) = max{j <= k : j == 0 or key[j] != key[j-1]}; the
-    // sorted keys are still in sm.key
+    // run starts: s(k) = max{j <= k : j == 0 or key[j] != key[j-1]}
     int last = -1;
-    int rs[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        if (e < E) {
-            const int k = t * E + e;
-            const bool start = (k == 0) || (k < ncount && key[e] != sm.key[k - 1]);
-            if (k < ncount && start) last = k;
-            rs[e] = last;  // -1 if the start lies in an earlier thread
-        }
+        const int k = t * E + e;
+        const bool start = (k == 0) || (k < ncount && key[e] != sm.key[k - 1]);
+        if (k < ncount && start) last = k;
+        pk[e] = (pk[e] & 0xFFFFu) | ((uint32_t)(last + 1) << 16);
     }
     // block exclusive max-scan of `last`
     int v = last;
@@ -312,34 +311,36 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
     __syncthreads();
     if (lane == 63) sm.red[wave] = v;
     __syncthreads();
-    int before = -1;
-    for (int ww = 0; ww < wave; ++ww) before = max(before, sm.red[ww]);
+    // max over the earlier waves (lanes 0..wave-1 hold their values)
+    int before = lane < wave ? sm.red[lane] : -1;
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1) before = max(before, __shfl_xor(before, d, 16));
+    before = __builtin_amdgcn_readfirstlane(before);
     int excl = __shfl_up(v, 1, 64);
     if (lane == 0) excl = -1;
     before = max(before, excl);
 #pragma unroll
     for (int e = 0; e < EPT; ++e)
-        if (e < E && rs[e] < 0) rs[e] = before;
+        if ((pk[e] >> 16) == 0u) pk[e] |= (uint32_t)(before + 1) << 16;
     __syncthreads();
     uint32_t* END = sm.key;  // reused: END[run start] = run end
     bool tie_here = false;
-    // A run ends at k when k+1 == ncount or rs(k+1) != rs(k).  rs of the
+    // A run ends at k when k+1 == ncount or s(k+1) != s(k).  s of the
     // successor is held by the same thread (e+1) or by thread t+1 (e = 0).
-    int rs_next_first = __shfl_down(rs[0], 1, 64);
+    uint32_t rs_next_first = __shfl_down(pk[0] >> 16, 1, 64);
     __syncthreads();
-    if (lane == 0) sm.red[wave] = rs[0];
+    if (lane == 0) sm.red[wave] = (int32_t)(pk[0] >> 16);
     __syncthreads();
-    if (lane == 63) rs_next_first = (wave + 1 < CS_WAVES) ? sm.red[wave + 1] : -2;
+    if (lane == 63) rs_next_first = (wave + 1 < CS_WAVES) ? (uint32_t)sm.red[wave + 1] : 0xFFFFFFFFu;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        if (e < E) {
-            const int k = t * E + e;
-            if (k < ncount) {
-                const int rn = (k + 1 == ncount) ? -2 : (e + 1 < E ? rs[e + 1] : rs_next_first);
-                if (rn != rs[e]) {
-                    END[rs[e]] = (uint32_t)(k + 1);
-                    if (k > rs[e]) tie_here = true;
-                }
+        const int k = t * E + e;
+        if (k < ncount) {
+            const uint32_t r1 = pk[e] >> 16;  // 1 + run start
+            const uint32_t rn = (k + 1 == ncount) ? 0xFFFFFFFFu : (e + 1 < E ? pk[e + 1] >> 16 : rs_next_first);
+            if (rn != r1) {
+                END[r1 - 1] = (uint32_t)(k + 1);
+                if ((uint32_t)k > r1 - 1) tie_here = true;
             }
         }
     }
@@ -350,22 +351,22 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int k = t * E + e;
-        if (e < E && k < ncount && rs[e] == k && END[k] - (uint32_t)k > 1u) ++nstart;
+        if (k < ncount && (pk[e] >> 16) == (uint32_t)k + 1u && END[k] - (uint32_t)k > 1u) ++nstart;
     }
     const uint32_t sincl = wave_incl_scan_u32(nstart);
     if (lane == 63) sm.red[wave] = (int32_t)sincl;
     __syncthreads();
-    uint32_t rid = sincl - nstart, nrun = 0;
-    for (int ww = 0; ww < CS_WAVES; ++ww) {
-        rid += (ww < wave) ? (uint32_t)sm.red[ww] : 0u;
-        nrun += (uint32_t)sm.red[ww];
-    }
+    // runs of earlier waves and of the column: a scan of the wave counts
+    // held by lanes 0..CS_WAVES-1
+    const uint32_t rsc = wave_incl_scan_u32(lane < CS_WAVES ? (uint32_t)sm.red[lane] : 0u);
+    const uint32_t nrun = (uint32_t)__builtin_amdgcn_readlane((int)rsc, CS_WAVES - 1);
+    uint32_t rid = sincl - nstart + (wave > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)rsc, wave - 1) : 0u);
     uint16_t* RID = sm.idx;  // reused: RID[run start] = run index
     uint32_t* rlc = out.rlist + (int64_t)col * (ld / 2);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int k = t * E + e;
-        if (e < E && k < ncount && rs[e] == k && END[k] - (uint32_t)k > 1u) {
+        if (k < ncount && (pk[e] >> 16) == (uint32_t)k + 1u && END[k] - (uint32_t)k > 1u) {
             RID[k] = (uint16_t)rid;
             rlc[rid] = (uint32_t)k | (END[k] << 16);
             ++rid;
@@ -374,19 +375,19 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        if (e < E) {
-            const int k = t * E + e;
-            if (k < ncount) {
-                ordc[k] = idx[e];
-                // a tied sample's position entry holds the flag bit and its
-                // run index instead of the sorted position
-                const uint32_t run_end = END[rs[e]];
-                const bool tied = run_end - (uint32_t)rs[e] > 1u;
-                posc[idx[e]] = (uint16_t)(tied ? (0x8000u | RID[rs[e]]) : (uint32_t)k);
-                runc[k] = (uint32_t)rs[e] | (run_end << 16);
-            } else if (idx[e] != 0xFFFF) {
-                posc[idx[e]] = 0xFFFF;  // missing sample
-            }
+        const int k = t * E + e;
+        const uint32_t ix = pk[e] & 0xFFFFu;
+        if (k < ncount) {
+            ordc[k] = (uint16_t)ix;
+            // a tied sample's position entry holds the flag bit and its
+            // run index instead of the sorted position
+            const uint32_t rs = (pk[e] >> 16) - 1u;
+            const uint32_t run_end = END[rs];
+            const bool tied = run_end - rs > 1u;
+            posc[ix] = (uint16_t)(tied ? (0x8000u | RID[rs]) : (uint32_t)k);
+            runc[k] = rs | (run_end << 16);
+        } else if (ix != 0xFFFFu) {
+            posc[ix] = 0xFFFF;  // missing sample
         }
     }
     // padding: sorted positions past the observed count hold the dummy
