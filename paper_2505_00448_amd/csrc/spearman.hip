@@ -216,22 +216,36 @@ __global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restri
         // own counters: private to the thread until the scan
 #pragma unroll
         for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = 0u;
+        {
+            // all increments issued before the first returned count is used
+            uint32_t old[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t d = (key[e] >> shift) & 15u;
-            const uint32_t h = (d & 1u) << 4;
-            const uint32_t old = atomicAdd(&mycnt[(d >> 1) * CS_THREADS], 1u << h);
-            pk[e] = (pk[e] & 0xFFFFu) | (((old >> h) & 0xFFFFu) << 16);
-            asm volatile("" : "+v"(pk[e]));
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t d = (key[e] >> shift) & 15u;
+                old[e] = atomicAdd(&mycnt[(d >> 1) * CS_THREADS], 1u << ((d & 1u) << 4));
+            }
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                uint32_t kk = key[e];
+                asm volatile("" : "+v"(kk));  // field shift recomputed, not kept
+                const uint32_t h = ((kk >> shift) & 1u) << 4;
+                pk[e] = (pk[e] & 0xFFFFu) | (((old[e] >> h) & 0xFFFFu) << 16);
+            }
         }
-        // own counters -> exclusive prefix over the wave's threads (packed
-        // pairs: no field exceeds 16 bits)
+        {
+            // own counters -> exclusive prefix over the wave's threads
+            // (packed pairs: no field exceeds 16 bits)
+            uint32_t own[8], incl[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t own = mycnt[k * CS_THREADS];
-            const uint32_t incl = wave_incl_scan_u32(own);
-            mycnt[k * CS_THREADS] = incl - own;
-            if (lane == 63) sm.wtot[wave][k] = incl;
+            for (int k = 0; k < 8; ++k) own[k] = mycnt[k * CS_THREADS];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) incl[k] = wave_incl_scan_u32(own[k]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = incl[k] - own[k];
+            if (lane == 63) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sm.wtot[wave][k] = incl[k];
+            }
         }
         __syncthreads();
         if (wave == 0) {
