@@ -61,9 +61,9 @@ FP32_MFMA_PEAK_FLOPS = 157.3e12
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "872a8cf9334bd2c7327d9c8762bfd0c5113029478445f8cec877aec72f80c6ae",
-    "fetch_kib": 161512.2,
-    "write_kib": 35006.3,
+    "source_sha256": "dcab5349c4e5d04a8cefe262c7bac29d3930c08bc12ed6120f3be52e51c2e068",
+    "fetch_kib": 141720.3,
+    "write_kib": 34861.8,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
