@@ -146,7 +146,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--form", default="headline",
-                    choices=["headline", "precision", "serving", "differentiation", "copy"])
+                    choices=["headline", "precision", "serving", "differentiation", "copy", "adjust"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
     ap.add_argument("--warmup-queries", type=int, default=100, help="serving: warm-up queries")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -171,6 +171,8 @@ def main() -> int:
         return run_differentiation(args)
     if args.form == "precision":
         return run_precision(args)
+    if args.form == "adjust":
+        return run_adjust(args)
 
     import numpy as np
     import torch
@@ -422,6 +424,76 @@ def run_differentiation(args) -> int:
         "fp32": out["fp32"], "bf16x3": out["bf16x3"],
     }
     print(json.dumps(res))
+    return 0
+
+
+def run_adjust(args) -> int:
+    """Multiple-testing correction of all-pairs p matrices (Bonferroni,
+    Benjamini-Hochberg, Benjamini-Yekutieli) at 1,000 and 4,000 variables,
+    plus the oracle's time on the host for the 1,000-variable matrix."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_00448_amd import _lib
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    hip = HipEvents()
+    e0, e1 = hip.new(), hip.new()
+    hip.rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    res = {}
+    for F in (1000, 4000):
+        Pm = torch.from_numpy(synth.pvalue_matrix(F)).to(dev)
+        out = torch.empty_like(Pm)
+        ws = torch.empty(lib.napy_adjust_workspace(F), dtype=torch.uint8, device=dev)
+        npairs = F * (F - 1) // 2
+        N = 4096
+        while N < npairs:
+            N *= 2
+        lg = int(math.log2(N // 4096))
+        # bitonic network over N elements of 12 B: lg (lg + 1) / 2 global steps
+        # and lg + 1 LDS tile passes, each reading and writing every element
+        sort_bytes = (lg * (lg + 1) // 2 + lg + 1) * 2 * 12 * N
+        row = {"pairs": npairs, "padded": N}
+        for name, code in (("bonferroni", 0), ("bh", 1), ("by", 2)):
+            def step():
+                hip.rt.hipEventRecord(e0, sh)
+                st = lib.napy_adjust_pvalues(P(Pm), F, F, P(out), F, code, P(ws), ws.numel(), sh)
+                _lib.check(st, "napy_adjust_pvalues")
+                hip.rt.hipEventRecord(e1, sh)
+            for _ in range(args.warmup):
+                step()
+            ts = []
+            for _ in range(max(args.steps, 5)):
+                step()
+                torch.cuda.synchronize(dev)
+                ts.append(hip.ms(e0, e1))
+            ms = float(np.median(ts))
+            row[name] = {"ms": ms, "pairs_per_s": npairs / (ms * 1e-3)}
+            if code != 0:
+                row[name]["sort_network_GBps"] = sort_bytes / (ms * 1e-3) / 1e9
+        res[str(F)] = row
+    hip.close()
+    cpu = {}
+    if not args.no_cpu_baseline:
+        from oracle import adjust as oadj
+        Ph = synth.pvalue_matrix(1000)
+        t0 = time.perf_counter()
+        oadj.adjust_matrix(Ph, "bh")
+        cpu = {"value": (time.perf_counter() - t0) * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+               "sample": "Benjamini-Hochberg on the whole 1,000-variable matrix (numpy, one thread)"}
+    print(json.dumps({
+        "metric": "adjust form: multiple-testing correction of an all-pairs p matrix",
+        "value": res["1000"]["bh"]["ms"], "unit": "ms per correction (Benjamini-Hochberg, 1,000 variables)",
+        "n_gpus": 1, "higher_is_better": False, "form": "adjust", "data": "synthetic",
+        "config": {"workload": "symmetric p matrices: 30% log-uniform on [1e-12, 1], 70% uniform, 20% rounded "
+                               "to 2 decimals, 2% undefined", "variables": [1000, 4000]},
+        "results": res, "cpu_baseline": cpu or None,
+    }))
     return 0
 
 

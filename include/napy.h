@@ -195,6 +195,36 @@ int napy_spearman_subset(const void* base, int64_t S, int64_t F,
                          void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Multiple-testing correction of an all-pairs p matrix (Section 3.4).
+ *
+ * The tests are the unordered pairs {i, j}, i != j, whose p-value is defined:
+ * the upper triangle (i < j) of p is read, NaN entries are not tests, and m
+ * is the number of the others.  With those m values in ascending order
+ * p_(1) <= ... <= p_(m):
+ *   NAPY_ADJ_BONFERRONI  min(1, m p)                    (Dunn 1961)
+ *   NAPY_ADJ_BH          min(1, min_{l >= k} m p_(l) / l) for p = p_(k)
+ *                        (Benjamini-Hochberg step-up)
+ *   NAPY_ADJ_BY          as BH with m replaced by m c(m),
+ *                        c(m) = sum_{i=1..m} 1/i (Benjamini-Yekutieli)
+ * The result is written to both triangles of out (F x F float64, ld ldo >= F);
+ * the diagonal (self-tests, not counted) and undefined pairs are NaN.  p holds
+ * values in [0, 1] or NaN (anything else is a precondition violation) and is
+ * read only: out may equal p (then ldo == ldp), any other overlap is not
+ * allowed.  1 <= F <= 65535.  napy_adjust_workspace(F) bytes of workspace
+ * (pure host function; about 12 B per pair rounded up to a power of two).
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    NAPY_ADJ_BONFERRONI = 0,
+    NAPY_ADJ_BH = 1,
+    NAPY_ADJ_BY = 2
+} napy_adjust_method;
+
+size_t napy_adjust_workspace(int64_t F);
+
+int napy_adjust_pvalues(const double* p, int64_t F, int64_t ldp, double* out, int64_t ldo,
+                        int32_t method, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Test hooks (not part of the computation path).
  *
  * napy_spearman_pair_ranks: the doubled average ranks 2*rank that the

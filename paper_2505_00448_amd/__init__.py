@@ -17,4 +17,5 @@ from .api import (  # noqa: F401,E402
     SpearmanBase,
     spearman_pair_ranks,
     pvalue_device,
+    adjust_pvalues,
 )

@@ -32,6 +32,7 @@ EXPORTS = [
     "napy_spearman_base_bytes", "napy_spearman_base_prepare",
     "napy_spearman_subset_workspace", "napy_spearman_subset",
     "napy_spearman_pair_ranks", "napy_pvalue_device", "napy_pvalue_host",
+    "napy_adjust_workspace", "napy_adjust_pvalues",
 ]
 
 
@@ -84,6 +85,8 @@ def load() -> ctypes.CDLL:
         "napy_spearman_pair_ranks": (ctypes.c_int, [P, i64, i64, i64, i32, i32, P, P, P, sz, O, P]),
         "napy_pvalue_device": (ctypes.c_int, [P, P, P, i64, P]),
         "napy_pvalue_host": (ctypes.c_int, [P, P, P, i64]),
+        "napy_adjust_workspace": (sz, [i64]),
+        "napy_adjust_pvalues": (ctypes.c_int, [P, i64, i64, P, i64, i32, P, sz, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -117,6 +117,40 @@ def spearman_pair_ranks(X: torch.Tensor, g: int, h: int, missing: Optional[float
     return rg[:S], rh[:S]
 
 
+_ADJUST = {"bonferroni": 0, "bh": 1, "by": 2}
+
+
+def adjust_pvalues(P: torch.Tensor, method: str = "bh", out: Optional[torch.Tensor] = None,
+                   workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Multiple-testing correction of a symmetric F x F p matrix (NApy,
+    Section 3.4): "bonferroni", "bh" (Benjamini-Hochberg) or "by"
+    (Benjamini-Yekutieli).  The tests are the pairs i < j with a defined p;
+    the diagonal and undefined pairs are NaN in the result.  ``out`` may be
+    ``P`` itself (in-place)."""
+    if method not in _ADJUST:
+        raise ValueError(f"method must be one of {sorted(_ADJUST)}")
+    if not isinstance(P, torch.Tensor) or P.dim() != 2 or P.shape[0] != P.shape[1]:
+        raise TypeError("P must be a square 2-D torch tensor")
+    if not P.is_cuda:
+        raise ValueError("P must be a CUDA (ROCm) tensor on the MI355X")
+    lib = _lib.load()
+    if P.dtype != torch.float64 or P.stride(1) != 1:
+        P = P.to(torch.float64).contiguous()
+    F = P.shape[0]
+    if out is None:
+        out = torch.empty((F, F), dtype=torch.float64, device=P.device)
+    elif out.shape != P.shape or out.dtype != torch.float64 or out.stride(1) != 1 or out.device != P.device:
+        raise ValueError("out must be a float64 F x F row-major tensor on P's device")
+    need = lib.napy_adjust_workspace(F)
+    if need == 0:
+        raise _lib.NapyError(_lib.NAPY_E_UNSUPPORTED, f"napy_adjust_workspace({F}) refused the shape")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, P.device)
+    st = lib.napy_adjust_pvalues(_ptr(P), F, P.stride(0), _ptr(out), out.stride(0), _ADJUST[method],
+                                 _ptr(ws), ws.numel(), _stream_handle(P.device))
+    _lib.check(st, "napy_adjust_pvalues")
+    return out
+
+
 def pvalue_device(r: torch.Tensor, n: torch.Tensor) -> torch.Tensor:
     """Test hook: the library's device p-value routine on (r, n) arrays."""
     lib = _lib.load()

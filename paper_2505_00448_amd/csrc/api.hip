@@ -41,6 +41,10 @@ size_t spearman_subset_ws_bytes(int64_t S, int64_t Sq, int64_t Fq);
 int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t* rows, int64_t Sq,
                         const int32_t* cols, int64_t Fq, double* r, double* p, int32_t* n, int64_t ldo,
                         void* ws, hipStream_t st);
+// multiple-testing correction (adjust.hip)
+size_t adjust_ws_bytes(int64_t F);
+int adjust_run(const double* p, int64_t F, int64_t ldp, double* out, int64_t ldo, int method, void* ws,
+               hipStream_t st);
 // backward (backward.hip)
 size_t backward_ws_bytes(int64_t S, int64_t F);
 int backward_run(const float* X, int64_t S, int64_t F, int64_t ldx, const double* saved, const float* dR,
@@ -257,6 +261,34 @@ int napy_spearman_pair_ranks(const float* X, int64_t S, int64_t F, int64_t ldx, 
     if ((!rank2_g || !rank2_h) && S > 0) return NAPY_E_INVALID;
     if (!ws || ws_bytes < spearman_ws_bytes(S, F) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
     return spearman_pair_ranks_run(X, S, F, ldx, g, h, rank2_g, rank2_h, ws, opts, (hipStream_t)stream);
+}
+
+size_t napy_adjust_workspace(int64_t F)
+{
+    if (F < 1 || F > MAX_F) return 0;
+    return adjust_ws_bytes(F);
+}
+
+int napy_adjust_pvalues(const double* p, int64_t F, int64_t ldp, double* out, int64_t ldo, int32_t method,
+                        void* ws, size_t ws_bytes, void* stream)
+{
+    if (F < 1) return NAPY_E_INVALID;
+    if (F > MAX_F) {
+        set_last_error("F=%lld outside the supported range", (long long)F);
+        return NAPY_E_UNSUPPORTED;
+    }
+    if (!p || !out || ldp < F || ldo < F) return NAPY_E_INVALID;
+    if (method != NAPY_ADJ_BONFERRONI && method != NAPY_ADJ_BH && method != NAPY_ADJ_BY) return NAPY_E_INVALID;
+    if ((const void*)out == (const void*)p) {
+        if (ldo != ldp) return NAPY_E_INVALID;
+    } else {
+        // any other overlap of the two F x F matrices is refused
+        const uintptr_t pa = (uintptr_t)p, pb = pa + (uintptr_t)((F - 1) * ldp + F) * sizeof(double);
+        const uintptr_t oa = (uintptr_t)out, ob = oa + (uintptr_t)((F - 1) * ldo + F) * sizeof(double);
+        if (pa < ob && oa < pb) return NAPY_E_INVALID;
+    }
+    if (!ws || ws_bytes < adjust_ws_bytes(F) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return adjust_run(p, F, ldp, out, ldo, method, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -18,4 +18,5 @@ from .workloads import (  # noqa: F401
     paper_shape,
     heavy_ties,
     edge_matrix,
+    pvalue_matrix,
 )

@@ -214,3 +214,26 @@ def edge_matrix() -> np.ndarray:
         [-0.0, 0.0, 1.0, -1.0, n, 2.0, -0.0, 0.5],     # 9 signed zeros tie
     ]
     return np.array(cols, dtype=np.float32).T.copy()
+
+
+def pvalue_matrix(F: int, seed: int = SEED_BASE + 12, nan_frac: float = 0.02,
+                  tie_frac: float = 0.2) -> np.ndarray:
+    """Symmetric F x F float64 matrix of p-values for the multiple-testing
+    correction: 30% log-uniform on [1e-12, 1] (strong associations), the rest
+    uniform on [0, 1) (null pairs); a tie_frac share rounded to 2 decimals
+    (groups of equal values); the first two pairs exactly 0 and 1; a nan_frac
+    share undefined (NaN).  The diagonal holds 0.5 (it is not a test)."""
+    rng = _rng(seed)
+    n = F * (F - 1) // 2
+    v = np.where(rng.random(n) < 0.3, 10.0 ** -rng.uniform(0, 12, n), rng.random(n))
+    tie = rng.random(n) < tie_frac
+    v[tie] = np.round(v[tie], 2)
+    if n > 4:
+        v[0] = 0.0
+        v[1] = 1.0
+    v[rng.random(n) < nan_frac] = np.nan
+    P = np.full((F, F), 0.5)
+    iu, ju = np.triu_indices(F, 1)
+    P[iu, ju] = v
+    P[ju, iu] = v
+    return P

@@ -149,3 +149,35 @@ def test_pvalue_arithmetic_against_mpmath():
             assert pv < 1e-290
         else:
             assert abs(pv - ref) <= 1e-12 * ref, (r, n, pv, ref)
+
+
+def test_adjust_arguments_rejected_on_host():
+    lib = _lib.load()
+    need = lib.napy_adjust_workspace(10)
+    assert need > 0 and lib.napy_adjust_workspace(0) == 0 and lib.napy_adjust_workspace(65536) == 0
+    # the workspace covers keys, indices and block minima of the padded pair count
+    assert lib.napy_adjust_workspace(1000) >= 524288 * 12
+    P = ctypes.c_void_p(0x100000)
+    OUT = ctypes.c_void_p(0x900000)
+    WS = ctypes.c_void_p(0x2000000)
+    ok = dict(p=P, F=10, ldp=10, out=OUT, ldo=10, method=1, ws=WS, nb=need)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.napy_adjust_pvalues(a["p"], a["F"], a["ldp"], a["out"], a["ldo"], a["method"],
+                                       a["ws"], a["nb"], None)
+
+    assert call(F=0) == _lib.NAPY_E_INVALID
+    assert call(F=65536) == _lib.NAPY_E_UNSUPPORTED
+    assert call(p=None) == _lib.NAPY_E_INVALID
+    assert call(out=None) == _lib.NAPY_E_INVALID
+    assert call(ldp=9) == _lib.NAPY_E_INVALID
+    assert call(ldo=9) == _lib.NAPY_E_INVALID
+    assert call(method=3) == _lib.NAPY_E_INVALID
+    assert call(method=-1) == _lib.NAPY_E_INVALID
+    # in place needs equal leading dimensions; partial overlap is refused
+    assert call(out=P, ldo=11, ldp=10) == _lib.NAPY_E_INVALID
+    assert call(out=ctypes.c_void_p(0x100000 + 8 * 50)) == _lib.NAPY_E_INVALID
+    assert call(ws=None) == _lib.NAPY_E_WORKSPACE
+    assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
+    assert call(ws=ctypes.c_void_p(0x2000000 + 64)) == _lib.NAPY_E_WORKSPACE
