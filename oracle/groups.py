@@ -34,6 +34,10 @@ Readings (the paper does not spell these out):
     zero-variance rule.
   * Zero variance is exact: every value of the group is equal (minimum ==
     maximum), not a computed variance below a threshold.
+  * A column that is not label-encoded as the test needs (a label that is not
+    an integer, negative, at or above the caller's category bound, or for the
+    t-test not 0 or 1) is not tested: its statistics and p-values are NaN and
+    its counts 0.
 """
 
 from __future__ import annotations
@@ -117,11 +121,13 @@ def ttest(L: np.ndarray, X: np.ndarray, welch: bool = False, missing: Optional[f
                 dichotomous=True)
 
 
-def anova(L: np.ndarray, X: np.ndarray, missing: Optional[float] = None, pairs=None):
-    return _run(L, X, missing, pairs, anova_groups, dichotomous=False)
+def anova(L: np.ndarray, X: np.ndarray, missing: Optional[float] = None, pairs=None,
+          ncat: Optional[int] = None):
+    """ncat: labels must lie in [0, ncat) (no bound if None)."""
+    return _run(L, X, missing, pairs, anova_groups, dichotomous=False, ncat=ncat)
 
 
-def _run(L, X, missing, pairs, test, dichotomous: bool):
+def _run(L, X, missing, pairs, test, dichotomous: bool, ncat: Optional[int] = None):
     L = np.asarray(L, dtype=np.float32)
     X = np.asarray(X, dtype=np.float32)
     S, FC = L.shape
@@ -133,6 +139,8 @@ def _run(L, X, missing, pairs, test, dichotomous: bool):
         col, ok = _labels(L[:, i], mL[:, i])
         labs = np.unique(col[~mL[:, i]]) if ok else None
         if dichotomous and labs is not None and not np.all(np.isin(labs, [0.0, 1.0])):
+            labs = None
+        if ncat is not None and labs is not None and labs.size and labs.max() >= ncat:
             labs = None
         if dichotomous and labs is not None:
             labs = np.array([0.0, 1.0])  # both groups are required
@@ -154,7 +162,7 @@ def _run(L, X, missing, pairs, test, dichotomous: bool):
         n = int(keep.sum())
         labs = cats[i]
         if labs is None:
-            put(k, i, j, np.nan, np.nan, n)
+            put(k, i, j, np.nan, np.nan, 0)
             continue
         lab = L[keep, i]
         y = X[keep, j].astype(np.float64)

@@ -100,8 +100,12 @@ def test_matrix_pairwise_deletion_by_hand():
         ref = stats.ttest_ind(y0, y1, equal_var=False)
         np.testing.assert_allclose([t[1, j], pt[1, j]], [ref.statistic, ref.pvalue], rtol=1e-10)
         assert nt[1, j] == keep.sum()
-    # column 0 has three labels: not dichotomous, so its t-tests are NaN
-    assert np.all(np.isnan(t[0]))
+    # column 0 has three labels: not dichotomous, so its t-tests are NaN, n 0
+    assert np.all(np.isnan(t[0])) and np.all(nt[0] == 0)
+    # a category bound below the largest label: column 0 not tested
+    F2, _, n2 = og.anova(L, X, ncat=2)
+    assert np.all(np.isnan(F2[0])) and np.all(n2[0] == 0)
+    np.testing.assert_array_equal(F2[1], F[1])
 
 
 def test_sentinel_and_listed_pairs():
