@@ -225,6 +225,50 @@ int napy_adjust_pvalues(const double* p, int64_t F, int64_t ldp, double* out, in
                         int32_t method, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Categorical x continuous tests with pairwise deletion (Section 3.5):
+ * two-sample t-test (Student or Welch) and one-way ANOVA.
+ *
+ * L is S x FC float32 (leading dimension ldl >= FC) holding label-encoded
+ * categorical features (Section 3.3: integers from 0); X is S x FQ float32
+ * (ldx >= FQ) holding continuous features; missing values as for napy_pearson
+ * (NaN, or opts->sentinel with use_sentinel).  Each pair (g, h) uses the
+ * samples where both L[., g] and X[., h] are present.  Outputs are FC x FQ
+ * row-major with leading dimension ldo >= FQ, entry (g, h) for categorical
+ * feature g and continuous feature h (Section 3.4): the statistic (t or F,
+ * float64), its two-sided p-value (float64) and n = |I(g, h)| (int32).  All
+ * three output pointers are required.
+ *
+ * napy_ttest: groups are label 0 and label 1, t = (mean_0 - mean_1) / se;
+ *   welch = 0 Student (pooled variance, df = n0 + n1 - 2), 1 Welch
+ *   (Welch-Satterthwaite df); p from the t distribution.  NaN when a group
+ *   has fewer than two samples, and for Student when the pooled variance is
+ *   zero; Welch with both variances zero gives t = +-inf, p = 0 when the means
+ *   differ, NaN when they are equal.
+ * napy_anova: the categories of a column are the labels observed anywhere in
+ *   it; labels must lie in [0, ncat), 2 <= ncat <= 32.  F = (SSB / (K - 1)) /
+ *   (SSW / (N - K)), p from Fisher's F distribution.  NaN when a category is
+ *   empty within I(g, h) or the column has one category; when every
+ *   within-category variance is zero, F = inf and p = 0 unless all category
+ *   means are equal (then NaN).
+ * A categorical column with a label outside what the test accepts (not an
+ *   integer, negative, >= ncat, or for the t-test not 0 or 1) is not tested:
+ *   its statistics and p are NaN and n is 0.
+ * Variances and means are decided zero/equal within 1e-10 relative (FP64
+ * sums).  The contractions run on FP64 matrix cores.
+ * ------------------------------------------------------------------------ */
+size_t napy_ttest_workspace(int64_t S, int64_t FC, int64_t FQ, const napy_opts* opts);
+
+int napy_ttest(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+               int32_t welch, double* t, double* p, int32_t* n, int64_t ldo,
+               void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+size_t napy_anova_workspace(int64_t S, int64_t FC, int64_t FQ, int32_t ncat, const napy_opts* opts);
+
+int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+               int32_t ncat, double* F, double* p, int32_t* n, int64_t ldo,
+               void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
  * Test hooks (not part of the computation path).
  *
  * napy_spearman_pair_ranks: the doubled average ranks 2*rank that the
@@ -246,6 +290,12 @@ int napy_spearman_pair_ranks(const float* X, int64_t S, int64_t F, int64_t ldx,
 int napy_pvalue_device(const double* r, const int32_t* n, double* p, int64_t count, void* stream);
 
 int napy_pvalue_host(const double* r, const int32_t* n, double* p, int64_t count);
+
+/* napy_fdist_sf_host: the library's F-distribution survival function
+ * P(F' > f; d1, d2) (used for the t-test as P(F' > t^2; 1, df) and for ANOVA)
+ * compiled for the host, on host arrays; for checking the arithmetic without a
+ * GPU. */
+int napy_fdist_sf_host(const double* f, const double* d1, const double* d2, double* p, int64_t count);
 
 #ifdef __cplusplus
 }

@@ -18,4 +18,6 @@ from .api import (  # noqa: F401,E402
     spearman_pair_ranks,
     pvalue_device,
     adjust_pvalues,
+    ttest,
+    anova,
 )

@@ -33,6 +33,7 @@ EXPORTS = [
     "napy_spearman_subset_workspace", "napy_spearman_subset",
     "napy_spearman_pair_ranks", "napy_pvalue_device", "napy_pvalue_host",
     "napy_adjust_workspace", "napy_adjust_pvalues",
+    "napy_ttest_workspace", "napy_ttest", "napy_anova_workspace", "napy_anova", "napy_fdist_sf_host",
 ]
 
 
@@ -87,6 +88,11 @@ def load() -> ctypes.CDLL:
         "napy_pvalue_host": (ctypes.c_int, [P, P, P, i64]),
         "napy_adjust_workspace": (sz, [i64]),
         "napy_adjust_pvalues": (ctypes.c_int, [P, i64, i64, P, i64, i32, P, sz, P]),
+        "napy_ttest_workspace": (sz, [i64, i64, i64, O]),
+        "napy_ttest": (ctypes.c_int, [P, i64, P, i64, i64, i64, i64, i32, P, P, P, i64, P, sz, O, P]),
+        "napy_anova_workspace": (sz, [i64, i64, i64, i32, O]),
+        "napy_anova": (ctypes.c_int, [P, i64, P, i64, i64, i64, i64, i32, P, P, P, i64, P, sz, O, P]),
+        "napy_fdist_sf_host": (ctypes.c_int, [P, P, P, P, i64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

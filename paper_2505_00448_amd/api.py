@@ -117,6 +117,60 @@ def spearman_pair_ranks(X: torch.Tensor, g: int, h: int, missing: Optional[float
     return rg[:S], rh[:S]
 
 
+def _groups_call(kind: str, L: torch.Tensor, X: torch.Tensor, welch: bool, ncat: Optional[int],
+                 missing: Optional[float], samples_axis: int, workspace: Optional[torch.Tensor]) -> dict:
+    lib = _lib.load()
+    L = _prep_input(L, samples_axis, False)
+    X = _prep_input(X, samples_axis, True)
+    if L.shape[0] != X.shape[0] or L.device != X.device:
+        raise ValueError("L and X must have the same samples on the same device")
+    S, FC = L.shape
+    FQ = X.shape[1]
+    opts = _lib.make_opts("fp64", missing)
+    if kind == "ttest":
+        need = lib.napy_ttest_workspace(S, FC, FQ, ctypes.byref(opts))
+    else:
+        if ncat is None:
+            # largest observed label + 1 (one device reduction)
+            lab = L if missing is None else torch.where(L == missing, torch.nan, L)
+            mx = torch.nan_to_num(lab, nan=-1.0).max() if L.numel() else torch.tensor(-1.0)
+            ncat = max(2, int(mx.item()) + 1)
+        need = lib.napy_anova_workspace(S, FC, FQ, int(ncat), ctypes.byref(opts))
+    if need == 0:
+        raise _lib.NapyError(_lib.NAPY_E_UNSUPPORTED, f"{kind} workspace refused S={S} FC={FC} FQ={FQ}")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+    stat = torch.empty((FC, FQ), dtype=torch.float64, device=X.device)
+    p = torch.empty((FC, FQ), dtype=torch.float64, device=X.device)
+    n = torch.empty((FC, FQ), dtype=torch.int32, device=X.device)
+    if kind == "ttest":
+        st = lib.napy_ttest(_ptr(L), L.stride(0), _ptr(X), X.stride(0), S, FC, FQ, int(bool(welch)), _ptr(stat),
+                            _ptr(p), _ptr(n), FQ, _ptr(ws), ws.numel(), ctypes.byref(opts),
+                            _stream_handle(X.device))
+        _lib.check(st, "napy_ttest")
+        return {"t": stat, "p": p, "n": n}
+    st = lib.napy_anova(_ptr(L), L.stride(0), _ptr(X), X.stride(0), S, FC, FQ, int(ncat), _ptr(stat), _ptr(p),
+                        _ptr(n), FQ, _ptr(ws), ws.numel(), ctypes.byref(opts), _stream_handle(X.device))
+    _lib.check(st, "napy_anova")
+    return {"F": stat, "p": p, "n": n}
+
+
+def ttest(L: torch.Tensor, X: torch.Tensor, welch: bool = False, missing: Optional[float] = None,
+          samples_axis: int = 0, workspace: Optional[torch.Tensor] = None) -> dict:
+    """Two-sample t-tests of every dichotomous column of L (labels 0/1)
+    against every continuous column of X with pairwise deletion (NApy,
+    Section 3.5): {"t", "p", "n"}, FC x FQ.  welch=False: Student."""
+    return _groups_call("ttest", L, X, welch, None, missing, samples_axis, workspace)
+
+
+def anova(L: torch.Tensor, X: torch.Tensor, ncat: Optional[int] = None, missing: Optional[float] = None,
+          samples_axis: int = 0, workspace: Optional[torch.Tensor] = None) -> dict:
+    """One-way ANOVA of every categorical column of L (labels 0 .. ncat-1)
+    against every continuous column of X with pairwise deletion (NApy,
+    Section 3.5): {"F", "p", "n"}, FC x FQ.  ncat defaults to the largest
+    observed label + 1."""
+    return _groups_call("anova", L, X, False, ncat, missing, samples_axis, workspace)
+
+
 _ADJUST = {"bonferroni": 0, "bh": 1, "by": 2}
 
 

@@ -45,6 +45,11 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
 size_t adjust_ws_bytes(int64_t F);
 int adjust_run(const double* p, int64_t F, int64_t ldp, double* out, int64_t ldo, int method, void* ws,
                hipStream_t st);
+// categorical x continuous tests (groups.hip)
+size_t groups_ws_bytes(int64_t S, int64_t FC, int64_t FQ, int ncat);
+int groups_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+               int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws, const napy_opts* opts,
+               hipStream_t st);
 // backward (backward.hip)
 size_t backward_ws_bytes(int64_t S, int64_t F);
 int backward_run(const float* X, int64_t S, int64_t F, int64_t ldx, const double* saved, const float* dR,
@@ -261,6 +266,64 @@ int napy_spearman_pair_ranks(const float* X, int64_t S, int64_t F, int64_t ldx, 
     if ((!rank2_g || !rank2_h) && S > 0) return NAPY_E_INVALID;
     if (!ws || ws_bytes < spearman_ws_bytes(S, F) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
     return spearman_pair_ranks_run(X, S, F, ldx, g, h, rank2_g, rank2_h, ws, opts, (hipStream_t)stream);
+}
+
+static int check_groups(int64_t S, int64_t FC, int64_t FQ, int ncat)
+{
+    if (S < 0 || FC < 1 || FQ < 1) return NAPY_E_INVALID;
+    if (ncat < 2 || ncat > 32) return NAPY_E_INVALID;
+    if (FC > MAX_F || FQ > MAX_F || S > MAX_S || FC * ncat * FQ > (int64_t)4000000000LL) {
+        set_last_error("shape S=%lld FC=%lld FQ=%lld ncat=%d outside the supported range", (long long)S,
+                       (long long)FC, (long long)FQ, ncat);
+        return NAPY_E_UNSUPPORTED;
+    }
+    return NAPY_OK;
+}
+
+static int groups_call(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                       int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws,
+                       size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    NAPY_TRY(check_groups(S, FC, FQ, ncat));
+    if (S > 0 && (!L || !X)) return NAPY_E_INVALID;
+    if (ldl < FC || ldx < FQ || ldo < FQ || !stat || !p || !n) return NAPY_E_INVALID;
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < groups_ws_bytes(S, FC, FQ, ncat) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return groups_run(L, ldl, X, ldx, S, FC, FQ, test, ncat, stat, p, n, ldo, ws, opts, (hipStream_t)stream);
+}
+
+size_t napy_ttest_workspace(int64_t S, int64_t FC, int64_t FQ, const napy_opts* opts)
+{
+    if (check_groups(S, FC, FQ, 2) != NAPY_OK || !opts_ok(opts)) return 0;
+    return groups_ws_bytes(S, FC, FQ, 2);
+}
+
+int napy_ttest(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+               int32_t welch, double* t, double* p, int32_t* n, int64_t ldo, void* ws, size_t ws_bytes,
+               const napy_opts* opts, void* stream)
+{
+    if (welch != 0 && welch != 1) return NAPY_E_INVALID;
+    return groups_call(L, ldl, X, ldx, S, FC, FQ, welch, 2, t, p, n, ldo, ws, ws_bytes, opts, stream);
+}
+
+size_t napy_anova_workspace(int64_t S, int64_t FC, int64_t FQ, int32_t ncat, const napy_opts* opts)
+{
+    if (check_groups(S, FC, FQ, ncat) != NAPY_OK || !opts_ok(opts)) return 0;
+    return groups_ws_bytes(S, FC, FQ, ncat);
+}
+
+int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+               int32_t ncat, double* F, double* p, int32_t* n, int64_t ldo, void* ws, size_t ws_bytes,
+               const napy_opts* opts, void* stream)
+{
+    return groups_call(L, ldl, X, ldx, S, FC, FQ, 2, ncat, F, p, n, ldo, ws, ws_bytes, opts, stream);
+}
+
+int napy_fdist_sf_host(const double* f, const double* d1, const double* d2, double* p, int64_t count)
+{
+    if (count < 0 || (count > 0 && (!f || !d1 || !d2 || !p))) return NAPY_E_INVALID;
+    for (int64_t i = 0; i < count; ++i) p[i] = fdist_sf(f[i], d1[i], d2[i]);
+    return NAPY_OK;
 }
 
 size_t napy_adjust_workspace(int64_t F)

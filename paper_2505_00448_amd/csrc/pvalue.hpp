@@ -123,4 +123,52 @@ NAPY_HD inline double corr_pvalue(double r, int64_t n)
     return p < 0.0 ? 0.0 : p;
 }
 
+// ln G(a + b) - ln G(a) for a, b > 0.  For a >= 20 from Stirling's series of
+// both log-gammas, arranged so that nothing large cancels:
+//   (a - 1/2) log1p(b/a) + b ln(a + b) - b + [s(a + b) - s(a)],
+//   s(z) = 1/(12z) - 1/(360z^3) + 1/(1260z^5) - 1/(1680z^7)
+// (the next term is below 1e-12 / z^9); below that from lgamma directly.
+NAPY_HD inline double stirling_tail(double z)
+{
+    const double iz = 1.0 / z, iz2 = iz * iz;
+    return iz * (1.0 / 12.0 - iz2 * (1.0 / 360.0 - iz2 * (1.0 / 1260.0 - iz2 * (1.0 / 1680.0))));
+}
+
+NAPY_HD inline double lgamma_ratio(double a, double b)
+{
+    if (a >= 20.0)
+        return (a - 0.5) * log1p(b / a) + b * log(a + b) - b + (stirling_tail(a + b) - stirling_tail(a));
+    return lgamma(a + b) - lgamma(a);
+}
+
+// Survival function of Fisher's F distribution with d1, d2 > 0 degrees of
+// freedom: P(F' > f) = I_x(d2/2, d1/2) with x = d2 / (d2 + d1 f) (its
+// complement y = d1 f / (d2 + d1 f) is formed directly, not as 1 - x).  The
+// continued fraction runs on the smaller tail, as in corr_pvalue; ln B(a, b) =
+// ln G(s) - [ln G(s + l) - ln G(l)] with s, l the smaller and larger of a, b.
+// The two-sided p of a t statistic with df degrees of freedom is
+// fdist_sf(t^2, 1, df).  f = +inf gives 0, f <= 0 gives 1, NaN gives NaN.
+NAPY_HD inline double fdist_sf(double f, double d1, double d2)
+{
+    if (!(f == f) || !(d1 > 0.0) || !(d2 > 0.0)) return NAN;
+    if (f <= 0.0) return 1.0;
+    if (f == INFINITY) return 0.0;
+    const double a = 0.5 * d2, b = 0.5 * d1;
+    const double den = d2 + d1 * f;
+    const double x = d2 / den, y = d1 * f / den;
+    const double sm = a < b ? a : b, lg = a < b ? b : a;
+    const double lnB = lgamma(sm) - lgamma_ratio(lg, sm);
+    // ln x and ln y from the complement when it is the small one (x near 1
+    // with a large a would otherwise lose digits)
+    const double lnx = y < 0.5 ? log1p(-y) : log(x);
+    const double lny = x < 0.5 ? log1p(-x) : log(y);
+    if (x < (a + 1.0) / (a + b + 2.0)) {
+        const double lf = a * lnx + b * lny - log(a) - lnB;
+        return exp(lf) * betacf_lentz(a, b, x);
+    }
+    const double lf = b * lny + a * lnx - log(b) - lnB;
+    const double p = 1.0 - exp(lf) * betacf_lentz(b, a, y);
+    return p < 0.0 ? 0.0 : p;
+}
+
 }  // namespace napy

@@ -19,4 +19,5 @@ from .workloads import (  # noqa: F401
     heavy_ties,
     edge_matrix,
     pvalue_matrix,
+    categorical_continuous,
 )

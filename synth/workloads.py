@@ -237,3 +237,24 @@ def pvalue_matrix(F: int, seed: int = SEED_BASE + 12, nan_frac: float = 0.02,
     P[iu, ju] = v
     P[ju, iu] = v
     return P
+
+
+def categorical_continuous(S: int, FC: int, FQ: int, ncat: int, missing: float = 0.3,
+                           seed: int = SEED_BASE + 13):
+    """Label-encoded categorical features (labels 0 .. ncat-1, every label
+    present in every column, as in the paper's simulated categorical data) and
+    continuous features; a third of the continuous columns are shifted by
+    0.3 sd per label of a random categorical column (so that some pairs carry
+    an effect); MCAR missingness at `missing` on both matrices.  Returns
+    (L, X) float32, samples x features."""
+    rng = _rng(seed)
+    L = rng.integers(0, ncat, size=(S, FC)).astype(np.float64)
+    if S >= ncat:
+        L[:ncat, :] = np.arange(ncat)[:, None]
+    X = rng.normal(size=(S, FQ)) * rng.uniform(0.5, 3.0, FQ) + rng.uniform(-50.0, 50.0, FQ)
+    src = rng.integers(0, FC, size=FQ)
+    eff = rng.random(FQ) < 1.0 / 3.0
+    X[:, eff] += 0.3 * L[:, src[eff]]
+    _mcar(rng, L, missing)
+    _mcar(rng, X, missing)
+    return L.astype(np.float32), X.astype(np.float32)

@@ -181,3 +181,95 @@ def test_adjust_arguments_rejected_on_host():
     assert call(ws=None) == _lib.NAPY_E_WORKSPACE
     assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
     assert call(ws=ctypes.c_void_p(0x2000000 + 64)) == _lib.NAPY_E_WORKSPACE
+
+
+def test_fdist_sf_host_matches_high_precision():
+    """The library's F tail (t-test and ANOVA p-values) against the
+    regularized incomplete beta evaluated by mpmath at 40 digits.  (SciPy's
+    f.sf is itself off by up to 3e-8 relative at 1e6 denominator degrees of
+    freedom, so it is not the reference here.)  The continued fraction loses
+    about log10 of its value in digits near its switch point, which reaches
+    1e-11 relative at 1e6 degrees of freedom; 1e-10 is the bar."""
+    import mpmath
+    from scipy import stats
+    mpmath.mp.dps = 40
+    lib = _lib.load()
+    d1s = [1.0, 2.0, 3.0, 7.5, 31.0]
+    d2s = [1.0, 2.7, 10.0, 100.0, 9998.0, 1e6]
+    fs = [1e-8, 1e-3, 0.5, 1.0, 2.0, 10.0, 1e2, 1e4]
+    grid = np.array([(f, a, b) for f in fs for a in d1s for b in d2s])
+    f = np.ascontiguousarray(grid[:, 0])
+    a = np.ascontiguousarray(grid[:, 1])
+    b = np.ascontiguousarray(grid[:, 2])
+    p = np.empty_like(f)
+    P = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    assert lib.napy_fdist_sf_host(P(f), P(a), P(b), P(p), f.size) == 0
+    def sf(fv, d1, d2):
+        F, A, B = mpmath.mpf(fv), mpmath.mpf(d1), mpmath.mpf(d2)
+        x, y = B / (B + A * F), A * F / (B + A * F)
+        with mpmath.workdps(80):  # room for the hypergeometric sums' cancellation
+            # the smaller tail directly: below the Beta(d2/2, d1/2) mean
+            if x < B / (A + B):
+                return float(mpmath.betainc(B / 2, A / 2, 0, x, regularized=True))
+            return float(1 - mpmath.betainc(A / 2, B / 2, 0, y, regularized=True))
+
+    ref = np.full(len(grid), np.nan)
+    for k, row in enumerate(grid):
+        try:
+            ref[k] = sf(*row)
+        except (mpmath.libmp.libhyper.NoConvergence, ValueError):
+            pass  # mpmath's hypergeometric series gives up on a few extreme points
+    chk = ~np.isnan(ref)
+    assert chk.sum() >= 0.9 * len(grid)
+    assert np.sum(chk & (b >= 9998.0)) >= 60  # the large-df region is covered
+    np.testing.assert_allclose(p[chk], ref[chk], rtol=1e-10, atol=0)
+    # within SciPy's own accuracy at moderate degrees of freedom
+    mod = b <= 100.0
+    np.testing.assert_allclose(p[mod], stats.f.sf(f[mod], a[mod], b[mod]), rtol=1e-9)
+    # the t-test form: P(F(1, df) > t^2) = two-sided t tail
+    t = np.array([0.01, 0.7, 2.5, 9.0, 40.0])
+    df = np.array([1.0, 4.0, 17.3, 250.0, 9998.0])
+    f2 = np.ascontiguousarray(t * t)
+    p2 = np.empty_like(f2)
+    ones = np.ones_like(f2)
+    assert lib.napy_fdist_sf_host(P(f2), P(ones), P(df), P(p2), f2.size) == 0
+    np.testing.assert_allclose(p2, 2 * stats.t.sf(t, df), rtol=1e-11)
+    # special values
+    sp = np.array([np.inf, 0.0, -1.0, np.nan])
+    pp = np.empty(4)
+    one4 = np.full(4, 3.0)
+    assert lib.napy_fdist_sf_host(P(sp), P(one4), P(one4), P(pp), 4) == 0
+    assert pp[0] == 0.0 and pp[1] == 1.0 and pp[2] == 1.0 and np.isnan(pp[3])
+
+
+def test_group_tests_arguments_rejected_on_host():
+    lib = _lib.load()
+    o = _lib.make_opts("fp64")
+    O = ctypes.byref(o)
+    need = lib.napy_ttest_workspace(100, 3, 5, O)
+    assert need > 0
+    assert lib.napy_anova_workspace(100, 3, 5, 1, O) == 0 and lib.napy_anova_workspace(100, 3, 5, 33, O) == 0
+    WS = ctypes.c_void_p(0x2000000)
+    ok = dict(L=FAKE, ldl=3, X=FAKE, ldx=5, S=100, FC=3, FQ=5, w=0, t=FAKE, p=FAKE, n=FAKE, ldo=5, ws=WS,
+              nb=need)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.napy_ttest(a["L"], a["ldl"], a["X"], a["ldx"], a["S"], a["FC"], a["FQ"], a["w"], a["t"],
+                              a["p"], a["n"], a["ldo"], a["ws"], a["nb"], O, None)
+
+    assert call(L=None) == _lib.NAPY_E_INVALID
+    assert call(X=None) == _lib.NAPY_E_INVALID
+    assert call(S=-1) == _lib.NAPY_E_INVALID
+    assert call(FC=0) == _lib.NAPY_E_INVALID
+    assert call(ldl=2) == _lib.NAPY_E_INVALID
+    assert call(ldx=4) == _lib.NAPY_E_INVALID
+    assert call(ldo=4) == _lib.NAPY_E_INVALID
+    assert call(w=2) == _lib.NAPY_E_INVALID
+    assert call(t=None) == _lib.NAPY_E_INVALID
+    assert call(n=None) == _lib.NAPY_E_INVALID
+    assert call(FQ=70000) == _lib.NAPY_E_UNSUPPORTED
+    assert call(ws=None) == _lib.NAPY_E_WORKSPACE
+    assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
+    assert lib.napy_anova(FAKE, 3, FAKE, 5, 100, 3, 5, 1, FAKE, FAKE, FAKE, 5, WS, need, O, None) \
+        == _lib.NAPY_E_INVALID
