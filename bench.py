@@ -53,6 +53,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9          # 32-bit lane operations per second
 HBM_PEAK_BPS = 8.0e12
 BF16_PEAK_FLOPS = 2.5e15
 FP32_MFMA_PEAK_FLOPS = 157.3e12
+FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 
 # HBM bytes per launch of the Spearman scan kernel on the headline workload:
 # rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE (KiB per dispatch), each scaled
@@ -146,7 +147,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--form", default="headline",
-                    choices=["headline", "precision", "serving", "differentiation", "copy", "adjust"])
+                    choices=["headline", "precision", "serving", "differentiation", "copy", "adjust", "groups"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
     ap.add_argument("--warmup-queries", type=int, default=100, help="serving: warm-up queries")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -173,6 +174,8 @@ def main() -> int:
         return run_precision(args)
     if args.form == "adjust":
         return run_adjust(args)
+    if args.form == "groups":
+        return run_groups(args)
 
     import numpy as np
     import torch
@@ -493,6 +496,93 @@ def run_adjust(args) -> int:
         "config": {"workload": "symmetric p matrices: 30% log-uniform on [1e-12, 1], 70% uniform, 20% rounded "
                                "to 2 decimals, 2% undefined", "variables": [1000, 4000]},
         "results": res, "cpu_baseline": cpu or None,
+    }))
+    return 0
+
+
+def run_groups(args) -> int:
+    """Categorical x continuous tests: Student and Welch t-tests of 1,000
+    dichotomous against 1,000 continuous features and one-way ANOVA of 1,000
+    four-category against 1,000 continuous features, 10,000 samples, 30%
+    missing on both sides; plus the oracle's rate on a sample of pairs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_00448_amd import _lib
+
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    hip = HipEvents()
+    e0, e1 = hip.new(), hip.new()
+    hip.rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    S, FC, FQ = 10_000, 1_000, 1_000
+    opts = _lib.make_opts("fp64")
+    res = {}
+    host = {}
+    for name, ncat in (("student", 2), ("welch", 2), ("anova", 4)):
+        L, X = synth.categorical_continuous(S, FC, FQ, ncat, seed=41 + ncat)
+        host[name] = (L, X)
+        Lt, Xt = torch.from_numpy(L).to(dev), torch.from_numpy(X).to(dev)
+        stat = torch.empty((FC, FQ), dtype=torch.float64, device=dev)
+        pv = torch.empty_like(stat)
+        n = torch.empty((FC, FQ), dtype=torch.int32, device=dev)
+        if name == "anova":
+            need = lib.napy_anova_workspace(S, FC, FQ, ncat, ctypes.byref(opts))
+        else:
+            need = lib.napy_ttest_workspace(S, FC, FQ, ctypes.byref(opts))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+        def step():
+            hip.rt.hipEventRecord(e0, sh)
+            if name == "anova":
+                st = lib.napy_anova(P(Lt), FC, P(Xt), FQ, S, FC, FQ, ncat, P(stat), P(pv), P(n), FQ, P(ws),
+                                    ws.numel(), ctypes.byref(opts), sh)
+            else:
+                st = lib.napy_ttest(P(Lt), FC, P(Xt), FQ, S, FC, FQ, int(name == "welch"), P(stat), P(pv), P(n),
+                                    FQ, P(ws), ws.numel(), ctypes.byref(opts), sh)
+            _lib.check(st, name)
+            hip.rt.hipEventRecord(e1, sh)
+
+        for _ in range(args.warmup):
+            step()
+        ts = []
+        for _ in range(max(args.steps, 5)):
+            step()
+            torch.cuda.synchronize(dev)
+            ts.append(hip.ms(e0, e1))
+        ms = float(np.median(ts))
+        # FP64 MFMA work: three products of the FC*ncat group indicators with
+        # FQ columns over S samples (indicator zeros included)
+        mfma_flop = 3 * 2.0 * FC * ncat * FQ * S
+        res[name] = {"ms": ms, "pairs_per_s": FC * FQ / (ms * 1e-3),
+                     "fp64_mfma_tflops": mfma_flop / (ms * 1e-3) / 1e12,
+                     "fp64_mfma_frac": mfma_flop / (ms * 1e-3) / FP64_PEAK_FLOPS}
+    hip.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import groups as og
+        L, X = host["welch"]
+        rng = np.random.default_rng(3)
+        pairs = list(zip(rng.integers(0, FC, 300).tolist(), rng.integers(0, FQ, 300).tolist()))
+        t0 = time.perf_counter()
+        og.ttest(L, X, welch=True, pairs=pairs)
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(pairs) / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"Welch t-test on {len(pairs)} random pairs of the same matrices (numpy, one thread), "
+                         f"{dt:.1f} s"}
+    print(json.dumps({
+        "metric": "groups form: categorical x continuous tests with pairwise deletion",
+        "value": res["welch"]["pairs_per_s"], "unit": "pairs/s (Welch t-test)", "n_gpus": 1,
+        "higher_is_better": True, "form": "groups", "data": "synthetic",
+        "config": {"workload": "10,000 samples; 1,000 categorical (2 or 4 labels, each present) x 1,000 "
+                               "continuous features; 30% MCAR on both; a third of the continuous columns shifted "
+                               "by a categorical column's label", "samples": S, "categorical": FC,
+                   "continuous": FQ},
+        "results": res, "cpu_baseline": cpu,
     }))
     return 0
 
