@@ -32,6 +32,7 @@ Readings (the paper does not spell these out):
     negative or at or above the caller's bound ncat) is not tested: NaN
     outputs and n = 0 for all its pairs.
   * The diagonal (g, g) is computed like any pair.
+  * A pair without complete samples (N = 0) has no test: NaN outputs.
 """
 
 from __future__ import annotations
@@ -49,9 +50,9 @@ def table_test(O: np.ndarray):
     r, c = O.shape
     R = O.sum(axis=1)
     C = O.sum(axis=0)
-    if np.any(R == 0) or np.any(C == 0):
-        return np.nan, np.nan, np.nan
     N = O.sum()
+    if np.any(R == 0) or np.any(C == 0) or N == 0:
+        return np.nan, np.nan, np.nan
     E = np.outer(R, C) / N
     chi2 = float(np.sum((O - E) ** 2 / E))
     if r < 2 or c < 2:
