@@ -269,6 +269,30 @@ int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
                void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Chi-squared test of independence between categorical features with
+ * pairwise deletion (Section 3.5), all pairs of one matrix.
+ *
+ * L is S x F float32 (ldl >= F), label-encoded (Section 3.3), labels in
+ * [0, ncat), 2 <= ncat <= 32; missing values as for napy_pearson.  For each
+ * pair (g, h) the r x c contingency table on I(g, h) (r, c: the labels
+ * observed anywhere in each column) gives chi2 = sum (O - E)^2 / E with
+ * E = row sum * column sum / N (no continuity correction), p = P(chi2_df >
+ * chi2) with df = (r - 1)(c - 1), Cramer's V = sqrt(chi2 / (N min(r-1, c-1)))
+ * (phi for 2 x 2) and n = N = |I(g, h)|.  Outputs chi2, p, v (float64) and n
+ * (int32) are full symmetric F x F with ldo >= F, all required; the diagonal
+ * is computed like any pair.  NaN everywhere when a category observed in a
+ * column is empty within I(g, h) or I(g, h) is empty; p and V NaN when a
+ * feature has one category.  A column with a label that is not an integer,
+ * negative or >= ncat is not tested (NaN, n = 0).  Counts are exact (FP64
+ * matrix cores).  Supported while F * ncat <= 50,000.
+ * ------------------------------------------------------------------------ */
+size_t napy_chi2_workspace(int64_t S, int64_t F, int32_t ncat, const napy_opts* opts);
+
+int napy_chi2(const float* L, int64_t ldl, int64_t S, int64_t F, int32_t ncat,
+              double* chi2, double* p, double* v, int32_t* n, int64_t ldo,
+              void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
  * Test hooks (not part of the computation path).
  *
  * napy_spearman_pair_ranks: the doubled average ranks 2*rank that the
@@ -296,6 +320,10 @@ int napy_pvalue_host(const double* r, const int32_t* n, double* p, int64_t count
  * compiled for the host, on host arrays; for checking the arithmetic without a
  * GPU. */
 int napy_fdist_sf_host(const double* f, const double* d1, const double* d2, double* p, int64_t count);
+
+/* napy_chi2_sf_host: the library's chi-squared survival function
+ * P(chi2_df > x) = Q(df/2, x/2) compiled for the host, on host arrays. */
+int napy_chi2_sf_host(const double* x, const double* df, double* p, int64_t count);
 
 #ifdef __cplusplus
 }

@@ -20,4 +20,5 @@ from .api import (  # noqa: F401,E402
     adjust_pvalues,
     ttest,
     anova,
+    chi2,
 )

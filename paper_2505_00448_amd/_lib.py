@@ -34,6 +34,7 @@ EXPORTS = [
     "napy_spearman_pair_ranks", "napy_pvalue_device", "napy_pvalue_host",
     "napy_adjust_workspace", "napy_adjust_pvalues",
     "napy_ttest_workspace", "napy_ttest", "napy_anova_workspace", "napy_anova", "napy_fdist_sf_host",
+    "napy_chi2_workspace", "napy_chi2", "napy_chi2_sf_host",
 ]
 
 
@@ -93,6 +94,9 @@ def load() -> ctypes.CDLL:
         "napy_anova_workspace": (sz, [i64, i64, i64, i32, O]),
         "napy_anova": (ctypes.c_int, [P, i64, P, i64, i64, i64, i64, i32, P, P, P, i64, P, sz, O, P]),
         "napy_fdist_sf_host": (ctypes.c_int, [P, P, P, P, i64]),
+        "napy_chi2_workspace": (sz, [i64, i64, i32, O]),
+        "napy_chi2": (ctypes.c_int, [P, i64, i64, i64, i32, P, P, P, P, i64, P, sz, O, P]),
+        "napy_chi2_sf_host": (ctypes.c_int, [P, P, P, i64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

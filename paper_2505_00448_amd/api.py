@@ -171,6 +171,32 @@ def anova(L: torch.Tensor, X: torch.Tensor, ncat: Optional[int] = None, missing:
     return _groups_call("anova", L, X, False, ncat, missing, samples_axis, workspace)
 
 
+def chi2(L: torch.Tensor, ncat: Optional[int] = None, missing: Optional[float] = None, samples_axis: int = 0,
+         workspace: Optional[torch.Tensor] = None) -> dict:
+    """Chi-squared tests of independence of every pair of label-encoded
+    categorical columns of L with pairwise deletion (NApy, Section 3.5):
+    {"chi2", "p", "v" (Cramer's V), "n"}, F x F.  ncat defaults to the
+    largest observed label + 1."""
+    lib = _lib.load()
+    L = _prep_input(L, samples_axis, False)
+    S, F = L.shape
+    opts = _lib.make_opts("fp64", missing)
+    if ncat is None:
+        lab = L if missing is None else torch.where(L == missing, torch.nan, L)
+        mx = torch.nan_to_num(lab, nan=-1.0).max() if L.numel() else torch.tensor(-1.0)
+        ncat = max(2, int(mx.item()) + 1)
+    need = lib.napy_chi2_workspace(S, F, int(ncat), ctypes.byref(opts))
+    if need == 0:
+        raise _lib.NapyError(_lib.NAPY_E_UNSUPPORTED, f"chi2 workspace refused S={S} F={F} ncat={ncat}")
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, L.device)
+    out = {k: torch.empty((F, F), dtype=torch.float64, device=L.device) for k in ("chi2", "p", "v")}
+    out["n"] = torch.empty((F, F), dtype=torch.int32, device=L.device)
+    st = lib.napy_chi2(_ptr(L), L.stride(0), S, F, int(ncat), _ptr(out["chi2"]), _ptr(out["p"]), _ptr(out["v"]),
+                       _ptr(out["n"]), F, _ptr(ws), ws.numel(), ctypes.byref(opts), _stream_handle(L.device))
+    _lib.check(st, "napy_chi2")
+    return out
+
+
 _ADJUST = {"bonferroni": 0, "bh": 1, "by": 2}
 
 

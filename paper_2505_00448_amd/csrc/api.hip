@@ -50,6 +50,10 @@ size_t groups_ws_bytes(int64_t S, int64_t FC, int64_t FQ, int ncat);
 int groups_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
                int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws, const napy_opts* opts,
                hipStream_t st);
+// chi-squared test (chi2.hip)
+size_t chi2_ws_bytes(int64_t S, int64_t F, int ncat);
+int chi2_run(const float* L, int64_t ldl, int64_t S, int64_t F, int ncat, double* chi, double* p, double* v,
+             int32_t* n, int64_t ldo, void* ws, const napy_opts* opts, hipStream_t st);
 // backward (backward.hip)
 size_t backward_ws_bytes(int64_t S, int64_t F);
 int backward_run(const float* X, int64_t S, int64_t F, int64_t ldx, const double* saved, const float* dR,
@@ -317,6 +321,40 @@ int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
                const napy_opts* opts, void* stream)
 {
     return groups_call(L, ldl, X, ldx, S, FC, FQ, 2, ncat, F, p, n, ldo, ws, ws_bytes, opts, stream);
+}
+
+static int check_chi2(int64_t S, int64_t F, int ncat)
+{
+    if (S < 0 || F < 1 || ncat < 2 || ncat > 32) return NAPY_E_INVALID;
+    if (F > MAX_F || S > MAX_S || F * ncat > 50000) {
+        set_last_error("shape S=%lld F=%lld ncat=%d outside the supported range", (long long)S, (long long)F, ncat);
+        return NAPY_E_UNSUPPORTED;
+    }
+    return NAPY_OK;
+}
+
+size_t napy_chi2_workspace(int64_t S, int64_t F, int32_t ncat, const napy_opts* opts)
+{
+    if (check_chi2(S, F, ncat) != NAPY_OK || !opts_ok(opts)) return 0;
+    return chi2_ws_bytes(S, F, ncat);
+}
+
+int napy_chi2(const float* L, int64_t ldl, int64_t S, int64_t F, int32_t ncat, double* chi2, double* p, double* v,
+              int32_t* n, int64_t ldo, void* ws, size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    NAPY_TRY(check_chi2(S, F, ncat));
+    if (S > 0 && !L) return NAPY_E_INVALID;
+    if (ldl < F || ldo < F || !chi2 || !p || !v || !n) return NAPY_E_INVALID;
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < chi2_ws_bytes(S, F, ncat) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return chi2_run(L, ldl, S, F, ncat, chi2, p, v, n, ldo, ws, opts, (hipStream_t)stream);
+}
+
+int napy_chi2_sf_host(const double* x, const double* df, double* p, int64_t count)
+{
+    if (count < 0 || (count > 0 && (!x || !df || !p))) return NAPY_E_INVALID;
+    for (int64_t i = 0; i < count; ++i) p[i] = chi2_sf(x[i], df[i]);
+    return NAPY_OK;
 }
 
 int napy_fdist_sf_host(const double* f, const double* d1, const double* d2, double* p, int64_t count)

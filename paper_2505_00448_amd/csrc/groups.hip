@@ -375,6 +375,20 @@ __global__ __launch_bounds__(256) void k_grp_combine(const double* __restrict__ 
     nout[g * ldo + h] = ok ? (int32_t)ntot : 0;
 }
 
+// per categorical column: observed-label mask and invalid-label flag
+int labels_launch(const float* L, int64_t ldl, int64_t S, int64_t FC, int ncat, int use_sent, float sent,
+                  uint64_t* catmask, int32_t* bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grp_zero, dim3((unsigned)ceil_div(FC, 256)), dim3(256), 0, st, catmask, bad, FC);
+    NAPY_TRY(check_launch("labels zero"));
+    if (S > 0) {
+        hipLaunchKernelGGL(k_grp_labels, dim3((unsigned)ceil_div(FC, 64), (unsigned)ceil_div(S, 256)), dim3(256), 0,
+                           st, L, S, FC, ldl, ncat, use_sent, sent, catmask, bad);
+        NAPY_TRY(check_launch("labels"));
+    }
+    return NAPY_OK;
+}
+
 int groups_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
                int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws, const napy_opts* opts,
                hipStream_t st)
@@ -386,13 +400,7 @@ int groups_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
     grp_carve(c, S, FC, FQ, ncat, w);
     const GrpPlan plan = grp_plan(S, FC, FQ, ncat);
     NAPY_TRY(colstats_launch(X, S, FQ, ldx, us, sv, w.cs, st));
-    hipLaunchKernelGGL(k_grp_zero, dim3((unsigned)ceil_div(FC, 256)), dim3(256), 0, st, w.catmask, w.bad, FC);
-    NAPY_TRY(check_launch("groups zero"));
-    if (S > 0) {
-        hipLaunchKernelGGL(k_grp_labels, dim3((unsigned)ceil_div(FC, 64), (unsigned)ceil_div(S, 256)), dim3(256), 0,
-                           st, L, S, FC, ldl, ncat, us, sv, w.catmask, w.bad);
-        NAPY_TRY(check_launch("groups labels"));
-    }
+    NAPY_TRY(labels_launch(L, ldl, S, FC, ncat, us, sv, w.catmask, w.bad, st));
     const int64_t nblk = (int64_t)plan.tiles_e * plan.tiles_h * plan.nsplit;
     hipLaunchKernelGGL(k_grp_tiles, dim3((unsigned)nblk), dim3(256), 0, st, L, ldl, X, ldx, S, FC, FQ, ncat, us, sv,
                        w.cs.mu64, plan, w.part);

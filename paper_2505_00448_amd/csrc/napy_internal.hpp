@@ -122,6 +122,11 @@ struct ColStats {
     double* psum;   // [R][F] partial sums
     int rows_chunks;
 };
+// observed-label mask (bit k: label k seen) and invalid-label flag of each
+// categorical column (groups.hip)
+int labels_launch(const float* L, int64_t ldl, int64_t S, int64_t FC, int ncat, int use_sent, float sent,
+                  uint64_t* catmask, int32_t* bad, hipStream_t st);
+
 int colstats_plan_chunks(int64_t S, int64_t F);
 void colstats_carve(Carver& c, int64_t S, int64_t F, ColStats& cs);
 int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,

@@ -171,4 +171,46 @@ NAPY_HD inline double fdist_sf(double f, double d1, double d2)
     return p < 0.0 ? 0.0 : p;
 }
 
+// Regularized upper incomplete gamma Q(a, x) = Gamma(a, x) / Gamma(a), a > 0
+// (A&S 6.5.3).  For x < a + 1 the series of P = 1 - Q (A&S 6.5.29,
+// P = e^-x x^a / Gamma(a) * sum_n x^n / (a (a+1) ... (a+n))); otherwise the
+// continued fraction of Q (A&S 6.5.31) by the modified Lentz algorithm, so the
+// tail computed directly is the small one.  The prefactor is formed in logs.
+NAPY_HD inline double gamma_q(double a, double x)
+{
+    if (!(x == x) || !(a > 0.0)) return NAN;
+    if (x <= 0.0) return 1.0;
+    if (x == INFINITY) return 0.0;
+    const double lpre = -x + a * log(x) - lgamma(a);
+    if (x < a + 1.0) {
+        double ap = a, del = 1.0 / a, sum = del;
+        for (int n = 1; n <= 100000; ++n) {
+            ap += 1.0;
+            del *= x / ap;
+            sum += del;
+            if (fabs(del) < fabs(sum) * 1e-17) break;
+        }
+        const double q = 1.0 - sum * exp(lpre);
+        return q < 0.0 ? 0.0 : q;
+    }
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i <= 100000; ++i) {
+        const double an = -(double)i * ((double)i - a);
+        b += 2.0;
+        d = an * d + b;
+        if (fabs(d) < tiny) d = tiny;
+        c = b + an / c;
+        if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        const double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return exp(lpre) * h;
+}
+
+// P(chi2_df > x) = Q(df / 2, x / 2)
+NAPY_HD inline double chi2_sf(double x, double df) { return gamma_q(0.5 * df, 0.5 * x); }
+
 }  // namespace napy

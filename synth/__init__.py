@@ -20,4 +20,5 @@ from .workloads import (  # noqa: F401
     edge_matrix,
     pvalue_matrix,
     categorical_continuous,
+    categorical_matrix,
 )

@@ -258,3 +258,21 @@ def categorical_continuous(S: int, FC: int, FQ: int, ncat: int, missing: float =
     _mcar(rng, L, missing)
     _mcar(rng, X, missing)
     return L.astype(np.float32), X.astype(np.float32)
+
+
+def categorical_matrix(S: int, F: int, ncat: int, missing: float = 0.3, seed: int = SEED_BASE + 14) -> np.ndarray:
+    """Label-encoded categorical features (labels 0 .. c_j - 1 with c_j drawn
+    from 2 .. ncat per column, every label present): quantiles of a rank-3
+    factor model, so that columns sharing factors are dependent; MCAR
+    missingness.  Returns S x F float32."""
+    rng = _rng(seed)
+    Z = factor_matrix(rng, S, F, 3)
+    L = np.empty((S, F))
+    for j in range(F):
+        c = int(rng.integers(2, ncat + 1))
+        edges = np.quantile(Z[:, j], np.linspace(0, 1, c + 1)[1:-1])
+        L[:, j] = np.searchsorted(edges, Z[:, j])
+        if S >= c:
+            L[:c, j] = np.arange(c)
+    _mcar(rng, L, missing)
+    return L.astype(np.float32)

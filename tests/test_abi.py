@@ -273,3 +273,49 @@ def test_group_tests_arguments_rejected_on_host():
     assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
     assert lib.napy_anova(FAKE, 3, FAKE, 5, 100, 3, 5, 1, FAKE, FAKE, FAKE, 5, WS, need, O, None) \
         == _lib.NAPY_E_INVALID
+
+
+def test_chi2_sf_host_matches_high_precision():
+    """The library's chi-squared tail Q(df/2, x/2) against mpmath at 40 digits."""
+    import mpmath
+    mpmath.mp.dps = 40
+    lib = _lib.load()
+    dfs = [1.0, 2.0, 3.0, 6.0, 9.0, 49.0, 961.0]
+    xs = [1e-6, 0.01, 0.5, 1.0, 3.0, 10.0, 50.0, 200.0, 1500.0, 4000.0]
+    grid = np.array([(x, d) for x in xs for d in dfs])
+    x = np.ascontiguousarray(grid[:, 0])
+    d = np.ascontiguousarray(grid[:, 1])
+    p = np.empty_like(x)
+    P = lambda v: v.ctypes.data_as(ctypes.c_void_p)
+    assert lib.napy_chi2_sf_host(P(x), P(d), P(p), x.size) == 0
+    ref = np.array([float(mpmath.gammainc(mpmath.mpf(dd) / 2, mpmath.mpf(xx) / 2, mpmath.inf, regularized=True))
+                    for xx, dd in grid])
+    ok = ref > 1e-300
+    np.testing.assert_allclose(p[ok], ref[ok], rtol=1e-12, atol=0)
+    assert np.all(p[~ok] < 1e-290)
+    sp = np.array([0.0, np.inf, np.nan])
+    pp = np.empty(3)
+    three = np.full(3, 3.0)
+    assert lib.napy_chi2_sf_host(P(sp), P(three), P(pp), 3) == 0
+    assert pp[0] == 1.0 and pp[1] == 0.0 and np.isnan(pp[2])
+
+
+def test_chi2_arguments_rejected_on_host():
+    lib = _lib.load()
+    o = _lib.make_opts("fp64")
+    O = ctypes.byref(o)
+    need = lib.napy_chi2_workspace(100, 10, 4, O)
+    assert need > 0 and lib.napy_chi2_workspace(100, 10, 1, O) == 0 and lib.napy_chi2_workspace(100, 20000, 4, O) == 0
+    WS = ctypes.c_void_p(0x2000000)
+
+    def call(L=FAKE, ldl=10, S=100, F=10, ncat=4, out=FAKE, n=FAKE, ldo=10, ws=WS, nb=need):
+        return lib.napy_chi2(L, ldl, S, F, ncat, out, out, out, n, ldo, ws, nb, O, None)
+
+    assert call(L=None) == _lib.NAPY_E_INVALID
+    assert call(ldl=9) == _lib.NAPY_E_INVALID
+    assert call(ldo=9) == _lib.NAPY_E_INVALID
+    assert call(ncat=33) == _lib.NAPY_E_INVALID
+    assert call(out=None) == _lib.NAPY_E_INVALID
+    assert call(n=None) == _lib.NAPY_E_INVALID
+    assert call(F=20000, ldl=20000, ldo=20000) == _lib.NAPY_E_UNSUPPORTED
+    assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
