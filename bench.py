@@ -501,10 +501,11 @@ def run_adjust(args) -> int:
 
 
 def run_groups(args) -> int:
-    """Categorical x continuous tests: Student and Welch t-tests of 1,000
-    dichotomous against 1,000 continuous features and one-way ANOVA of 1,000
-    four-category against 1,000 continuous features, 10,000 samples, 30%
-    missing on both sides; plus the oracle's rate on a sample of pairs."""
+    """Tests with categorical features: Student and Welch t-tests of 1,000
+    dichotomous against 1,000 continuous features, one-way ANOVA of 1,000
+    four-category against 1,000 continuous features, and chi-squared tests of
+    all pairs of 1,000 categorical features (2 to 4 labels); 10,000 samples,
+    30% missing; plus the oracle's rate on a sample of pairs."""
     import numpy as np
     import torch
 
@@ -561,6 +562,34 @@ def run_groups(args) -> int:
         res[name] = {"ms": ms, "pairs_per_s": FC * FQ / (ms * 1e-3),
                      "fp64_mfma_tflops": mfma_flop / (ms * 1e-3) / 1e12,
                      "fp64_mfma_frac": mfma_flop / (ms * 1e-3) / FP64_PEAK_FLOPS}
+    # chi-squared test of all pairs of 1,000 categorical features (2..4 labels)
+    Lc = synth.categorical_matrix(S, FC, 4, seed=47)
+    Lct = torch.from_numpy(Lc).to(dev)
+    outs = [torch.empty((FC, FC), dtype=torch.float64, device=dev) for _ in range(3)]
+    nc = torch.empty((FC, FC), dtype=torch.int32, device=dev)
+    wsc = torch.empty(lib.napy_chi2_workspace(S, FC, 4, ctypes.byref(opts)), dtype=torch.uint8, device=dev)
+
+    def chi_step():
+        hip.rt.hipEventRecord(e0, sh)
+        st = lib.napy_chi2(P(Lct), FC, S, FC, 4, P(outs[0]), P(outs[1]), P(outs[2]), P(nc), FC, P(wsc),
+                           wsc.numel(), ctypes.byref(opts), sh)
+        _lib.check(st, "chi2")
+        hip.rt.hipEventRecord(e1, sh)
+
+    for _ in range(args.warmup):
+        chi_step()
+    ts = []
+    for _ in range(max(args.steps, 5)):
+        chi_step()
+        torch.cuda.synchronize(dev)
+        ts.append(hip.ms(e0, e1))
+    ms = float(np.median(ts))
+    E = FC * 4
+    T = (E + 63) // 64
+    chi_flop = 2.0 * (T * (T + 1) // 2) * 64 * 64 * S  # upper-triangle tiles of indicator products
+    res["chi2"] = {"ms": ms, "pairs_per_s": FC * (FC + 1) / 2 / (ms * 1e-3),
+                   "fp64_mfma_tflops": chi_flop / (ms * 1e-3) / 1e12,
+                   "fp64_mfma_frac": chi_flop / (ms * 1e-3) / FP64_PEAK_FLOPS}
     hip.close()
     cpu = None
     if not args.no_cpu_baseline:
