@@ -269,6 +269,48 @@ int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
                void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Rank tests of categorical x continuous pairs with pairwise deletion
+ * (Section 3.5): Mann-Whitney U and Kruskal-Wallis H.
+ *
+ * Inputs, missing values, output layout and the untested-column rule are
+ * those of napy_ttest / napy_anova above.  Within I(g, h) the continuous
+ * values are ranked 1..n with tied values given the average of their ranks;
+ * R_k is the rank sum of label k, n_k its size, T = sum over groups of tied
+ * values of t^3 - t.  S <= 24,576 (sorted orders hold 16-bit sample indices).
+ *
+ * napy_mannwhitney: groups are label 0 and label 1; the statistic is
+ *   U1 = R_0 - n0 (n0 + 1) / 2.  Two-sided p with U = max(U1, n0 n1 - U1):
+ *   asymptotic, z = (U - n0 n1 / 2 - 1/2) / s with
+ *   s^2 = n0 n1 / 12 ((n + 1) - T / (n (n - 1))) (continuity and tie
+ *   corrections), p = min(1, 2 Q(z)) (Q the standard normal tail; s = 0 gives
+ *   p = 1); or exact, p = min(1, 2 P(U' >= U)) under random assignment of the
+ *   n ranks.  mode NAPY_MWU_AUTO takes the exact p when I(g, h) has no ties
+ *   and a group has fewer than eight samples, NAPY_MWU_ASYMPTOTIC never.  NaN
+ *   when a group is empty.
+ * napy_kruskal: categories as for napy_anova (labels in [0, ncat),
+ *   2 <= ncat <= 32); H = 12 / (n (n + 1)) sum_k (R_k - n_k (n + 1) / 2)^2 /
+ *   n_k / (1 - T / (n^3 - n)), p = P(chi2_{K-1} > H).  NaN when a category is
+ *   empty within I(g, h), the column has one category, or every value in
+ *   I(g, h) is tied.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    NAPY_MWU_AUTO = 0,
+    NAPY_MWU_ASYMPTOTIC = 1
+} napy_mwu_mode;
+
+size_t napy_mannwhitney_workspace(int64_t S, int64_t FC, int64_t FQ, const napy_opts* opts);
+
+int napy_mannwhitney(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                     int32_t mode, double* U, double* p, int32_t* n, int64_t ldo,
+                     void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+size_t napy_kruskal_workspace(int64_t S, int64_t FC, int64_t FQ, int32_t ncat, const napy_opts* opts);
+
+int napy_kruskal(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                 int32_t ncat, double* H, double* p, int32_t* n, int64_t ldo,
+                 void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
  * Chi-squared test of independence between categorical features with
  * pairwise deletion (Section 3.5), all pairs of one matrix.
  *

@@ -21,4 +21,6 @@ from .api import (  # noqa: F401,E402
     ttest,
     anova,
     chi2,
+    mannwhitney,
+    kruskal,
 )

@@ -35,6 +35,7 @@ EXPORTS = [
     "napy_adjust_workspace", "napy_adjust_pvalues",
     "napy_ttest_workspace", "napy_ttest", "napy_anova_workspace", "napy_anova", "napy_fdist_sf_host",
     "napy_chi2_workspace", "napy_chi2", "napy_chi2_sf_host",
+    "napy_mannwhitney_workspace", "napy_mannwhitney", "napy_kruskal_workspace", "napy_kruskal",
 ]
 
 
@@ -97,6 +98,10 @@ def load() -> ctypes.CDLL:
         "napy_chi2_workspace": (sz, [i64, i64, i32, O]),
         "napy_chi2": (ctypes.c_int, [P, i64, i64, i64, i32, P, P, P, P, i64, P, sz, O, P]),
         "napy_chi2_sf_host": (ctypes.c_int, [P, P, P, i64]),
+        "napy_mannwhitney_workspace": (sz, [i64, i64, i64, O]),
+        "napy_mannwhitney": (ctypes.c_int, [P, i64, P, i64, i64, i64, i64, i32, P, P, P, i64, P, sz, O, P]),
+        "napy_kruskal_workspace": (sz, [i64, i64, i64, i32, O]),
+        "napy_kruskal": (ctypes.c_int, [P, i64, P, i64, i64, i64, i64, i32, P, P, P, i64, P, sz, O, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -127,31 +127,38 @@ def _groups_call(kind: str, L: torch.Tensor, X: torch.Tensor, welch: bool, ncat:
     S, FC = L.shape
     FQ = X.shape[1]
     opts = _lib.make_opts("fp64", missing)
+    if kind in ("anova", "kruskal") and ncat is None:
+        # largest observed label + 1 (one device reduction)
+        lab = L if missing is None else torch.where(L == missing, torch.nan, L)
+        mx = torch.nan_to_num(lab, nan=-1.0).max() if L.numel() else torch.tensor(-1.0)
+        ncat = max(2, int(mx.item()) + 1)
     if kind == "ttest":
         need = lib.napy_ttest_workspace(S, FC, FQ, ctypes.byref(opts))
-    else:
-        if ncat is None:
-            # largest observed label + 1 (one device reduction)
-            lab = L if missing is None else torch.where(L == missing, torch.nan, L)
-            mx = torch.nan_to_num(lab, nan=-1.0).max() if L.numel() else torch.tensor(-1.0)
-            ncat = max(2, int(mx.item()) + 1)
+    elif kind == "anova":
         need = lib.napy_anova_workspace(S, FC, FQ, int(ncat), ctypes.byref(opts))
+    elif kind == "mannwhitney":
+        need = lib.napy_mannwhitney_workspace(S, FC, FQ, ctypes.byref(opts))
+    else:
+        need = lib.napy_kruskal_workspace(S, FC, FQ, int(ncat), ctypes.byref(opts))
     if need == 0:
         raise _lib.NapyError(_lib.NAPY_E_UNSUPPORTED, f"{kind} workspace refused S={S} FC={FC} FQ={FQ}")
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
     stat = torch.empty((FC, FQ), dtype=torch.float64, device=X.device)
     p = torch.empty((FC, FQ), dtype=torch.float64, device=X.device)
     n = torch.empty((FC, FQ), dtype=torch.int32, device=X.device)
+    args = (_ptr(L), L.stride(0), _ptr(X), X.stride(0), S, FC, FQ)
+    tail = (_ptr(stat), _ptr(p), _ptr(n), FQ, _ptr(ws), ws.numel(), ctypes.byref(opts), _stream_handle(X.device))
     if kind == "ttest":
-        st = lib.napy_ttest(_ptr(L), L.stride(0), _ptr(X), X.stride(0), S, FC, FQ, int(bool(welch)), _ptr(stat),
-                            _ptr(p), _ptr(n), FQ, _ptr(ws), ws.numel(), ctypes.byref(opts),
-                            _stream_handle(X.device))
-        _lib.check(st, "napy_ttest")
+        _lib.check(lib.napy_ttest(*args, int(bool(welch)), *tail), "napy_ttest")
         return {"t": stat, "p": p, "n": n}
-    st = lib.napy_anova(_ptr(L), L.stride(0), _ptr(X), X.stride(0), S, FC, FQ, int(ncat), _ptr(stat), _ptr(p),
-                        _ptr(n), FQ, _ptr(ws), ws.numel(), ctypes.byref(opts), _stream_handle(X.device))
-    _lib.check(st, "napy_anova")
-    return {"F": stat, "p": p, "n": n}
+    if kind == "anova":
+        _lib.check(lib.napy_anova(*args, int(ncat), *tail), "napy_anova")
+        return {"F": stat, "p": p, "n": n}
+    if kind == "mannwhitney":
+        _lib.check(lib.napy_mannwhitney(*args, int(welch), *tail), "napy_mannwhitney")
+        return {"U": stat, "p": p, "n": n}
+    _lib.check(lib.napy_kruskal(*args, int(ncat), *tail), "napy_kruskal")
+    return {"H": stat, "p": p, "n": n}
 
 
 def ttest(L: torch.Tensor, X: torch.Tensor, welch: bool = False, missing: Optional[float] = None,
@@ -169,6 +176,30 @@ def anova(L: torch.Tensor, X: torch.Tensor, ncat: Optional[int] = None, missing:
     Section 3.5): {"F", "p", "n"}, FC x FQ.  ncat defaults to the largest
     observed label + 1."""
     return _groups_call("anova", L, X, False, ncat, missing, samples_axis, workspace)
+
+
+_MWU_MODE = {"auto": 0, "asymptotic": 1}
+
+
+def mannwhitney(L: torch.Tensor, X: torch.Tensor, mode: str = "auto", missing: Optional[float] = None,
+                samples_axis: int = 0, workspace: Optional[torch.Tensor] = None) -> dict:
+    """Mann-Whitney U tests of every dichotomous column of L (labels 0/1)
+    against every continuous column of X with pairwise deletion (NApy,
+    Section 3.5): {"U" (of label 0), "p", "n"}, FC x FQ.  mode "auto": exact
+    p when the pair has no ties and a group has fewer than eight samples,
+    else asymptotic; "asymptotic": always the normal approximation."""
+    if mode not in _MWU_MODE:
+        raise ValueError(f"mode must be one of {sorted(_MWU_MODE)}")
+    return _groups_call("mannwhitney", L, X, _MWU_MODE[mode], None, missing, samples_axis, workspace)
+
+
+def kruskal(L: torch.Tensor, X: torch.Tensor, ncat: Optional[int] = None, missing: Optional[float] = None,
+            samples_axis: int = 0, workspace: Optional[torch.Tensor] = None) -> dict:
+    """Kruskal-Wallis H tests of every categorical column of L (labels 0 ..
+    ncat-1) against every continuous column of X with pairwise deletion
+    (NApy, Section 3.5): {"H", "p", "n"}, FC x FQ.  ncat defaults to the
+    largest observed label + 1."""
+    return _groups_call("kruskal", L, X, False, ncat, missing, samples_axis, workspace)
 
 
 def chi2(L: torch.Tensor, ncat: Optional[int] = None, missing: Optional[float] = None, samples_axis: int = 0,

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnapy.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "pearson.hip", "spearman.hip", "backward.hip", "adjust.hip", "groups.hip", "chi2.hip"]
+SOURCES = ["api.hip", "pearson.hip", "spearman.hip", "backward.hip", "adjust.hip", "groups.hip", "chi2.hip", "ranktests.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

@@ -50,6 +50,11 @@ size_t groups_ws_bytes(int64_t S, int64_t FC, int64_t FQ, int ncat);
 int groups_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
                int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws, const napy_opts* opts,
                hipStream_t st);
+// rank tests (ranktests.hip)
+size_t ranktests_ws_bytes(int64_t S, int64_t FC, int64_t FQ, bool mwu);
+int ranktests_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                  int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws,
+                  const napy_opts* opts, hipStream_t st);
 // chi-squared test (chi2.hip)
 size_t chi2_ws_bytes(int64_t S, int64_t F, int ncat);
 int chi2_run(const float* L, int64_t ldl, int64_t S, int64_t F, int ncat, double* chi, double* p, double* v,
@@ -321,6 +326,55 @@ int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
                const napy_opts* opts, void* stream)
 {
     return groups_call(L, ldl, X, ldx, S, FC, FQ, 2, ncat, F, p, n, ldo, ws, ws_bytes, opts, stream);
+}
+
+static int check_ranks(int64_t S, int64_t FC, int64_t FQ, int ncat)
+{
+    NAPY_TRY(check_groups(S, FC, FQ, ncat));
+    if (S > MAX_S_SPEARMAN) {
+        set_last_error("rank tests support S <= %lld samples (got %lld)", (long long)MAX_S_SPEARMAN, (long long)S);
+        return NAPY_E_UNSUPPORTED;
+    }
+    return NAPY_OK;
+}
+
+static int ranks_call(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                      int test, int ncat, double* stat, double* p, int32_t* n, int64_t ldo, void* ws,
+                      size_t ws_bytes, const napy_opts* opts, void* stream)
+{
+    NAPY_TRY(check_ranks(S, FC, FQ, ncat));
+    if (S > 0 && (!L || !X)) return NAPY_E_INVALID;
+    if (ldl < FC || ldx < FQ || ldo < FQ || !stat || !p || !n) return NAPY_E_INVALID;
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    if (!ws || ws_bytes < ranktests_ws_bytes(S, FC, FQ, test <= 1) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
+    return ranktests_run(L, ldl, X, ldx, S, FC, FQ, test, ncat, stat, p, n, ldo, ws, opts, (hipStream_t)stream);
+}
+
+size_t napy_mannwhitney_workspace(int64_t S, int64_t FC, int64_t FQ, const napy_opts* opts)
+{
+    if (check_ranks(S, FC, FQ, 2) != NAPY_OK || !opts_ok(opts)) return 0;
+    return ranktests_ws_bytes(S, FC, FQ, true);
+}
+
+int napy_mannwhitney(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                     int32_t mode, double* U, double* p, int32_t* n, int64_t ldo, void* ws, size_t ws_bytes,
+                     const napy_opts* opts, void* stream)
+{
+    if (mode != NAPY_MWU_AUTO && mode != NAPY_MWU_ASYMPTOTIC) return NAPY_E_INVALID;
+    return ranks_call(L, ldl, X, ldx, S, FC, FQ, mode, 2, U, p, n, ldo, ws, ws_bytes, opts, stream);
+}
+
+size_t napy_kruskal_workspace(int64_t S, int64_t FC, int64_t FQ, int32_t ncat, const napy_opts* opts)
+{
+    if (check_ranks(S, FC, FQ, ncat) != NAPY_OK || !opts_ok(opts)) return 0;
+    return ranktests_ws_bytes(S, FC, FQ, false);
+}
+
+int napy_kruskal(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,
+                 int32_t ncat, double* H, double* p, int32_t* n, int64_t ldo, void* ws, size_t ws_bytes,
+                 const napy_opts* opts, void* stream)
+{
+    return ranks_call(L, ldl, X, ldx, S, FC, FQ, 2, ncat, H, p, n, ldo, ws, ws_bytes, opts, stream);
 }
 
 static int check_chi2(int64_t S, int64_t F, int ncat)

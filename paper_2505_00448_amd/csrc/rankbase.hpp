@@ -1,0 +1,53 @@
+// Per-column sorted orders of a samples x variables matrix (the Spearman
+// sort): layout shared by the Spearman scan, the subset queries and the rank
+// tests.
+#pragma once
+
+#include "napy_internal.hpp"
+
+namespace napy {
+
+struct SpearBase {
+    uint16_t* ord;     // [F][ld]
+    uint16_t* pos;     // [F][ld]
+    uint32_t* runs;    // [F][ld]
+    uint64_t* tbits;   // [F][ld/64]: bit k set if sorted position k lies in a tie run
+    uint32_t* rlist;   // [F][ld/2]: tie run r (length > 1) of the column as s | e << 16
+    int32_t* nruns;    // [F] number of tie runs
+    int32_t* ncol;     // [F]
+    int32_t* hasties;  // [F]
+    int32_t* tcount;   // [F] number of positions in tie runs
+    int32_t* perm;     // [F] processing order of the columns (see k_perm)
+    int64_t ld;
+};
+
+// Row stride of the per-column arrays: room for every sample plus one dummy
+// sample index S whose position is always "missing", padded to whole groups
+// of four 64-position chunks, so sorted-order reads past a column's observed
+// count need no bounds test.
+inline int64_t spear_ld(int64_t S) { return round_up(S + 1, 256); }
+// sorted orders may be read up to this many entries past the last row
+constexpr int64_t ORD_TAIL = 512;
+
+inline void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
+{
+    b.ld = spear_ld(S);
+    b.ord = c.take<uint16_t>((size_t)F * b.ld + ORD_TAIL);
+    b.pos = c.take<uint16_t>((size_t)F * b.ld);
+    b.runs = c.take<uint32_t>((size_t)F * b.ld);
+    b.tbits = c.take<uint64_t>((size_t)F * (b.ld / 64));
+    b.rlist = c.take<uint32_t>((size_t)F * (b.ld / 2));
+    b.nruns = c.take<int32_t>(F);
+    b.ncol = c.take<int32_t>(F);
+    b.hasties = c.take<int32_t>(F);
+    b.tcount = c.take<int32_t>(F);
+    b.perm = c.take<int32_t>(F);
+}
+
+// Sorts the columns of X into a base in `base` (spearman_base_bytes(S, F)
+// bytes, carved by base_carve then a keys buffer).  Defined in spearman.hip.
+int spearman_base_prepare_run(const float* X, int64_t S, int64_t F, int64_t ldx, void* base,
+                              const napy_opts* opts, hipStream_t st);
+size_t spearman_base_bytes(int64_t S, int64_t F);
+
+}  // namespace napy

@@ -275,6 +275,41 @@ def test_group_tests_arguments_rejected_on_host():
         == _lib.NAPY_E_INVALID
 
 
+def test_rank_tests_arguments_rejected_on_host():
+    lib = _lib.load()
+    o = _lib.make_opts("fp64")
+    O = ctypes.byref(o)
+    need = lib.napy_mannwhitney_workspace(100, 3, 5, O)
+    assert need > 0 and lib.napy_kruskal_workspace(100, 3, 5, 4, O) > 0
+    assert lib.napy_kruskal_workspace(100, 3, 5, 1, O) == 0 and lib.napy_kruskal_workspace(100, 3, 5, 33, O) == 0
+    assert lib.napy_mannwhitney_workspace(24577, 3, 5, O) == 0  # 16-bit sorted orders
+    WS = ctypes.c_void_p(0x2000000)
+    ok = dict(L=FAKE, ldl=3, X=FAKE, ldx=5, S=100, FC=3, FQ=5, m=0, u=FAKE, p=FAKE, n=FAKE, ldo=5, ws=WS, nb=need)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.napy_mannwhitney(a["L"], a["ldl"], a["X"], a["ldx"], a["S"], a["FC"], a["FQ"], a["m"], a["u"],
+                                    a["p"], a["n"], a["ldo"], a["ws"], a["nb"], O, None)
+
+    assert call(L=None) == _lib.NAPY_E_INVALID
+    assert call(X=None) == _lib.NAPY_E_INVALID
+    assert call(S=-1) == _lib.NAPY_E_INVALID
+    assert call(FQ=0) == _lib.NAPY_E_INVALID
+    assert call(ldl=2) == _lib.NAPY_E_INVALID
+    assert call(ldo=4) == _lib.NAPY_E_INVALID
+    assert call(m=2) == _lib.NAPY_E_INVALID
+    assert call(p=None) == _lib.NAPY_E_INVALID
+    assert call(S=30000) == _lib.NAPY_E_UNSUPPORTED
+    assert call(ws=None) == _lib.NAPY_E_WORKSPACE
+    assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
+    assert call(ws=ctypes.c_void_p(0x2000010)) == _lib.NAPY_E_WORKSPACE  # not 256-byte aligned
+    kneed = lib.napy_kruskal_workspace(100, 3, 5, 4, O)
+    assert lib.napy_kruskal(FAKE, 3, FAKE, 5, 100, 3, 5, 40, FAKE, FAKE, FAKE, 5, WS, kneed, O, None) \
+        == _lib.NAPY_E_INVALID
+    assert lib.napy_kruskal(FAKE, 3, FAKE, 5, 100, 3, 5, 4, FAKE, FAKE, FAKE, 5, WS, kneed - 1, O, None) \
+        == _lib.NAPY_E_WORKSPACE
+
+
 def test_chi2_sf_host_matches_high_precision():
     """The library's chi-squared tail Q(df/2, x/2) against mpmath at 40 digits."""
     import mpmath
