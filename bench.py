@@ -501,11 +501,12 @@ def run_adjust(args) -> int:
 
 
 def run_groups(args) -> int:
-    """Tests with categorical features: Student and Welch t-tests of 1,000
-    dichotomous against 1,000 continuous features, one-way ANOVA of 1,000
-    four-category against 1,000 continuous features, and chi-squared tests of
-    all pairs of 1,000 categorical features (2 to 4 labels); 10,000 samples,
-    30% missing; plus the oracle's rate on a sample of pairs."""
+    """Tests with categorical features: Student and Welch t-tests and
+    Mann-Whitney U of 1,000 dichotomous against 1,000 continuous features,
+    one-way ANOVA and Kruskal-Wallis H of 1,000 four-category against 1,000
+    continuous features, and chi-squared tests of all pairs of 1,000
+    categorical features (2 to 4 labels); 10,000 samples, 30% missing; plus
+    the oracle's rate on a sample of pairs."""
     import numpy as np
     import torch
 
@@ -524,7 +525,7 @@ def run_groups(args) -> int:
     opts = _lib.make_opts("fp64")
     res = {}
     host = {}
-    for name, ncat in (("student", 2), ("welch", 2), ("anova", 4)):
+    for name, ncat in (("student", 2), ("welch", 2), ("anova", 4), ("mannwhitney", 2), ("kruskal", 4)):
         L, X = synth.categorical_continuous(S, FC, FQ, ncat, seed=41 + ncat)
         host[name] = (L, X)
         Lt, Xt = torch.from_numpy(L).to(dev), torch.from_numpy(X).to(dev)
@@ -533,6 +534,10 @@ def run_groups(args) -> int:
         n = torch.empty((FC, FQ), dtype=torch.int32, device=dev)
         if name == "anova":
             need = lib.napy_anova_workspace(S, FC, FQ, ncat, ctypes.byref(opts))
+        elif name == "mannwhitney":
+            need = lib.napy_mannwhitney_workspace(S, FC, FQ, ctypes.byref(opts))
+        elif name == "kruskal":
+            need = lib.napy_kruskal_workspace(S, FC, FQ, ncat, ctypes.byref(opts))
         else:
             need = lib.napy_ttest_workspace(S, FC, FQ, ctypes.byref(opts))
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -542,6 +547,12 @@ def run_groups(args) -> int:
             if name == "anova":
                 st = lib.napy_anova(P(Lt), FC, P(Xt), FQ, S, FC, FQ, ncat, P(stat), P(pv), P(n), FQ, P(ws),
                                     ws.numel(), ctypes.byref(opts), sh)
+            elif name == "mannwhitney":
+                st = lib.napy_mannwhitney(P(Lt), FC, P(Xt), FQ, S, FC, FQ, 0, P(stat), P(pv), P(n), FQ, P(ws),
+                                          ws.numel(), ctypes.byref(opts), sh)
+            elif name == "kruskal":
+                st = lib.napy_kruskal(P(Lt), FC, P(Xt), FQ, S, FC, FQ, ncat, P(stat), P(pv), P(n), FQ, P(ws),
+                                      ws.numel(), ctypes.byref(opts), sh)
             else:
                 st = lib.napy_ttest(P(Lt), FC, P(Xt), FQ, S, FC, FQ, int(name == "welch"), P(stat), P(pv), P(n),
                                     FQ, P(ws), ws.numel(), ctypes.byref(opts), sh)
@@ -556,6 +567,11 @@ def run_groups(args) -> int:
             torch.cuda.synchronize(dev)
             ts.append(hip.ms(e0, e1))
         ms = float(np.median(ts))
+        if name in ("mannwhitney", "kruskal"):
+            # sort of the FQ columns plus one walk of S sorted positions per pair
+            res[name] = {"ms": ms, "pairs_per_s": FC * FQ / (ms * 1e-3),
+                         "walk_positions_per_s": FC * FQ * S / (ms * 1e-3)}
+            continue
         # FP64 MFMA work: three products of the FC*ncat group indicators with
         # FQ columns over S samples (indicator zeros included)
         mfma_flop = 3 * 2.0 * FC * ncat * FQ * S
@@ -607,7 +623,8 @@ def run_groups(args) -> int:
         "metric": "groups form: categorical x continuous tests with pairwise deletion",
         "value": res["welch"]["pairs_per_s"], "unit": "pairs/s (Welch t-test)", "n_gpus": 1,
         "higher_is_better": True, "form": "groups", "data": "synthetic",
-        "config": {"workload": "10,000 samples; 1,000 categorical (2 or 4 labels, each present) x 1,000 "
+        "config": {"workload": "10,000 samples; 1,000 categorical (2 labels: t-tests, Mann-Whitney; 4 labels: "
+                               "ANOVA, Kruskal-Wallis; each label present) x 1,000 "
                                "continuous features; 30% MCAR on both; a third of the continuous columns shifted "
                                "by a categorical column's label", "samples": S, "categorical": FC,
                    "continuous": FQ},

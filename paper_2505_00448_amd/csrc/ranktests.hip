@@ -34,6 +34,7 @@ namespace napy {
 
 constexpr int RK_WAVES = 8;
 constexpr int RK_THREADS = 64 * RK_WAVES;
+constexpr int RK_U = 4;  // chunks of 64 sorted positions per pipelined step
 constexpr int RK_EX_THREADS = 256;
 constexpr int RK_EX_BLOCKS = 64;  // concurrent exact-p computations
 constexpr int RK_EXACT_MAXM = 7;  // exact mode: the smaller group below eight
@@ -43,6 +44,7 @@ struct RankWs {
     uint8_t* lab;        // [FC][ld] labels as bytes
     uint64_t* catmask;   // [FC]
     int32_t* bad;        // [FC]
+    int32_t* cls;        // [FQ] tie handling class
     uint32_t* nexact;    // [1]
     int4* exact;         // [FC * FQ] (g, h, U, m | M << 16 as packed ints)
     double* slab;        // [RK_EX_BLOCKS][2][dmax + 1]
@@ -58,6 +60,7 @@ static void rk_carve(Carver& c, int64_t S, int64_t FC, int64_t FQ, bool mwu, Ran
     w.lab = c.take<uint8_t>((size_t)FC * spear_ld(S));
     w.catmask = c.take<uint64_t>(FC);
     w.bad = c.take<int32_t>(FC);
+    w.cls = c.take<int32_t>(FQ);
     w.nexact = c.take<uint32_t>(1);
     w.exact = c.take<int4>(mwu ? (size_t)FC * FQ : 1);
     w.dmax = rk_dmax(S);
@@ -109,18 +112,146 @@ __device__ __forceinline__ uint32_t rk_count(const uint2* tab, uint32_t x)
 
 __device__ __forceinline__ double normal_sf(double z) { return 0.5 * erfc(z * 0.70710678118654752440); }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Tie handling class of each continuous column: 0 no ties; 1 short runs,
+// handled after the walk by one lane per run (cheap when the runs are few
+// and short); 2 otherwise: a kept-count table along the column's order
+// gives every tied position its average rank during the walk.
+__global__ __launch_bounds__(256) void k_rank_cls(SpearBase bs, int64_t FQ, int32_t* __restrict__ cls)
+{
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= FQ) return;
+    const int nr = bs.nruns[c];
+    const uint32_t* rl = bs.rlist + c * (bs.ld / 2);
+    uint32_t mx = 0;
+    for (int r = lane; r < nr; r += 64) {
+        const uint32_t rr = rl[r];
+        mx = max(mx, (rr >> 16) - (rr & 0xFFFFu));
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+    if (lane == 0) {
+        const int64_t nch = (bs.ncol[c] + 63) / 64;
+        const int64_t serial = ceil_div(nr, 64) * (int64_t)mx;  // dependent steps of the run pass
+        cls[c] = nr == 0 ? 0 : (serial * 8 <= nch ? 1 : 2);
+    }
+}
+
+// One walk of h's sorted order for the labels g0 .. g0 + NA - 1: every kept
+// position gets its doubled rank 2 C1 (C1 = kept positions before it + 1), or
+// with TABLE the tied average C(s) + C(e) + 1; summed per label (acc, per
+// lane) and counted (cnt, wave-uniform).  Returns the kept count.  Chunks are
+// processed RK_U at a time with the next group's sorted orders in flight;
+// chunks from nch up to the group's end hold the dummy sample (never kept),
+// and reads past the column stay inside the ord allocation.
+template <int NA, bool TABLE>
+__device__ __forceinline__ uint32_t rank_walk(const uint16_t* __restrict__ ordH, const uint32_t* __restrict__ runsH,
+                                              const uint64_t* __restrict__ tbH, const uint8_t* labL,
+                                              const uint2* tab, int nch, int g0, int lane, uint32_t (&acc)[NA],
+                                              uint32_t (&cnt)[NA])
+{
+    uint32_t carry = 0;  // kept samples before the chunk (wave-uniform)
+    uint32_t nxt[RK_U];
+#pragma unroll
+    for (int j = 0; j < RK_U; ++j) nxt[j] = ordH[j * 64 + lane];
+    for (int c0 = 0; c0 < nch; c0 += RK_U) {
+        uint64_t tbw[RK_U];
+        uint32_t rr[RK_U];
+        if (TABLE) {
+            // tie bits of the group (ld / 64 is a multiple of RK_U) and the run
+            // bounds of its tied positions, loaded before the next group's
+            // orders so that waiting for them leaves those in flight
+#pragma unroll
+            for (int j = 0; j < RK_U; ++j) tbw[j] = tbH[c0 + j];
+#pragma unroll
+            for (int j = 0; j < RK_U; ++j) rr[j] = ((tbw[j] >> lane) & 1ull) ? runsH[(c0 + j) * 64 + lane] : 0u;
+        }
+        uint32_t lbs[RK_U];
+#pragma unroll
+        for (int j = 0; j < RK_U; ++j) lbs[j] = labL[nxt[j]];
+#pragma unroll
+        for (int j = 0; j < RK_U; ++j) nxt[j] = ordH[(c0 + RK_U + j) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < RK_U; ++j) {
+            const uint32_t lb = lbs[j];
+            const uint64_t m = __ballot(lb != 0xFFu);
+            uint32_t r2 = 2u * __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, carry)) + 2u;
+            if (TABLE && ((tbw[j] >> lane) & 1ull)) {
+                const uint32_t s = rr[j] & 0xFFFFu, e = rr[j] >> 16;
+                r2 = rk_count(tab, s) + rk_count(tab, e) + 1u;
+            }
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                const bool in = lb == (uint32_t)(g0 + k);
+                acc[k] += in ? r2 : 0u;
+                cnt[k] += (uint32_t)__popcll(__ballot(in));
+            }
+            carry += (uint32_t)__popcll(m);
+        }
+    }
+    return carry;
+}
+
+// Short tie runs, one lane per run: the walk gave the t kept members of a run
+// the doubled ranks 2 (C(s) + j), j = 1 .. t, their average is C(s) + C(e) + 1
+// = 2 C(s) + t + 1, so a member with label k changes label k's sum by
+// t + 1 - 2 j.  Adds t^3 - t per run to `tie` when `tieterm`.
+template <int NA>
+__device__ __forceinline__ void rank_short_runs(const uint16_t* __restrict__ ordH, const uint32_t* __restrict__ rl,
+                                                int nr, const uint8_t* labL, int g0, int lane, uint32_t (&acc)[NA],
+                                                bool tieterm, double& tie)
+{
+    for (int r = lane; r < nr; r += 64) {
+        const uint32_t rr = rl[r];
+        const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
+        uint32_t t = 0;
+        uint32_t nkr[NA], jsum[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) nkr[k] = jsum[k] = 0u;
+        for (uint32_t q = s; q < e; ++q) {
+            const uint32_t lb = labL[ordH[q]];
+            if (lb != 0xFFu) {
+                ++t;
+#pragma unroll
+                for (int k = 0; k < NA; ++k)
+                    if (lb == (uint32_t)(g0 + k)) {
+                        ++nkr[k];
+                        jsum[k] += t;
+                    }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) acc[k] += nkr[k] * (t + 1u) - 2u * jsum[k];  // modulo 2^32
+        if (tieterm) {
+            const double td = (double)t;
+            tie += td * td * td - td;
+        }
+    }
+}
+
 // test: 0 Mann-Whitney (auto), 1 Mann-Whitney (asymptotic), 2 Kruskal-Wallis.
 // The labels are summed in windows of NW (one walk per window), which bounds
-// the per-lane accumulators for up to 32 categories.
+// the per-lane accumulators for up to 32 categories.  With two labels only
+// label 0 is summed: label 1 holds the rest of n (n + 1) and of n.
 template <int NW>
-__global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const uint8_t* __restrict__ lab, int64_t S,
-                                                          int64_t FC, int64_t FQ, int test, int ncat,
+__global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const uint8_t* __restrict__ lab,
+                                                          const int32_t* __restrict__ cls, int64_t S, int64_t FC,
+                                                          int64_t FQ, int test, int ncat,
                                                           const uint64_t* __restrict__ catmask,
                                                           const int32_t* __restrict__ bad, double* __restrict__ stat,
                                                           double* __restrict__ pval, int32_t* __restrict__ nout,
                                                           int64_t ldo, uint32_t* __restrict__ nexact,
                                                           int4* __restrict__ exact)
 {
+    constexpr int NA = NW == 2 ? 1 : NW;
     extern __shared__ __attribute__((aligned(16))) unsigned char rk_smem[];
     __shared__ double res[RK_WAVES][2][32];  // per wave: doubled rank sums, counts
     const int64_t ld = bs.ld;
@@ -143,11 +274,14 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
     const uint16_t* ordH = bs.ord + h * ld;
     const uint32_t* runsH = bs.runs + h * ld;
     const uint64_t* tbH = bs.tbits + h * (ld / 64);
-    const bool tied = bs.hasties[h] != 0;
+    const uint32_t* rl = bs.rlist + h * (ld / 2);
+    const int nr = bs.nruns[h];
+    const int mode = cls[h];
     const int nch = (nh + 63) >> 6;
     uint2* tab = tabs + (size_t)wave * nwp;
 
-    if (tied) {
+    double tie = 0.0;  // sum of t^3 - t, exact below 2^53
+    if (mode == 2) {
         // kept bits along h's order (positions from nh on hold the dummy sample)
         const int NWD = (nh + 1 + 31) >> 5;
         for (int c = 0; c < (NWD + 1) / 2; ++c) {
@@ -168,48 +302,38 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
             run += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
         wave_sync_lds();
+        for (int r = lane; r < nr; r += 64) {
+            const uint32_t rr = rl[r];
+            const double t = (double)(rk_count(tab, rr >> 16) - rk_count(tab, rr & 0xFFFFu));
+            tie += t * t * t - t;
+        }
     }
 
-    double tie = 0.0;  // sum of t^3 - t, exact below 2^53
+    uint32_t ntot = 0;
     for (int g0 = 0; g0 < ncat; g0 += NW) {
-        uint32_t acc[NW];  // doubled rank sums of this lane's samples (below 2^32)
-        uint32_t cnt[NW];  // wave-uniform counts
+        uint32_t acc[NA];  // doubled rank sums of this lane's samples, modulo 2^32
+        uint32_t cnt[NA];  // wave-uniform counts
 #pragma unroll
-        for (int k = 0; k < NW; ++k) acc[k] = cnt[k] = 0u;
-        uint32_t carry = 0;  // kept samples before the chunk (wave-uniform)
-        for (int c = 0; c < nch; ++c) {
-            const uint32_t pos = (uint32_t)(c * 64 + lane);
-            const uint32_t iv = ordH[pos];
-            const uint32_t lb = labL[iv];
-            const uint64_t m = __ballot(lb != 0xFFu);
-            uint32_t r2 = 2u * (carry + mbcnt64(m) + 1u);
-            if (tied && tbH[c] != 0ull && pos < (uint32_t)nh) {
-                const uint32_t rr = runsH[pos];
-                const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
-                if (e - s > 1u) {
-                    const uint32_t cs = rk_count(tab, s), ce = rk_count(tab, e);
-                    r2 = cs + ce + 1u;
-                    if (pos == s && g0 == 0) {
-                        const double t = (double)(ce - cs);
-                        tie += t * t * t - t;
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                const bool in = lb == (uint32_t)(g0 + k);
-                acc[k] += in ? r2 : 0u;
-                cnt[k] += (uint32_t)__popcll(__ballot(in));
-            }
-            carry += (uint32_t)__popcll(m);
+        for (int k = 0; k < NA; ++k) acc[k] = cnt[k] = 0u;
+        if (mode == 2) {
+            ntot = rank_walk<NA, true>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt);
+        } else {
+            ntot = rank_walk<NA, false>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt);
+            if (mode == 1) rank_short_runs<NA>(ordH, rl, nr, labL, g0, lane, acc, g0 == 0, tie);
         }
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const double r2sum = wave_sum_f64((double)acc[k]);
+        for (int k = 0; k < NA; ++k) {
+            // the label's total is below 2^32, so the modular sum is exact
+            const uint32_t r2sum = wave_sum_u32(acc[k]);
             if (lane == 0 && g0 + k < 32) {
-                res[wave][0][g0 + k] = r2sum;
+                res[wave][0][g0 + k] = (double)r2sum;
                 res[wave][1][g0 + k] = (double)cnt[k];
             }
+        }
+        if (NW == 2 && lane == 0) {
+            const double n = (double)ntot;
+            res[wave][0][1] = n * (n + 1.0) - res[wave][0][0];
+            res[wave][1][1] = n - res[wave][1][0];
         }
     }
     const double T = wave_sum_f64(tie);
@@ -218,8 +342,6 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
     const double* R2 = res[wave][0];
     const double* nk = res[wave][1];
     double st = NAN, p = NAN;
-    double ntot = 0.0;
-    for (int k = 0; k < ncat; ++k) ntot += nk[k];
     const bool ok = bad[g] == 0;
     if (ok && test <= 1) {
         const double n0 = nk[0], n1 = nk[1];
@@ -243,7 +365,7 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
         // (the R_k add up to n (n + 1) / 2): no cancellation for small H
         const uint64_t cm = catmask[g];
         const int K = __popcll(cm);
-        const double n = ntot;
+        const double n = (double)ntot;
         bool empty = false;
         double s = 0.0;
         for (int k = 0; k < ncat; ++k) {
@@ -367,8 +489,8 @@ static int walk_launch(const RankWs& w, int64_t S, int64_t FC, int64_t FQ, int t
         attr = true;
     }
     hipLaunchKernelGGL(k_rank_walk<NW>, dim3((unsigned)FC, (unsigned)ceil_div(FQ, RK_WAVES)), dim3(RK_THREADS), smem,
-                       st, w.base, w.lab, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo, w.nexact,
-                       w.exact);
+                       st, w.base, w.lab, w.cls, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo,
+                       w.nexact, w.exact);
     return check_launch("rank walk");
 }
 
@@ -387,6 +509,8 @@ int ranktests_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int6
     hipLaunchKernelGGL(k_rank_labels, dim3((unsigned)ceil_div(FC, 64), (unsigned)ceil_div(w.base.ld, 64)), dim3(256),
                        0, st, L, ldl, S, FC, ncat, us, sv, w.base.ld, w.lab, w.nexact);
     NAPY_TRY(check_launch("rank labels"));
+    hipLaunchKernelGGL(k_rank_cls, dim3((unsigned)ceil_div(FQ, 4)), dim3(256), 0, st, w.base, FQ, w.cls);
+    NAPY_TRY(check_launch("rank classes"));
     if (ncat <= 2) NAPY_TRY(walk_launch<2>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
     else if (ncat <= 4) NAPY_TRY(walk_launch<4>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
     else NAPY_TRY(walk_launch<8>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));

@@ -116,6 +116,40 @@ def test_mannwhitney_many_exact_pairs(gpu_device):
     _check("mwu", _run("mwu", L, X, gpu_device), orank.mannwhitney(L, X), "many exact")
 
 
+def test_tie_patterns(gpu_device):
+    """Tie runs handled each way the library chooses: a few short runs (pairs
+    and triples, some across 64-position chunks), the same plus one long
+    run, many medium runs, and no ties."""
+    print("rank tests tie patterns", flush=True)
+    rng = np.random.default_rng(29)
+    S = 3000
+    cols = []
+    for kind in range(12):
+        x = rng.permutation(S).astype(np.float64)
+        if kind % 4 == 0:
+            for _ in range(25):
+                a, b = rng.choice(S, 2, replace=False)
+                x[b] = x[a]
+            t = rng.choice(S, 3, replace=False)
+            x[t] = x[t[0]]
+        elif kind % 4 == 1:
+            for _ in range(10):
+                a, b = rng.choice(S, 2, replace=False)
+                x[b] = x[a]
+            x[rng.choice(S, 300, replace=False)] = -1.0
+        elif kind % 4 == 2:
+            x = np.floor(x / 37.0)
+        cols.append(x)
+    X = np.column_stack(cols)
+    X[rng.random(X.shape) < 0.05] = np.nan
+    X = X.astype(np.float32)
+    L = rng.integers(0, 3, (S, 7)).astype(np.float32)
+    L[rng.random(L.shape) < 0.1] = np.nan
+    D = np.where(np.isnan(L), np.nan, L >= 1).astype(np.float32)
+    _check("mwu", _run("mwu", D, X, gpu_device), orank.mannwhitney(D, X), "tie patterns mwu")
+    _check("kw", _run("kw", L, X, gpu_device, ncat=3), orank.kruskal(L, X, ncat=3), "tie patterns kruskal")
+
+
 @pytest.mark.parametrize("ncat", [3, 5, 9, 17])
 def test_kruskal_matches_oracle(gpu_device, ncat):
     import synth
