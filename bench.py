@@ -62,9 +62,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "dcab5349c4e5d04a8cefe262c7bac29d3930c08bc12ed6120f3be52e51c2e068",
-    "fetch_kib": 141720.3,
-    "write_kib": 34861.8,
+    "source_sha256": "c5db03042a73f02874d4526f9003b24b531d5c2ca647535379916b4db361d5f0",
+    "fetch_kib": 141707.9,
+    "write_kib": 34872.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
@@ -73,7 +73,7 @@ SCAN_TRAFFIC = {
 def scan_source_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in ("spearman.hip", "napy_internal.hpp"):
+    for name in ("spearman.hip", "rankbase.hpp", "napy_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2505_00448_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

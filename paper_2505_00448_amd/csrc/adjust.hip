@@ -16,8 +16,9 @@
 //                    p >= 0; NaN -> all ones but the last bit, padding -> all
 //                    ones, so they sort after every p and padding last) and
 //                    pair indices i * F + j of the upper triangle, padded to
-//                    a power of two N >= ADJ_TILE; m counted by atomics.
-//   k_adj_factor     m, and the factor m or m c(m).
+//                    a power of two N >= ADJ_TILE; one workgroup per row,
+//                    which also counts the row's defined p-values.
+//   k_adj_factor     m (the sum of the row counts), and the factor m or m c(m).
 //   bitonic sort     k_bitonic_tile (LDS tiles of ADJ_TILE elements, every
 //                    step with a stride below the tile), k_bitonic_step (one
 //                    global step per larger stride).
@@ -42,6 +43,7 @@ struct AdjWs {
     uint64_t* keys;  // [N]; after the sort, q as double
     uint32_t* vals;  // [N]
     double* bmin;    // [N / ADJ_SCAN] block minima, then their exclusive suffix minima
+    uint32_t* rowm;  // [F] defined p-values per row of the upper triangle
     uint32_t* m;     // [1]
     double* factor;  // [1]
 };
@@ -61,6 +63,7 @@ static void adj_carve(Carver& c, int64_t F, AdjWs& w)
     w.keys = c.take<uint64_t>(N);
     w.vals = c.take<uint32_t>(N);
     w.bmin = c.take<double>(N / ADJ_SCAN);
+    w.rowm = c.take<uint32_t>(F);
     w.m = c.take<uint32_t>(1);
     w.factor = c.take<double>(1);
 }
@@ -74,34 +77,43 @@ size_t adjust_ws_bytes(int64_t F)
 }
 
 __global__ __launch_bounds__(256) void k_adj_pad(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                 int64_t from, int64_t N, uint32_t* __restrict__ m)
+                                                 int64_t from, int64_t N)
 {
     const int64_t k = from + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *m = 0u;
     if (k < N) {
         keys[k] = ADJ_KEY_PAD;
         vals[k] = ADJ_NO_PAIR;
     }
 }
 
-// row i = blockIdx.y, columns j = i + 1 + blockIdx.x * 256 + threadIdx.x
+__device__ __forceinline__ uint32_t block256_sum_u32(uint32_t v)
+{
+    __shared__ uint32_t part[4];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return part[0] + part[1] + part[2] + part[3];
+}
+
+// one workgroup per row i of the upper triangle: columns j > i
 __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ p, int64_t F, int64_t ldp,
                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                    uint32_t* __restrict__ m)
+                                                    uint32_t* __restrict__ rowm)
 {
-    const int64_t i = blockIdx.y;
-    const int64_t j = i + 1 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool defined = false;
-    if (j < F) {
+    const int64_t i = blockIdx.x;
+    const int64_t u0 = i * (2 * F - i - 1) / 2 - (i + 1);  // pair index u0 + j
+    uint32_t c = 0;
+    for (int64_t j = i + 1 + threadIdx.x; j < F; j += 256) {
         const double v = p[i * ldp + j];
-        defined = !isnan(v);
-        const int64_t u = i * (2 * F - i - 1) / 2 + (j - i - 1);
+        const bool defined = !isnan(v);
         // + 0.0 turns -0 into +0, whose bits sort first
-        keys[u] = defined ? (uint64_t)__double_as_longlong(v + 0.0) : ADJ_KEY_NAN;
-        vals[u] = (uint32_t)(i * F + j);
+        keys[u0 + j] = defined ? (uint64_t)__double_as_longlong(v + 0.0) : ADJ_KEY_NAN;
+        vals[u0 + j] = (uint32_t)(i * F + j);
+        c += defined ? 1u : 0u;
     }
-    const uint64_t b = __ballot(defined);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(m, (uint32_t)__popcll(b));
+    c = block256_sum_u32(c);
+    if (threadIdx.x == 0) rowm[i] = c;
 }
 
 // c(m) = sum_{i <= m} 1/i: summed from the small end below 1024 terms, else
@@ -119,10 +131,16 @@ __device__ double harmonic_number(uint32_t m)
     return log(x) + euler_gamma + 0.5 / x - x2 * (1.0 / 12.0 - x2 * (1.0 / 120.0 - x2 * (1.0 / 252.0)));
 }
 
-__global__ void k_adj_factor(const uint32_t* __restrict__ m, int method, double* __restrict__ factor)
+__global__ __launch_bounds__(256) void k_adj_factor(const uint32_t* __restrict__ rowm, int64_t rows, int method,
+                                                    uint32_t* __restrict__ m, double* __restrict__ factor)
 {
-    const uint32_t mm = *m;
-    *factor = method == NAPY_ADJ_BY ? (double)mm * harmonic_number(mm) : (double)mm;
+    uint32_t c = 0;
+    for (int64_t i = threadIdx.x; i < rows; i += 256) c += rowm[i];
+    const uint32_t mm = block256_sum_u32(c);
+    if (threadIdx.x == 0) {
+        *m = mm;
+        *factor = method == NAPY_ADJ_BY ? (double)mm * harmonic_number(mm) : (double)mm;
+    }
 }
 
 __device__ __forceinline__ void cmp_swap(uint64_t& ka, uint32_t& va, uint64_t& kb, uint32_t& vb, bool ascending)
@@ -313,14 +331,14 @@ int adjust_run(const double* p, int64_t F, int64_t ldp, double* out, int64_t ldo
     adj_carve(c, F, w);
     const int64_t np = adj_npairs(F), N = adj_n(F);
     hipLaunchKernelGGL(k_adj_pad, dim3((unsigned)ceil_div(N - np, 256) + 1), dim3(256), 0, st, w.keys, w.vals, np,
-                       N, w.m);
+                       N);
     NAPY_TRY(check_launch("adjust pad"));
     if (F > 1) {
-        hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)ceil_div(F - 1, 256), (unsigned)(F - 1)), dim3(256), 0, st,
-                           p, F, ldp, w.keys, w.vals, w.m);
+        hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)(F - 1)), dim3(256), 0, st, p, F, ldp, w.keys, w.vals,
+                           w.rowm);
         NAPY_TRY(check_launch("adjust gather"));
     }
-    hipLaunchKernelGGL(k_adj_factor, dim3(1), dim3(1), 0, st, w.m, method, w.factor);
+    hipLaunchKernelGGL(k_adj_factor, dim3(1), dim3(256), 0, st, w.rowm, F - 1, method, w.m, w.factor);
     NAPY_TRY(check_launch("adjust factor"));
     if (np > 0) {
         if (method == NAPY_ADJ_BONFERRONI) {
