@@ -44,7 +44,6 @@
 
 namespace napy {
 
-constexpr int SORT_THREADS = 1024;  // subset compaction
 constexpr int SPEARMAN_MAX_S = 24576;
 // column sort: 1024 threads (16 waves) and up to CS_EPT_MAX keys per thread
 constexpr int CS_THREADS = 1024;
@@ -1063,99 +1062,156 @@ __global__ __launch_bounds__(256) void k_rowmap_set(const int32_t* __restrict__ 
     if (j < Sq) rowmap[rows[j]] = (int32_t)j;
 }
 
+// Exclusive prefix sum of v over the 1024 threads of a workgroup; *total
+// gets the sum.  wtot: 16 words of LDS.
+__device__ __forceinline__ uint32_t block1024_excl_scan(uint32_t v, uint32_t* wtot, uint32_t* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan_u32(v);
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    const uint32_t wincl = wave_incl_scan_u32(lane < 16 ? wtot[lane] : 0u);
+    const uint32_t before = wave > 0 ? (uint32_t)__shfl((int)wincl, wave - 1, 64) : 0u;
+    *total = (uint32_t)__shfl((int)wincl, 15, 64);
+    __syncthreads();  // wtot may be reused
+    return before + incl - v;
+}
+
+constexpr int CP_THREADS = 1024;
+constexpr int CP_BATCH = 8;  // gathers in flight per thread
+
+__host__ __device__ inline size_t compact_smem_bytes(int64_t base_ld) { return (size_t)round_up(4 * base_ld + 2, 16); }
+
 // One 1024-thread workgroup per query column: keeps the base column's sorted
 // order restricted to the query rows (order preserved), renumbers samples and
 // positions, and maps tie runs through the prefix count of kept positions.
-__global__ __launch_bounds__(SORT_THREADS) void k_compact(SpearBase base, const int32_t* __restrict__ cols,
-                                                          const int32_t* __restrict__ rowmap, int64_t Sq,
-                                                          SpearBase q)
+//   A  X[k] = query row of the sample at base position k (0xFFFF: not in the
+//      query), gathers batched CP_BATCH per thread.
+//   B  P[k] = kept positions below k, one block scan with every thread owning
+//      a consecutive range of positions; the kept samples' new order and
+//      positions.
+//   C  the query's tie runs are the base runs keeping two or more samples,
+//      numbered in position order by a block scan over the base run list;
+//      QR[base run] = query run number (in X's place).
+//   D  run bounds of every kept position; a sample in a query tie run gets
+//      the flag and its run's number (through its base run index).
+__global__ __launch_bounds__(CP_THREADS) void k_compact(SpearBase base, const int32_t* __restrict__ cols,
+                                                         const int32_t* __restrict__ rowmap, int64_t Sq,
+                                                         SpearBase q)
 {
-    __shared__ uint16_t P[SPEARMAN_MAX_S + 1];  // kept positions below k
-    __shared__ uint16_t RQ[SPEARMAN_MAX_S];     // run index at a kept run's first position
-    __shared__ uint32_t nrun_sh;
-    __shared__ uint32_t wsum[16];
+    extern __shared__ __attribute__((aligned(16))) unsigned char cp_smem[];
+    __shared__ uint32_t wtot[16];
+    uint16_t* X = (uint16_t*)cp_smem;  // [base.ld]
+    uint16_t* P = X + base.ld;         // [base.ld + 1]
     const int qc = blockIdx.x;
+    const int t = threadIdx.x;
     const int64_t c = cols[qc];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nc = base.ncol[c];
     const uint16_t* ord = base.ord + c * base.ld;
     const uint32_t* runs = base.runs + c * base.ld;
+    const uint16_t* bpos = base.pos + c * base.ld;
+    const uint32_t* brl = base.rlist + c * (base.ld / 2);
+    const int nrb = base.nruns[c];
     uint16_t* qord = q.ord + (int64_t)qc * q.ld;
     uint16_t* qpos = q.pos + (int64_t)qc * q.ld;
     uint32_t* qruns = q.runs + (int64_t)qc * q.ld;
-    for (int64_t j = t; j < q.ld; j += SORT_THREADS) qpos[j] = 0xFFFF;
-    __syncthreads();
-    uint32_t carry = 0;
-    for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
-        const int k = k0 + t;
-        int32_t nr = -1;
-        if (k < nc) nr = rowmap[ord[k]];
-        const bool kept = nr >= 0;
-        const uint64_t m = __ballot(kept);
-        if (lane == 0) wsum[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t before = carry;
-        for (int w = 0; w < wave; ++w) before += wsum[w];
-        uint32_t tot = 0;
-        for (int w = 0; w < 16; ++w) tot += wsum[w];
-        const uint32_t kp = before + mbcnt64(m);
-        if (k < nc) P[k] = (uint16_t)kp;
-        if (kept) {
-            qord[kp] = (uint16_t)nr;
-            qpos[nr] = (uint16_t)kp;
-        }
-        carry += tot;
-        __syncthreads();
-    }
-    if (t == 0) P[nc] = (uint16_t)carry;
-    for (int64_t k = carry + t; k < q.ld; k += SORT_THREADS) qord[k] = (uint16_t)Sq;
-    if (qc == (int)gridDim.x - 1)
-        for (int64_t k = t; k < ORD_TAIL; k += SORT_THREADS) qord[q.ld + k] = (uint16_t)Sq;
-    __syncthreads();
-    // tie runs of the kept samples: each base run restricted to the kept
-    // positions; the ones still longer than 1 get run indices (in any order:
-    // every use of the index goes through the run list) and a list entry
     uint32_t* qrl = q.rlist + (int64_t)qc * (q.ld / 2);
-    if (t == 0) nrun_sh = 0;
-    __syncthreads();
-    int tie = 0;
-    for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
-        const int k = k0 + t;
-        if (k < nc) {
-            const int32_t nr = rowmap[ord[k]];
-            if (nr >= 0) {
-                const uint32_t rr = runs[k];
-                const uint32_t s0 = P[rr & 0xFFFFu], e0 = P[rr >> 16];
-                qruns[P[k]] = s0 | (e0 << 16);
-                const bool tied = e0 - s0 > 1u;
-                tie |= tied;
-                if (!tied) {
-                    qpos[nr] = (uint16_t)P[k];
-                } else if (P[k] == s0) {
-                    const uint32_t rid = atomicAdd(&nrun_sh, 1u);
-                    RQ[s0] = (uint16_t)rid;
-                    qrl[rid] = s0 | (e0 << 16);
-                }
-            }
+    for (int64_t j = t; j < q.ld; j += CP_THREADS) qpos[j] = 0xFFFF;
+
+    // A
+    for (int k0 = 0; k0 < nc; k0 += CP_BATCH * CP_THREADS) {
+        uint32_t iv[CP_BATCH];
+        int32_t nr[CP_BATCH];
+#pragma unroll
+        for (int u = 0; u < CP_BATCH; ++u) {
+            const int k = k0 + u * CP_THREADS + t;
+            iv[u] = ord[k < nc ? k : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < CP_BATCH; ++u) nr[u] = (k0 + u * CP_THREADS + t < nc) ? rowmap[iv[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < CP_BATCH; ++u) {
+            const int k = k0 + u * CP_THREADS + t;
+            if (k < nc) X[k] = nr[u] >= 0 ? (uint16_t)nr[u] : (uint16_t)0xFFFF;
         }
     }
     __syncthreads();
-    for (int k0 = 0; k0 < nc; k0 += SORT_THREADS) {
-        const int k = k0 + t;
-        if (k < nc) {
-            const int32_t nr = rowmap[ord[k]];
-            if (nr >= 0) {
-                const uint32_t rr = runs[k];
-                const uint32_t s0 = P[rr & 0xFFFFu], e0 = P[rr >> 16];
-                if (e0 - s0 > 1u) qpos[nr] = (uint16_t)(POS_TIED | RQ[s0]);
+
+    // B
+    const int E = (nc + CP_THREADS - 1) / CP_THREADS;
+    const int ka = min(t * E, nc), kb = min(ka + E, nc);
+    uint32_t cnt = 0;
+    for (int k = ka; k < kb; ++k) cnt += X[k] != 0xFFFF ? 1u : 0u;
+    uint32_t total;
+    uint32_t kp = block1024_excl_scan(cnt, wtot, &total);
+    for (int k = ka; k < kb; ++k) {
+        P[k] = (uint16_t)kp;
+        const uint32_t x = X[k];
+        if (x != 0xFFFFu) {
+            qord[kp] = (uint16_t)x;
+            qpos[x] = (uint16_t)kp;
+            ++kp;
+        }
+    }
+    if (t == 0) P[nc] = (uint16_t)total;
+    for (int64_t k = total + t; k < q.ld; k += CP_THREADS) qord[k] = (uint16_t)Sq;
+    if (qc == (int)gridDim.x - 1)
+        for (int64_t k = t; k < ORD_TAIL; k += CP_THREADS) qord[q.ld + k] = (uint16_t)Sq;
+    __syncthreads();
+
+    // C
+    uint16_t* QR = X;
+    const int Er = (nrb + CP_THREADS - 1) / CP_THREADS;
+    const int ra = min(t * Er, nrb), rz = min(ra + Er, nrb);
+    uint32_t nt = 0;
+    for (int r = ra; r < rz; ++r) {
+        const uint32_t rr = brl[r];
+        nt += (uint32_t)P[rr >> 16] - (uint32_t)P[rr & 0xFFFFu] > 1u ? 1u : 0u;
+    }
+    uint32_t nq;
+    uint32_t rid = block1024_excl_scan(nt, wtot, &nq);
+    for (int r = ra; r < rz; ++r) {
+        const uint32_t rr = brl[r];
+        const uint32_t s0 = P[rr & 0xFFFFu], e0 = P[rr >> 16];
+        if (e0 - s0 > 1u) {
+            QR[r] = (uint16_t)rid;
+            qrl[rid] = s0 | (e0 << 16);
+            ++rid;
+        }
+    }
+    __syncthreads();
+
+    // D
+    for (int k0 = 0; k0 < nc; k0 += CP_BATCH * CP_THREADS) {
+        uint32_t iv[CP_BATCH], rr[CP_BATCH];
+        int32_t nr[CP_BATCH];
+#pragma unroll
+        for (int u = 0; u < CP_BATCH; ++u) {
+            const int k = k0 + u * CP_THREADS + t;
+            iv[u] = ord[k < nc ? k : 0];
+            rr[u] = runs[k < nc ? k : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < CP_BATCH; ++u) nr[u] = (k0 + u * CP_THREADS + t < nc) ? rowmap[iv[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < CP_BATCH; ++u) {
+            const int k = k0 + u * CP_THREADS + t;
+            if (k >= nc || nr[u] < 0) continue;
+            const uint32_t kpk = P[k];
+            const uint32_t s = rr[u] & 0xFFFFu, e = rr[u] >> 16;
+            if (e - s == 1u) {
+                qruns[kpk] = kpk | ((kpk + 1u) << 16);
+            } else {
+                const uint32_t s0 = P[s], e0 = P[e];
+                qruns[kpk] = s0 | (e0 << 16);
+                if (e0 - s0 > 1u) qpos[nr[u]] = (uint16_t)(POS_TIED | QR[bpos[iv[u]] & POS_MASK]);
             }
         }
     }
-    const int anytie = __syncthreads_or(tie);
     if (t == 0) {
-        q.ncol[qc] = (int32_t)carry;
-        q.hasties[qc] = anytie;
-        q.nruns[qc] = (int32_t)nrun_sh;
+        q.ncol[qc] = (int32_t)total;
+        q.hasties[qc] = nq > 0u ? 1 : 0;
+        q.nruns[qc] = (int32_t)nq;
     }
 }
 
@@ -1365,8 +1421,18 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
         hipLaunchKernelGGL(k_rowmap_set, dim3((unsigned)ceil_div(Sq, 256)), dim3(256), 0, st, rows, Sq, rowmap);
         NAPY_TRY(check_launch("rowmap_set"));
     }
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)Fq), dim3(SORT_THREADS), 0, st, b, cols, rowmap, Sq, w.base);
-    NAPY_TRY(check_launch("compact"));
+    {
+        const size_t smem = compact_smem_bytes(b.ld);
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_compact, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)compact_smem_bytes(spear_ld(SPEARMAN_MAX_S)));
+            if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_compact)");
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)Fq), dim3(CP_THREADS), smem, st, b, cols, rowmap, Sq, w.base);
+        NAPY_TRY(check_launch("compact"));
+    }
     NAPY_TRY(tiebits_launch(w.base, Fq, st));
     PairOut po{w.sums, w.ab, nullptr, nullptr, 0, 0};
     NAPY_TRY(pairs_launch(w.base, w.pres, Sq, Fq, po, st));

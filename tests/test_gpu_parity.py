@@ -220,6 +220,39 @@ def test_subset_queries_match_full_calls(gpu_device):
         assert_r_close(_np(got["r"]), ro, 1e-12, "subset-spearman")
 
 
+def test_subset_queries_with_ties(gpu_device):
+    """Subset queries on a base with tie runs of every kind: few levels, long
+    runs, scattered pairs, a constant column.  Row subsets shrink runs to one
+    sample or empty them; the result must equal the full call on the
+    submatrix bit for bit, and the oracle."""
+    import torch
+    napy = _napy()
+    S = 2500
+    rng = np.random.default_rng(44)
+    X = np.concatenate([synth.heavy_ties(S, 6, levels=3, seed=7), synth.heavy_ties(S, 6, levels=40, seed=8),
+                        synth.cfg_serving_base(S=S, F=6)], axis=1).astype(np.float64)
+    for j in range(12, 18):
+        for _ in range(30):  # scattered duplicate pairs in continuous columns
+            a, b = rng.choice(S, 2, replace=False)
+            X[b, j] = X[a, j]
+    X = np.column_stack([X, np.full(S, 1.5)]).astype(np.float32)
+    Xd = _to_dev(X, gpu_device)
+    base = napy.SpearmanBase(Xd)
+    F = X.shape[1]
+    for trial, frac in enumerate((0.02, 0.3, 0.9, 1.0)):
+        rows = np.sort(rng.choice(S, size=max(3, int(frac * S)), replace=False)).astype(np.int32)
+        cols = rng.permutation(F)[: max(2, F - 3 * trial)].astype(np.int32)
+        print(f"subset with ties trial {trial}: {rows.size} rows, {cols.size} columns", flush=True)
+        got = base.subset(torch.from_numpy(rows).to(gpu_device), torch.from_numpy(cols).to(gpu_device))
+        sub = X[np.ix_(rows, cols)]
+        ref = napy.spearman(_to_dev(sub, gpu_device))
+        for k in ("r", "p", "n"):
+            assert np.array_equal(_np(got[k]), _np(ref[k]), equal_nan=True), (trial, k)
+        ro, po, no = orc.spearman(sub)
+        assert_counts_equal(_np(got["n"]), no, "subset-ties")
+        assert_r_close(_np(got["r"]), ro, 1e-12, "subset-ties")
+
+
 # ---------------------------------------------------------------------------
 # full-size headline configuration (10,000 x 1,000): sampled pairs + properties
 # ---------------------------------------------------------------------------
