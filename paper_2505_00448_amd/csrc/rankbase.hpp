@@ -18,6 +18,7 @@ struct SpearBase {
     int32_t* hasties;  // [F]
     int32_t* tcount;   // [F] number of positions in tie runs
     int32_t* perm;     // [F] processing order of the columns (see k_perm)
+    int32_t* tcls;     // [F] tie class: 0 no ties, 1 few short runs, 2 otherwise (see k_tcls)
     int64_t ld;
 };
 
@@ -42,6 +43,7 @@ inline void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
     b.hasties = c.take<int32_t>(F);
     b.tcount = c.take<int32_t>(F);
     b.perm = c.take<int32_t>(F);
+    b.tcls = c.take<int32_t>(F);
 }
 
 // Sorts the columns of X into a base in `base` (spearman_base_bytes(S, F)

@@ -44,7 +44,6 @@ struct RankWs {
     uint8_t* lab;        // [FC][ld] labels as bytes
     uint64_t* catmask;   // [FC]
     int32_t* bad;        // [FC]
-    int32_t* cls;        // [FQ] tie handling class
     uint32_t* nexact;    // [1]
     int4* exact;         // [FC * FQ] (g, h, U, m | M << 16 as packed ints)
     double* slab;        // [RK_EX_BLOCKS][2][dmax + 1]
@@ -60,7 +59,6 @@ static void rk_carve(Carver& c, int64_t S, int64_t FC, int64_t FQ, bool mwu, Ran
     w.lab = c.take<uint8_t>((size_t)FC * spear_ld(S));
     w.catmask = c.take<uint64_t>(FC);
     w.bad = c.take<int32_t>(FC);
-    w.cls = c.take<int32_t>(FQ);
     w.nexact = c.take<uint32_t>(1);
     w.exact = c.take<int4>(mwu ? (size_t)FC * FQ : 1);
     w.dmax = rk_dmax(S);
@@ -117,31 +115,6 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
-}
-
-// Tie handling class of each continuous column: 0 no ties; 1 short runs,
-// handled after the walk by one lane per run (cheap when the runs are few
-// and short); 2 otherwise: a kept-count table along the column's order
-// gives every tied position its average rank during the walk.
-__global__ __launch_bounds__(256) void k_rank_cls(SpearBase bs, int64_t FQ, int32_t* __restrict__ cls)
-{
-    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (c >= FQ) return;
-    const int nr = bs.nruns[c];
-    const uint32_t* rl = bs.rlist + c * (bs.ld / 2);
-    uint32_t mx = 0;
-    for (int r = lane; r < nr; r += 64) {
-        const uint32_t rr = rl[r];
-        mx = max(mx, (rr >> 16) - (rr & 0xFFFFu));
-    }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
-    if (lane == 0) {
-        const int64_t nch = (bs.ncol[c] + 63) / 64;
-        const int64_t serial = ceil_div(nr, 64) * (int64_t)mx;  // dependent steps of the run pass
-        cls[c] = nr == 0 ? 0 : (serial * 8 <= nch ? 1 : 2);
-    }
 }
 
 // One walk of h's sorted order for the labels g0 .. g0 + NA - 1: every kept
@@ -242,9 +215,8 @@ __device__ __forceinline__ void rank_short_runs(const uint16_t* __restrict__ ord
 // the per-lane accumulators for up to 32 categories.  With two labels only
 // label 0 is summed: label 1 holds the rest of n (n + 1) and of n.
 template <int NW>
-__global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const uint8_t* __restrict__ lab,
-                                                          const int32_t* __restrict__ cls, int64_t S, int64_t FC,
-                                                          int64_t FQ, int test, int ncat,
+__global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const uint8_t* __restrict__ lab, int64_t S,
+                                                          int64_t FC, int64_t FQ, int test, int ncat,
                                                           const uint64_t* __restrict__ catmask,
                                                           const int32_t* __restrict__ bad, double* __restrict__ stat,
                                                           double* __restrict__ pval, int32_t* __restrict__ nout,
@@ -276,7 +248,7 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
     const uint64_t* tbH = bs.tbits + h * (ld / 64);
     const uint32_t* rl = bs.rlist + h * (ld / 2);
     const int nr = bs.nruns[h];
-    const int mode = cls[h];
+    const int mode = bs.tcls[h];  // tie class: 0 none, 1 few short runs, 2 otherwise
     const int nch = (nh + 63) >> 6;
     uint2* tab = tabs + (size_t)wave * nwp;
 
@@ -489,8 +461,8 @@ static int walk_launch(const RankWs& w, int64_t S, int64_t FC, int64_t FQ, int t
         attr = true;
     }
     hipLaunchKernelGGL(k_rank_walk<NW>, dim3((unsigned)FC, (unsigned)ceil_div(FQ, RK_WAVES)), dim3(RK_THREADS), smem,
-                       st, w.base, w.lab, w.cls, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo,
-                       w.nexact, w.exact);
+                       st, w.base, w.lab, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo, w.nexact,
+                       w.exact);
     return check_launch("rank walk");
 }
 
@@ -509,8 +481,6 @@ int ranktests_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int6
     hipLaunchKernelGGL(k_rank_labels, dim3((unsigned)ceil_div(FC, 64), (unsigned)ceil_div(w.base.ld, 64)), dim3(256),
                        0, st, L, ldl, S, FC, ncat, us, sv, w.base.ld, w.lab, w.nexact);
     NAPY_TRY(check_launch("rank labels"));
-    hipLaunchKernelGGL(k_rank_cls, dim3((unsigned)ceil_div(FQ, 4)), dim3(256), 0, st, w.base, FQ, w.cls);
-    NAPY_TRY(check_launch("rank classes"));
     if (ncat <= 2) NAPY_TRY(walk_launch<2>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
     else if (ncat <= 4) NAPY_TRY(walk_launch<4>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
     else NAPY_TRY(walk_launch<8>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));

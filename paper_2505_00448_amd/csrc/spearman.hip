@@ -428,17 +428,46 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
     if (i < count) a[i] = 0;
 }
 
-// Processing order of the columns: columns whose values are mostly tied
-// (more than 1/8 of the observed positions in tie runs) first, then the
-// others, each group by decreasing observed count.  Pairs are walked along
-// the later column of this order: the walked side is the shorter one, and a
-// densely tied column is (nearly always) the fixed side, whose tie runs are
-// looked up per sample, which is cheaper than resolving runs while streaming.
+// Tie class of each column, from its run list: 0 no ties; 1 few short runs
+// (one lane per run can settle them after a walk that treats them as
+// untied: ceil(runs / 64) * longest run, times 8, at most the column's
+// 64-position chunks); 2 otherwise.
+__global__ __launch_bounds__(256) void k_tcls(SpearBase bs, int64_t F)
+{
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= F) return;
+    const int nr = bs.nruns[c];
+    const uint32_t* rl = bs.rlist + c * (bs.ld / 2);
+    uint32_t mx = 0;
+    for (int r = lane; r < nr; r += 64) {
+        const uint32_t rr = rl[r];
+        mx = max(mx, (rr >> 16) - (rr & 0xFFFFu));
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+    if (lane == 0) {
+        const int64_t nch = (bs.ncol[c] + 63) / 64;
+        const int64_t serial = ceil_div(nr, 64) * (int64_t)mx;
+        bs.tcls[c] = nr == 0 ? 0 : (serial * 8 <= nch ? 1 : 2);
+    }
+}
+
+// Processing order of the columns: first the columns whose ties are dense
+// (more than 1/8 of the observed positions in tie runs) or otherwise not few
+// and short, then the others; each group by decreasing observed count in
+// steps of 256, and within a step the untied columns before those with a few
+// short runs.  Pairs are walked along the later column of this order: the
+// walked side is the shorter one (to within a step), a column with dense or
+// long runs is (nearly always) the fixed side, whose tie runs are looked up
+// per sample, and a column with a few short runs is preferably the walked
+// side, whose runs are settled after the walk.
 __device__ __forceinline__ uint32_t perm_key(const SpearBase& bs, int64_t c)
 {
     const int32_t n = bs.ncol[c];
-    const bool dense = bs.tcount[c] * 8 > n;
-    return ((dense ? 0u : 1u) << 20) | (uint32_t)(65535 - n);
+    const int cls = bs.tcls[c];
+    const bool fixed_side = bs.tcount[c] * 8 > n || cls == 2;
+    return ((fixed_side ? 0u : 1u) << 20) | (((uint32_t)(65535 - n) >> 8) << 1) | (cls == 1 ? 1u : 0u);
 }
 
 // rank of each column's key (ties by column index): 64 columns per
@@ -475,6 +504,8 @@ static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
     NAPY_TRY(check_launch("fill"));
     hipLaunchKernelGGL(k_tiebits, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)F), dim3(256), 0, st, bs);
     NAPY_TRY(check_launch("tiebits"));
+    hipLaunchKernelGGL(k_tcls, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, bs, F);
+    NAPY_TRY(check_launch("tie classes"));
     hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 64)), dim3(256), 0, st, bs, F);
     return check_launch("perm");
 }
@@ -768,6 +799,37 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
     ws.Au = uA;
 }
 
+// Partner b with a few short tie runs, walked as untied: the t complete
+// samples of a run [s, e) got the doubled ranks 2 (C(s) + j), j = 1..t, whose
+// average is 2 C(s) + t + 1, so the sum of R_a R_b changes by
+// sum_j R_a,j (t + 1 - 2 j).  One lane per run; adds that to corr and
+// t^3 - t to d3B.
+template <bool TA>
+__device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ rlB,
+                                                    int nrb, const uint16_t* posA, const uint2* tab,
+                                                    const uint32_t* __restrict__ rlA, const uint32_t* rrun, int lane,
+                                                    int64_t& corr, uint64_t& d3B)
+{
+    for (int r = lane; r < nrb; r += 64) {
+        const uint32_t rr = rlB[r];
+        const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
+        uint32_t t = 0;
+        uint64_t sra = 0, sraj = 0;
+        for (uint32_t k = s; k < e; ++k) {
+            const uint32_t pv = posA[ordB[k]];
+            if (pv == 0xFFFFu) continue;
+            ++t;
+            uint32_t Ra;
+            if (TA && (pv & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pv);
+            else Ra = 2u * cnt1(tab, pv);
+            sra += Ra;
+            sraj += (uint64_t)Ra * t;
+        }
+        corr += (int64_t)((uint64_t)(t + 1u) * sra) - 2 * (int64_t)sraj;
+        if (t > 1u) d3B += cube_minus(t);
+    }
+}
+
 // LDS layout of the pair kernel for S samples and PB partners
 // llvm.amdgcn.writelane: old with one lane replaced by a wave-uniform value
 // (v_writelane_b32).  Declared through the intrinsic so that the compiler
@@ -985,18 +1047,31 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         const uint64_t* tbB = bs.tbits + b * (ld / 64);
         const uint2* tj = tab + (size_t)j * L.nwp;
         const uint32_t* rj = rtab ? rrun + j * RUN_TABLE_MAX : nullptr;
+        // b's tie runs resolved in the walk (class 2), or settled after an
+        // untied walk (class 1; the debug walk reports every rank, so it
+        // resolves them in the walk)
+        const int cB = DBG ? (tB ? 2 : 0) : bs.tcls[b];
         WalkSums w;
 #define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
         if (tA) {
-            if (tB) NAPY_WALK(true, true);
+            if (cB == 2) NAPY_WALK(true, true);
             else NAPY_WALK(true, false);
         } else {
-            if (tB) NAPY_WALK(false, true);
+            if (cB == 2) NAPY_WALK(false, true);
             else NAPY_WALK(false, false);
         }
 #undef NAPY_WALK
-        const uint64_t sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au;
-        const uint64_t d3B = tB ? wave_sum_u64(w.d3B) : 0ull;
+        int64_t corr = 0;
+        uint64_t d3s = 0;
+        if (!DBG && cB == 1) {
+            const uint32_t* rlB = bs.rlist + b * (ld / 2);
+            const int nrb = bs.nruns[b];
+            if (tA) settle_short_runs_b<true>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+            else settle_short_runs_b<false>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+        }
+        const uint64_t sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au +
+                            wave_sum_u64((uint64_t)corr);
+        const uint64_t d3B = tB ? wave_sum_u64(w.d3B + d3s) : 0ull;
         if (lane == 0 && !DBG) {
             const int64_t nn = (int64_t)w.n;
             const int64_t closed = sum_sq_doubled_untied(nn);
