@@ -19,6 +19,9 @@ struct SpearBase {
     int32_t* tcount;   // [F] number of positions in tie runs
     int32_t* perm;     // [F] processing order of the columns (see k_perm)
     int32_t* tcls;     // [F] tie class: 0 no ties, 1 few short runs, 2 otherwise (see k_tcls)
+    int32_t* nsing;    // [F] untied observed positions of a densely tied column whose tie runs and
+                       //     untied positions number at most RUN_GROUPS_MAX, else -1 (see k_tcls)
+    uint16_t* sing;    // [F][RUN_GROUPS_MAX] those untied positions, ascending
     int64_t ld;
 };
 
@@ -29,6 +32,9 @@ struct SpearBase {
 inline int64_t spear_ld(int64_t S) { return round_up(S + 1, 256); }
 // sorted orders may be read up to this many entries past the last row
 constexpr int64_t ORD_TAIL = 512;
+// value groups (tie runs plus untied positions) of a column whose ranks the
+// pair scan takes from a per-partner table in LDS
+constexpr int RUN_GROUPS_MAX = 23;
 
 inline void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
 {
@@ -44,6 +50,8 @@ inline void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
     b.tcount = c.take<int32_t>(F);
     b.perm = c.take<int32_t>(F);
     b.tcls = c.take<int32_t>(F);
+    b.nsing = c.take<int32_t>(F);
+    b.sing = c.take<uint16_t>((size_t)F * RUN_GROUPS_MAX);
 }
 
 // Sorts the columns of X into a base in `base` (spearman_base_bytes(S, F)

@@ -431,13 +431,17 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
 // Tie class of each column, from its run list: 0 no ties; 1 few short runs
 // (one lane per run can settle them after a walk that treats them as
 // untied: ceil(runs / 64) * longest run, times 8, at most the column's
-// 64-position chunks); 2 otherwise.
+// 64-position chunks); 2 otherwise.  A densely tied column (more than 1/8 of
+// its observed positions in runs) whose runs and untied positions number at
+// most RUN_GROUPS_MAX also gets the list of its untied positions (nsing; -1
+// for every other column).
 __global__ __launch_bounds__(256) void k_tcls(SpearBase bs, int64_t F)
 {
     const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (c >= F) return;
     const int nr = bs.nruns[c];
+    const int nc = bs.ncol[c];
     const uint32_t* rl = bs.rlist + c * (bs.ld / 2);
     uint32_t mx = 0;
     for (int r = lane; r < nr; r += 64) {
@@ -446,10 +450,37 @@ __global__ __launch_bounds__(256) void k_tcls(SpearBase bs, int64_t F)
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+    const int nsg = nc - bs.tcount[c];
+    const bool grouped = nr > 0 && bs.tcount[c] * 8 > nc && nr + nsg <= RUN_GROUPS_MAX;
+    if (grouped) {
+        // untied positions below nc: clear tie bits, one 64-bit word per lane
+        const uint64_t* tb = bs.tbits + c * (bs.ld / 64);
+        uint16_t* sg = bs.sing + c * RUN_GROUPS_MAX;
+        uint32_t base = 0;
+        for (int w0 = 0; w0 * 64 < nc; w0 += 64) {
+            const int w = w0 + lane;
+            uint64_t word = 0;
+            if (w * 64 < nc) {
+                word = ~tb[w];
+                const int valid = nc - w * 64;
+                if (valid < 64) word &= (1ull << valid) - 1ull;
+            }
+            const uint32_t cnt = (uint32_t)__popcll(word);
+            const uint32_t incl = wave_incl_scan_u32(cnt);
+            uint32_t at = base + incl - cnt;
+            while (word) {
+                const int bit = __builtin_ctzll(word);
+                sg[at++] = (uint16_t)(w * 64 + bit);
+                word &= word - 1ull;
+            }
+            base += (uint32_t)__shfl((int)incl, 63, 64);
+        }
+    }
     if (lane == 0) {
-        const int64_t nch = (bs.ncol[c] + 63) / 64;
+        const int64_t nch = (nc + 63) / 64;
         const int64_t serial = ceil_div(nr, 64) * (int64_t)mx;
         bs.tcls[c] = nr == 0 ? 0 : (serial * 8 <= nch ? 1 : 2);
+        bs.nsing[c] = grouped ? nsg : -1;
     }
 }
 
@@ -601,8 +632,13 @@ constexpr int WALK_U = 4;  // chunks of 64 positions per group; rows are padded 
 // a's tied samples: their stored position is the flag bit plus the index of
 // their tie run in a's run list.  With at most RUN_TABLE_MAX runs each run's
 // doubled average rank for the partner sits in LDS; with more, it comes from
-// the run's bounds (run list, global) and two table lookups.
-constexpr int RUN_TABLE_MAX = 20;
+// the run's bounds (run list, global) and two table lookups.  A grouped a
+// (its runs and untied positions at most RUN_GROUPS_MAX) has its untied
+// samples flagged as one-sample runs numbered after the runs, so every
+// sample's rank comes from the table; entry RUN_TABLE_MAX of a partner's
+// table is 0 (missing samples).
+constexpr int RUN_TABLE_MAX = RUN_GROUPS_MAX;
+constexpr int RUN_TABLE_STRIDE = RUN_TABLE_MAX + 1;
 
 // rank of a tied a-sample: from the run-rank table when a has at most
 // RUN_TABLE_MAX runs (rrun != nullptr), else from the run list
@@ -614,10 +650,12 @@ __device__ __forceinline__ uint32_t ra_of_tied(const uint2* tab, const uint32_t*
 }
 
 // One chunk of 64 positions of b's sorted order without tied b-positions.
-// b's C1 = carry1 + (complete samples at lower lanes) by mbcnt; a's C1 from
-// the partner table, 0 for missing or tied a-positions (both map to the
-// table's zero entry), whose products are added separately.
-template <bool TA, bool DBG>
+// b's C1 = carry1 + (complete samples at lower lanes) by mbcnt.  TA = 0 (a
+// untied) or 1 (a with ties): a's C1 from the partner table, 0 for missing
+// or tied a-positions (both map to the table's zero entry), whose products
+// are added separately.  TA = 2 (a grouped): every complete sample's R_a
+// from the run-rank table, no partner-table lookup and no branch.
+template <int TA, bool DBG>
 __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, const uint2* tab, uint32_t XS,
                                                   const uint32_t* __restrict__ rlA, const uint32_t* rrun,
                                                   uint32_t& carry1, uint32_t& t32, uint64_t& sAt,
@@ -625,20 +663,26 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
 {
     const bool kept = pv != 0xFFFFu;
     const uint64_t mask = __ballot(kept);
-    const uint32_t ca1 = cnt1(tab, min(pv, XS));
     const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, carry1));
-    t32 += __umul24(ca1, cb1);
-    bool tied = false;
-    if constexpr (TA) {
-        tied = kept && (pv & POS_TIED);
-        // R_a * C1_b < 2^31: one 32-bit product per sample
-        if (tied) sAt += __umul24(ra_of_tied(tab, rlA, rrun, pv), cb1);
-    }
-    if constexpr (DBG) {
-        if (kept) {
-            dbg_ra[iv] = (int32_t)(tied ? ra_of_tied(tab, rlA, rrun, pv) : 2u * ca1);
-            dbg_rb[iv] = (int32_t)(2u * cb1);
+    if constexpr (TA == 2) {
+        // missing: 0x7FFF -> the zero entry
+        const uint32_t Ra = rrun[min(pv & POS_MASK, (uint32_t)RUN_TABLE_MAX)];
+        sAt += __umul24(Ra, cb1);
+    } else {
+        const uint32_t ca1 = cnt1(tab, min(pv, XS));
+        t32 += __umul24(ca1, cb1);
+        bool tied = false;
+        if constexpr (TA == 1) {
+            tied = kept && (pv & POS_TIED);
+            // R_a * C1_b < 2^31: one 32-bit product per sample
+            if (tied) sAt += __umul24(ra_of_tied(tab, rlA, rrun, pv), cb1);
+        }
+        if constexpr (DBG) {
+            if (kept) {
+                dbg_ra[iv] = (int32_t)(tied ? ra_of_tied(tab, rlA, rrun, pv) : 2u * ca1);
+                dbg_rb[iv] = (int32_t)(2u * cb1);
+            }
         }
     }
     carry1 += (uint32_t)__popcll(mask);
@@ -655,7 +699,7 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
 // next chunk is carried as wave-uniform state (its start count, plus per
 // lane the a-ranks of its complete samples so far) and settled where it
 // ends, and the lane at each run's last position records t^3 - t for it.
-template <bool TA, bool TB, bool DBG>
+template <int TA, bool TB, bool DBG>
 __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
                                           const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ rlA,
                                           int nbv, const uint16_t* posA, const uint2* tab, const uint32_t* rrun,
@@ -804,7 +848,7 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
 // average is 2 C(s) + t + 1, so the sum of R_a R_b changes by
 // sum_j R_a,j (t + 1 - 2 j).  One lane per run; adds that to corr and
 // t^3 - t to d3B.
-template <bool TA>
+template <int TA>
 __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ rlB,
                                                     int nrb, const uint16_t* posA, const uint2* tab,
                                                     const uint32_t* __restrict__ rlA, const uint32_t* rrun, int lane,
@@ -820,7 +864,7 @@ __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__
             if (pv == 0xFFFFu) continue;
             ++t;
             uint32_t Ra;
-            if (TA && (pv & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pv);
+            if (TA != 0 && (pv & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pv);
             else Ra = 2u * cnt1(tab, pv);
             sra += Ra;
             sraj += (uint64_t)Ra * t;
@@ -886,7 +930,7 @@ struct PairSmem {
 };
 
 // posA: positions of samples 0..S (S is the dummy); tab: PB partner tables;
-// corr: PB tie-defect sums; rrun: [PB][RUN_TABLE_MAX] run ranks
+// corr: PB tie-defect sums; rrun: [PB][RUN_TABLE_STRIDE] run ranks
 __host__ __device__ inline PairSmem pair_smem(int64_t ld, int64_t S, int PB)
 {
     (void)ld;
@@ -895,7 +939,7 @@ __host__ __device__ inline PairSmem pair_smem(int64_t ld, int64_t S, int PB)
     m.off_tab = (size_t)round_up(2 * (S + 1), 16);
     m.off_corr = m.off_tab + (size_t)PB * m.nwp * 8;
     m.off_rrun = m.off_corr + (size_t)PB * 8;
-    m.bytes = m.off_rrun + (size_t)PB * RUN_TABLE_MAX * 4;
+    m.bytes = m.off_rrun + (size_t)PB * RUN_TABLE_STRIDE * 4;
     return m;
 }
 
@@ -951,7 +995,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     uint16_t* posA = (uint16_t*)smem_raw;
     uint2* tab = (uint2*)(smem_raw + L.off_tab);                               // [PB][nwp]
     unsigned long long* corrA = (unsigned long long*)(smem_raw + L.off_corr);  // [PB]
-    uint32_t* rrun = (uint32_t*)(smem_raw + L.off_rrun);                       // [PB][RUN_TABLE_MAX]
+    uint32_t* rrun = (uint32_t*)(smem_raw + L.off_rrun);                       // [PB][RUN_TABLE_STRIDE]
 
     const int na = bs.ncol[a];
     const int tA = bs.hasties[a];
@@ -959,6 +1003,9 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const uint32_t* rlA = bs.rlist + a * (ld / 2);
     const int nra = tA ? bs.nruns[a] : 0;
     const bool rtab = tA && nra <= RUN_TABLE_MAX;  // run-rank table in LDS
+    const int nsg = (!DBG && tA) ? bs.nsing[a] : -1;
+    const bool grouped = nsg >= 0;  // implies rtab (runs + untied positions <= RUN_TABLE_MAX)
+    const uint16_t* sgA = bs.sing + a * RUN_GROUPS_MAX;
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
     const int nc64 = (NW + 1) >> 1;
     // the partner block's presence bytes go where a's positions will be
@@ -1018,19 +1065,31 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     if (tA) {
         // per tie run [s, e) of a and partner: C(e) - C(s) complete samples
         // (tie defect) with doubled average rank C(s) + C(e) + 1 (run-rank
-        // table)
+        // table); a grouped a adds its untied positions as runs [s, s + 1)
+        // after the runs, and its untied samples' positions become those
+        // runs' numbers
         const int nj = DBG ? 1 : PB;
-        for (int r = threadIdx.x; r < nra; r += PAIR_THREADS) {
-            const uint32_t rr = rlA[r];
-            const uint32_t s = rr & 0xFFFFu, e = rr >> 16;
+        const int ngr = grouped ? nra + nsg : nra;
+        for (int r = threadIdx.x; r < ngr; r += PAIR_THREADS) {
+            uint32_t s, e;
+            if (r < nra) {
+                const uint32_t rr = rlA[r];
+                s = rr & 0xFFFFu;
+                e = rr >> 16;
+            } else {
+                s = sgA[r - nra];
+                e = s + 1u;
+                posA[ordA[s]] = (uint16_t)(POS_TIED | (uint32_t)r);
+            }
             for (int j = 0; j < nj; ++j) {
                 const uint2* tj = tab + (size_t)j * L.nwp;
                 const uint32_t c1s = cnt1(tj, s), c1e = cnt1(tj, e);
-                if (rtab) rrun[j * RUN_TABLE_MAX + r] = c1s + c1e - 1u;
+                if (rtab) rrun[j * RUN_TABLE_STRIDE + r] = c1s + c1e - 1u;
                 const uint32_t tt = c1e - c1s;
                 if (tt > 1u) atomicAdd(&corrA[j], (unsigned long long)cube_minus(tt));
             }
         }
+        if (rtab && threadIdx.x < nj) rrun[threadIdx.x * RUN_TABLE_STRIDE + RUN_TABLE_MAX] = 0u;
         __syncthreads();
     }
 
@@ -1046,19 +1105,22 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         const uint32_t* runsB = bs.runs + b * ld;
         const uint64_t* tbB = bs.tbits + b * (ld / 64);
         const uint2* tj = tab + (size_t)j * L.nwp;
-        const uint32_t* rj = rtab ? rrun + j * RUN_TABLE_MAX : nullptr;
+        const uint32_t* rj = rtab ? rrun + j * RUN_TABLE_STRIDE : nullptr;
         // b's tie runs resolved in the walk (class 2), or settled after an
         // untied walk (class 1; the debug walk reports every rank, so it
         // resolves them in the walk)
         const int cB = DBG ? (tB ? 2 : 0) : bs.tcls[b];
         WalkSums w;
 #define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
-        if (tA) {
-            if (cB == 2) NAPY_WALK(true, true);
-            else NAPY_WALK(true, false);
+        if (grouped) {
+            if (cB == 2) NAPY_WALK(2, true);
+            else NAPY_WALK(2, false);
+        } else if (tA) {
+            if (cB == 2) NAPY_WALK(1, true);
+            else NAPY_WALK(1, false);
         } else {
-            if (cB == 2) NAPY_WALK(false, true);
-            else NAPY_WALK(false, false);
+            if (cB == 2) NAPY_WALK(0, true);
+            else NAPY_WALK(0, false);
         }
 #undef NAPY_WALK
         int64_t corr = 0;
@@ -1066,8 +1128,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         if (!DBG && cB == 1) {
             const uint32_t* rlB = bs.rlist + b * (ld / 2);
             const int nrb = bs.nruns[b];
-            if (tA) settle_short_runs_b<true>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
-            else settle_short_runs_b<false>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+            if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+            else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
         }
         const uint64_t sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au +
                             wave_sum_u64((uint64_t)corr);
