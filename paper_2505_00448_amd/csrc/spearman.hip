@@ -874,6 +874,103 @@ __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__
     }
 }
 
+// Walk of a grouped partner b (its tie runs and untied positions, at most
+// RUN_GROUPS_MAX groups, partition its observed positions): every complete
+// sample of a group has the group's doubled average rank 2 C + t + 1 (C
+// complete samples before the group, t in it), so the sum of R_a R_b is
+// sum over groups of that rank times the group's sum of R_a.  One pass over
+// b's order, four chunks in flight; each lane sums R_a of its samples in the
+// open group, which is closed (one wave sum) at its end.  Returns the sum,
+// n and the tie defect sum of t^3 - t.
+template <int TA>
+__device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB, int nbv,
+                                               const uint32_t* __restrict__ rlB, int nrb,
+                                               const uint16_t* __restrict__ sgB, int nsgB, const uint16_t* posA,
+                                               const uint2* tab, const uint32_t* __restrict__ rlA,
+                                               const uint32_t* rrun, uint32_t XS, int lane, uint64_t& sum,
+                                               uint32_t& n, uint64_t& d3B)
+{
+    constexpr int U = WALK_U;
+    // group starts in position order: lane g holds the start of group g,
+    // lane G (the group count) holds nbv, lanes above it all ones
+    const uint32_t rsv = lane < nrb ? rlB[lane] & 0xFFFFu : 0xFFFFFFFFu;
+    const uint32_t sgv = lane < nsgB ? (uint32_t)sgB[lane] : 0xFFFFFFFFu;
+    const int G = nrb + nsgB;
+    uint32_t bnd = lane == G ? (uint32_t)nbv : 0xFFFFFFFFu;
+    {
+        int ir = 0, is = 0;
+        for (int g = 0; g < G; ++g) {
+            const uint32_t r = ir < nrb ? (uint32_t)__builtin_amdgcn_readlane((int)rsv, ir) : 0xFFFFFFFFu;
+            const uint32_t q = is < nsgB ? (uint32_t)__builtin_amdgcn_readlane((int)sgv, is) : 0xFFFFFFFFu;
+            const uint32_t st = r < q ? r : q;
+            if (r < q) ++ir;
+            else ++is;
+            if (lane == g) bnd = st;
+        }
+    }
+    int gcur = 0;
+    uint32_t gnext = (uint32_t)__builtin_amdgcn_readlane((int)bnd, 1);
+    uint32_t carry = 0, t = 0, acc = 0;
+    uint64_t tot = 0, d3 = 0;
+    const int ngrp = (((nbv + 63) >> 6) + U - 1) / U;
+    uint32_t ivn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ivn[u] = ordB[u * 64 + lane];
+    for (int gi = 0; gi < ngrp; ++gi) {
+        uint32_t pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pv[u] = posA[ivn[u]];
+        // rows are padded to whole groups of U chunks; the read past the
+        // last group stays inside the ord allocation
+#pragma unroll
+        for (int u = 0; u < U; ++u) ivn[u] = ordB[((gi + 1) * U + u) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t c0 = (uint32_t)((gi * U + u) * 64);
+            const uint32_t k = c0 + (uint32_t)lane;
+            const uint32_t p = pv[u];
+            const bool kept = p != 0xFFFFu;  // positions from nbv on hold the dummy sample
+            uint32_t Ra;
+            if constexpr (TA == 2) {
+                Ra = rrun[min(p & POS_MASK, (uint32_t)RUN_TABLE_MAX)];
+            } else {
+                Ra = 2u * cnt1(tab, min(p, XS));
+                if constexpr (TA == 1)
+                    if (kept && (p & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, p);
+            }
+            uint32_t val = kept ? Ra : 0u;  // R_a >= 1 for a complete sample
+            while (gnext < c0 + 64u) {
+                // the open group ends inside this chunk
+                const bool in = k < gnext;
+                const uint32_t v = in ? val : 0u;
+                acc += v;
+                t += (uint32_t)__popcll(__ballot(v != 0u));
+                val = in ? 0u : val;
+                const uint32_t sra = wave_sum_u32(acc);  // below 2^32: t * (2 S + 1)
+                tot += (uint64_t)(2u * carry + t + 1u) * sra;
+                if (t > 1u) d3 += cube_minus(t);
+                carry += t;
+                acc = 0u;
+                t = 0u;
+                ++gcur;
+                gnext = (uint32_t)__builtin_amdgcn_readlane((int)bnd, gcur + 1);
+            }
+            acc += val;
+            t += (uint32_t)__popcll(__ballot(val != 0u));
+        }
+    }
+    if (gcur < G) {
+        // the last group ends with the walked chunks (nbv a multiple of 64 U)
+        const uint32_t sra = wave_sum_u32(acc);
+        tot += (uint64_t)(2u * carry + t + 1u) * sra;
+        if (t > 1u) d3 += cube_minus(t);
+        carry += t;
+    }
+    sum = tot;
+    n = carry;
+    d3B = d3;
+}
+
 // LDS layout of the pair kernel for S samples and PB partners
 // llvm.amdgcn.writelane: old with one lane replaced by a wave-uniform value
 // (v_writelane_b32).  Declared through the intrinsic so that the compiler
@@ -1110,30 +1207,44 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         // untied walk (class 1; the debug walk reports every rank, so it
         // resolves them in the walk)
         const int cB = DBG ? (tB ? 2 : 0) : bs.tcls[b];
+        const int nsgB = DBG ? -1 : bs.nsing[b];
         WalkSums w;
-#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
-        if (grouped) {
-            if (cB == 2) NAPY_WALK(2, true);
-            else NAPY_WALK(2, false);
-        } else if (tA) {
-            if (cB == 2) NAPY_WALK(1, true);
-            else NAPY_WALK(1, false);
-        } else {
-            if (cB == 2) NAPY_WALK(0, true);
-            else NAPY_WALK(0, false);
-        }
-#undef NAPY_WALK
-        int64_t corr = 0;
-        uint64_t d3s = 0;
-        if (!DBG && cB == 1) {
+        uint64_t sA, d3B;
+        if (nsgB >= 0) {
+            // b grouped: one pass by value groups
             const uint32_t* rlB = bs.rlist + b * (ld / 2);
             const int nrb = bs.nruns[b];
-            if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
-            else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+            const uint16_t* sgB = bs.sing + b * RUN_GROUPS_MAX;
+            uint32_t ng;
+            if (grouped) grouped_b_walk<2>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, lane, sA, ng, d3B);
+            else if (tA) grouped_b_walk<1>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, lane, sA, ng, d3B);
+            else grouped_b_walk<0>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, lane, sA, ng, d3B);
+            w.n = ng;
+        } else {
+#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
+            if (grouped) {
+                if (cB == 2) NAPY_WALK(2, true);
+                else NAPY_WALK(2, false);
+            } else if (tA) {
+                if (cB == 2) NAPY_WALK(1, true);
+                else NAPY_WALK(1, false);
+            } else {
+                if (cB == 2) NAPY_WALK(0, true);
+                else NAPY_WALK(0, false);
+            }
+#undef NAPY_WALK
+            int64_t corr = 0;
+            uint64_t d3s = 0;
+            if (!DBG && cB == 1) {
+                const uint32_t* rlB = bs.rlist + b * (ld / 2);
+                const int nrb = bs.nruns[b];
+                if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+                else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+            }
+            sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au +
+                 wave_sum_u64((uint64_t)corr);
+            d3B = tB ? wave_sum_u64(w.d3B + d3s) : 0ull;
         }
-        const uint64_t sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au +
-                            wave_sum_u64((uint64_t)corr);
-        const uint64_t d3B = tB ? wave_sum_u64(w.d3B + d3s) : 0ull;
         if (lane == 0 && !DBG) {
             const int64_t nn = (int64_t)w.n;
             const int64_t closed = sum_sq_doubled_untied(nn);

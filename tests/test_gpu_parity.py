@@ -351,6 +351,38 @@ def test_tie_runs_across_chunks(gpu_device):
     _check_full("spearman", X, gpu_device, where="tie-stress")
 
 
+def _grouped_matrix(S=1024, seed=31):
+    """Columns of few value groups (tie runs plus untied values, at most a
+    couple of dozen), with observed counts that are exact multiples of 64 and
+    256, next to untied columns and columns with a few duplicate pairs."""
+    rng = np.random.default_rng(seed)
+
+    def observe(x, count):
+        x = x.astype(np.float64)
+        x[rng.permutation(S)[count:]] = np.nan
+        return x
+
+    cols = [observe(rng.poisson(3, S), 256), observe(rng.poisson(4, S), 512), observe(rng.poisson(2, S), 640),
+            rng.poisson(4, S).astype(np.float64)]
+    few = rng.integers(0, 6, S).astype(np.float64)
+    few[rng.choice(S, 3, replace=False)] = [100.0, 101.5, -7.0]  # three untied values
+    cols.append(observe(few, 700))
+    cols.append(observe(rng.integers(0, 15, S), 900))
+    x = rng.standard_normal(S)
+    cols.append(observe(x, 716))
+    d = rng.standard_normal(S)
+    for _ in range(4):
+        a, b = rng.choice(S, 2, replace=False)
+        d[b] = d[a]
+    cols.append(observe(d, 830))
+    return np.column_stack(cols).astype(np.float32)
+
+
+def test_grouped_columns(gpu_device):
+    X = _grouped_matrix()
+    _check_full("spearman", X, gpu_device, where="grouped-columns")
+
+
 def test_tie_runs_ranks_bit_exact(gpu_device):
     napy = _napy()
     X = _tie_stress_matrix(S=1500, seed=5)
