@@ -62,9 +62,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "c5db03042a73f02874d4526f9003b24b531d5c2ca647535379916b4db361d5f0",
-    "fetch_kib": 141707.9,
-    "write_kib": 34872.0,
+    "source_sha256": "9273be464fe8b51219ef25220a8887da339902dec55a5c73984b05320c1c342c",
+    "fetch_kib": 139982.2,
+    "write_kib": 25771.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }

@@ -428,6 +428,20 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
     if (i < count) a[i] = 0;
 }
 
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
 // Tie class of each column, from its run list: 0 no ties; 1 few short runs
 // (one lane per run can settle them after a walk that treats them as
 // untied: ceil(runs / 64) * longest run, times 8, at most the column's
@@ -501,32 +515,21 @@ __device__ __forceinline__ uint32_t perm_key(const SpearBase& bs, int64_t c)
     return ((fixed_side ? 0u : 1u) << 20) | (((uint32_t)(65535 - n) >> 8) << 1) | (cls == 1 ? 1u : 0u);
 }
 
-// rank of each column's key (ties by column index): 64 columns per
-// workgroup, four threads per column over the other keys, staged in LDS
+// rank of each column's key (ties by column index), one wave per column
+// comparing against all keys, then the column goes to that place of perm
 __global__ __launch_bounds__(256) void k_perm(SpearBase bs, int64_t F)
 {
-    __shared__ uint32_t kd_s[1024];
-    __shared__ uint32_t part[4][64];
-    const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t c = (int64_t)blockIdx.x * 64 + cl;
-    const uint32_t kc = c < F ? perm_key(bs, c) : 0u;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= F) return;
+    const uint32_t kc = perm_key(bs, c);
     uint32_t rank = 0;
-    for (int64_t d0 = 0; d0 < F; d0 += 1024) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 1024; i += 256) {
-            const int64_t d = d0 + i;
-            kd_s[i] = d < F ? perm_key(bs, d) : 0u;
-        }
-        __syncthreads();
-        const int nd = (int)min((int64_t)1024, F - d0);
-        for (int i = q; i < nd; i += 4) {
-            const uint32_t kd = kd_s[i];
-            rank += (kd < kc) || (kd == kc && d0 + i < c);
-        }
+    for (int64_t d = lane; d < F; d += 64) {
+        const uint32_t kd = perm_key(bs, d);
+        rank += (kd < kc) || (kd == kc && d < c);
     }
-    part[q][cl] = rank;
-    __syncthreads();
-    if (q == 0 && c < F) bs.perm[part[0][cl] + part[1][cl] + part[2][cl] + part[3][cl]] = (int32_t)c;
+    rank = wave_sum_u32(rank);
+    if (lane == 0) bs.perm[rank] = (int32_t)c;
 }
 
 static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
@@ -537,7 +540,7 @@ static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
     NAPY_TRY(check_launch("tiebits"));
     hipLaunchKernelGGL(k_tcls, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, bs, F);
     NAPY_TRY(check_launch("tie classes"));
-    hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 64)), dim3(256), 0, st, bs, F);
+    hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, bs, F);
     return check_launch("perm");
 }
 
@@ -563,20 +566,6 @@ __global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64
 
 constexpr int PAIR_THREADS = 512;
 constexpr int PAIR_WAVES = PAIR_THREADS / 64;
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
 
 // bits of `mask` at lanes below x (x in 0..64)
 __device__ __forceinline__ uint64_t bits_below(uint64_t mask, uint32_t x)
