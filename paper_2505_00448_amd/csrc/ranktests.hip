@@ -15,9 +15,13 @@
 //   labels_launch (shared)  observed-label mask and invalid flag per column.
 //   k_rank_labels           labels transposed to bytes per column (0xFF:
 //                           missing or not a label of the test).
-//   k_rank_walk<NG>         one categorical column g and 8 continuous columns
+//   k_rank_walk<NW>         one categorical column g and 8 continuous columns
 //                           per workgroup, one wave per pair: the walk, the
 //                           group rank sums and counts, then U or H, p and n.
+//                           Two labels: label 0 summed with selects; more:
+//                           windows of four labels, each position's doubled
+//                           rank added by one LDS atomic to its lane's slot
+//                           of its label.
 //   k_mwu_exact             pairs whose p is exact (no ties within I and a
 //                           group below eight samples): the distribution of U
 //                           from the generating function
@@ -120,15 +124,17 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 // One walk of h's sorted order for the labels g0 .. g0 + NA - 1: every kept
 // position gets its doubled rank 2 C1 (C1 = kept positions before it + 1), or
 // with TABLE the tied average C(s) + C(e) + 1; summed per label (acc, per
-// lane) and counted (cnt, wave-uniform).  Returns the kept count.  Chunks are
+// lane) and counted (cnt, wave-uniform) with selects and ballots, or with
+// LDSACC added with one LDS atomic per position into the lane's slot of its
+// label in accw (sum in the low 40 bits, count above).  Returns the kept count.  Chunks are
 // processed RK_U at a time with the next group's sorted orders in flight;
 // chunks from nch up to the group's end hold the dummy sample (never kept),
 // and reads past the column stay inside the ord allocation.
-template <int NA, bool TABLE>
+template <int NA, bool TABLE, bool LDSACC>
 __device__ __forceinline__ uint32_t rank_walk(const uint16_t* __restrict__ ordH, const uint32_t* __restrict__ runsH,
                                               const uint64_t* __restrict__ tbH, const uint8_t* labL,
                                               const uint2* tab, int nch, int g0, int lane, uint32_t (&acc)[NA],
-                                              uint32_t (&cnt)[NA])
+                                              uint32_t (&cnt)[NA], unsigned long long* accw)
 {
     uint32_t carry = 0;  // kept samples before the chunk (wave-uniform)
     uint32_t nxt[RK_U];
@@ -161,11 +167,17 @@ __device__ __forceinline__ uint32_t rank_walk(const uint16_t* __restrict__ ordH,
                 const uint32_t s = rr[j] & 0xFFFFu, e = rr[j] >> 16;
                 r2 = rk_count(tab, s) + rk_count(tab, e) + 1u;
             }
+            if constexpr (LDSACC) {
+                // this lane's slot of the sample's label: count in bits 40 and up
+                const uint32_t kk = lb - (uint32_t)g0;
+                if (kk < (uint32_t)NA) atomicAdd(&accw[kk * 64u + (uint32_t)lane], (1ull << 40) | r2);
+            } else {
 #pragma unroll
-            for (int k = 0; k < NA; ++k) {
-                const bool in = lb == (uint32_t)(g0 + k);
-                acc[k] += in ? r2 : 0u;
-                cnt[k] += (uint32_t)__popcll(__ballot(in));
+                for (int k = 0; k < NA; ++k) {
+                    const bool in = lb == (uint32_t)(g0 + k);
+                    acc[k] += in ? r2 : 0u;
+                    cnt[k] += (uint32_t)__popcll(__ballot(in));
+                }
             }
             carry += (uint32_t)__popcll(m);
         }
@@ -212,7 +224,7 @@ __device__ __forceinline__ void rank_short_runs(const uint16_t* __restrict__ ord
 
 // test: 0 Mann-Whitney (auto), 1 Mann-Whitney (asymptotic), 2 Kruskal-Wallis.
 // The labels are summed in windows of NW (one walk per window), which bounds
-// the per-lane accumulators for up to 32 categories.  With two labels only
+// the per-lane accumulators (in LDS for NW > 2) for up to 32 categories.  With two labels only
 // label 0 is summed: label 1 holds the rest of n (n + 1) and of n.
 template <int NW>
 __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const uint8_t* __restrict__ lab, int64_t S,
@@ -224,6 +236,7 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
                                                           int4* __restrict__ exact)
 {
     constexpr int NA = NW == 2 ? 1 : NW;
+    constexpr bool LDSACC = NW > 2;
     extern __shared__ __attribute__((aligned(16))) unsigned char rk_smem[];
     __shared__ double res[RK_WAVES][2][32];  // per wave: doubled rank sums, counts
     const int64_t ld = bs.ld;
@@ -251,6 +264,7 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
     const int mode = bs.tcls[h];  // tie class: 0 none, 1 few short runs, 2 otherwise
     const int nch = (nh + 63) >> 6;
     uint2* tab = tabs + (size_t)wave * nwp;
+    unsigned long long* accw = (unsigned long long*)(tabs + (size_t)RK_WAVES * nwp) + (size_t)wave * NA * 64;
 
     double tie = 0.0;  // sum of t^3 - t, exact below 2^53
     if (mode == 2) {
@@ -283,15 +297,29 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
 
     uint32_t ntot = 0;
     for (int g0 = 0; g0 < ncat; g0 += NW) {
-        uint32_t acc[NA];  // doubled rank sums of this lane's samples, modulo 2^32
+        uint32_t acc[NA];  // doubled rank sums (or their corrections) of this lane, modulo 2^32
         uint32_t cnt[NA];  // wave-uniform counts
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k] = cnt[k] = 0u;
+        if constexpr (LDSACC) {
+#pragma unroll
+            for (int k = 0; k < NA; ++k) accw[k * 64 + lane] = 0ull;
+            wave_sync_lds();
+        }
         if (mode == 2) {
-            ntot = rank_walk<NA, true>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt);
+            ntot = rank_walk<NA, true, LDSACC>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt, accw);
         } else {
-            ntot = rank_walk<NA, false>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt);
+            ntot = rank_walk<NA, false, LDSACC>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt, accw);
             if (mode == 1) rank_short_runs<NA>(ordH, rl, nr, labL, g0, lane, acc, g0 == 0, tie);
+        }
+        if constexpr (LDSACC) {
+            wave_sync_lds();
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                const unsigned long long v = accw[k * 64 + lane];
+                acc[k] += (uint32_t)(v & ((1ull << 40) - 1ull));
+                cnt[k] = wave_sum_u32((uint32_t)(v >> 40));
+            }
         }
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
@@ -452,7 +480,8 @@ template <int NW>
 static int walk_launch(const RankWs& w, int64_t S, int64_t FC, int64_t FQ, int test, int ncat, double* stat,
                        double* p, int32_t* n, int64_t ldo, hipStream_t st)
 {
-    const size_t smem = (size_t)round_up(w.base.ld, 16) + (size_t)RK_WAVES * ((S + 1 + 31) / 32 + 1) * 8;
+    const size_t smem = (size_t)round_up(w.base.ld, 16) + (size_t)RK_WAVES * ((S + 1 + 31) / 32 + 1) * 8 +
+                        (NW > 2 ? (size_t)RK_WAVES * NW * 64 * 8 : 0);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_rank_walk<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -482,8 +511,7 @@ int ranktests_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int6
                        0, st, L, ldl, S, FC, ncat, us, sv, w.base.ld, w.lab, w.nexact);
     NAPY_TRY(check_launch("rank labels"));
     if (ncat <= 2) NAPY_TRY(walk_launch<2>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
-    else if (ncat <= 4) NAPY_TRY(walk_launch<4>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
-    else NAPY_TRY(walk_launch<8>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
+    else NAPY_TRY(walk_launch<4>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, st));
     if (mwu) {
         hipLaunchKernelGGL(k_mwu_exact, dim3(RK_EX_BLOCKS), dim3(RK_EX_THREADS), 0, st, w.nexact, w.exact, w.slab,
                            w.dmax, p, ldo);
