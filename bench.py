@@ -458,9 +458,15 @@ def run_adjust(args) -> int:
         while N < npairs:
             N *= 2
         lg = int(math.log2(N // 4096))
-        # bitonic network over N elements of 12 B: lg (lg + 1) / 2 global steps
-        # and lg + 1 LDS tile passes, each reading and writing every element
-        sort_bytes = (lg * (lg + 1) // 2 + lg + 1) * 2 * 12 * N
+        # bitonic network over N elements of 12 B, as the library runs it: one
+        # LDS pass sorting the 4,096-element tiles, then per merge level k >
+        # 4,096 the strides k/2 .. 4,096 in global passes of up to three
+        # strides and one LDS pass for the smaller strides; every pass reads
+        # and writes every element
+        passes = 1
+        for lk in range(13, lg + 13):  # lg = log2(N / 4096) merge levels above the tile
+            passes += -(-(lk - 12) // 3) + 1
+        sort_bytes = passes * 2 * 12 * N
         row = {"pairs": npairs, "padded": N}
         for name, code in (("bonferroni", 0), ("bh", 1), ("by", 2)):
             def step():

@@ -20,8 +20,8 @@
 //                    which also counts the row's defined p-values.
 //   k_adj_factor     m (the sum of the row counts), and the factor m or m c(m).
 //   bitonic sort     k_bitonic_tile (LDS tiles of ADJ_TILE elements, every
-//                    step with a stride below the tile), k_bitonic_step (one
-//                    global step per larger stride).
+//                    step with a stride below the tile), k_bitonic_multi (up
+//                    to three larger strides per global pass).
 //   k_adj_scale      q_k = factor p_(k) / k and its suffix minimum within
 //                    each block of ADJ_SCAN elements, plus the block minima.
 //   k_adj_blocks     suffix minimum over the block minima (one workgroup).
@@ -197,23 +197,42 @@ __global__ __launch_bounds__(ADJ_TILE_THREADS) void k_bitonic_tile(uint64_t* __r
 }
 
 // one global step of stage k with stride j = 2^lj >= ADJ_TILE: thread per pair
-__global__ __launch_bounds__(256) void k_bitonic_step(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                      int lj, int64_t k, int64_t npairs)
+
+// R consecutive global strides j, j/2, .., j/2^(R-1) (lj = log2 j, all at
+// least ADJ_TILE) of merge level k in one pass: a thread holds the 2^R
+// elements b + m j / 2^(R-1) (b: its index with zero bits at the R stride
+// positions), which all lie in one k-block and take one direction, and does
+// the R compare-exchange rounds in registers.
+template <int R>
+__global__ __launch_bounds__(256) void k_bitonic_multi(uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                       int lj, int64_t k, int64_t ngroups)
 {
+    constexpr int E = 1 << R;
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= npairs) return;
-    const int64_t j = (int64_t)1 << lj;
-    const int64_t lo = ((q >> lj) << (lj + 1)) | (q & (j - 1));
-    const int64_t hi = lo + j;
-    uint64_t ka = keys[lo], kb = keys[hi];
-    uint32_t va = vals[lo], vb = vals[hi];
-    const uint64_t ka0 = ka;
-    cmp_swap(ka, va, kb, vb, (lo & k) == 0);
-    if (ka != ka0) {
-        keys[lo] = ka;
-        keys[hi] = kb;
-        vals[lo] = va;
-        vals[hi] = vb;
+    if (q >= ngroups) return;
+    const int lo = lj - R + 1;  // lowest stride bit
+    const int64_t low = q & (((int64_t)1 << lo) - 1);
+    const int64_t b = ((q >> lo) << (lj + 1)) | low;
+    const int64_t step = (int64_t)1 << lo;
+    const bool asc = (b & k) == 0;
+    uint64_t kk[E];
+    uint32_t vv[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        kk[m] = keys[b + m * step];
+        vv[m] = vals[b + m * step];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int h = 1 << (R - 1 - r);  // partner distance in m for stride j >> r
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if ((m & h) == 0) cmp_swap(kk[m], vv[m], kk[m + h], vv[m + h], asc);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        keys[b + m * step] = kk[m];
+        vals[b + m * step] = vv[m];
     }
 }
 
@@ -351,12 +370,20 @@ int adjust_run(const double* p, int64_t F, int64_t ldp, double* out, int64_t ldo
                                (int64_t)0);
             NAPY_TRY(check_launch("adjust sort tiles"));
             for (int64_t k = 2 * (int64_t)ADJ_TILE; k <= N; k <<= 1) {
-                for (int64_t j = k >> 1; j >= ADJ_TILE; j >>= 1) {
-                    int lj = 0;
-                    while (((int64_t)1 << lj) < j) ++lj;
-                    hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)ceil_div(N / 2, 256)), dim3(256), 0, st, w.keys,
-                                       w.vals, lj, k, N / 2);
+                // global strides k/2 .. ADJ_TILE, up to three per pass
+                int lj = 0;
+                while (((int64_t)1 << lj) < (k >> 1)) ++lj;
+                int ltile = 0;
+                while (((int64_t)1 << ltile) < ADJ_TILE) ++ltile;
+                while (lj >= ltile) {
+                    const int R = lj - ltile + 1 >= 3 ? 3 : lj - ltile + 1;
+                    const int64_t ng = N >> R;
+                    const unsigned nb = (unsigned)ceil_div(ng, 256);
+                    if (R == 3) hipLaunchKernelGGL(k_bitonic_multi<3>, dim3(nb), dim3(256), 0, st, w.keys, w.vals, lj, k, ng);
+                    else if (R == 2) hipLaunchKernelGGL(k_bitonic_multi<2>, dim3(nb), dim3(256), 0, st, w.keys, w.vals, lj, k, ng);
+                    else hipLaunchKernelGGL(k_bitonic_multi<1>, dim3(nb), dim3(256), 0, st, w.keys, w.vals, lj, k, ng);
                     NAPY_TRY(check_launch("adjust sort step"));
+                    lj -= R;
                 }
                 hipLaunchKernelGGL(k_bitonic_tile, dim3(ntiles), dim3(ADJ_TILE_THREADS), 0, st, w.keys, w.vals, k);
                 NAPY_TRY(check_launch("adjust sort merge"));
