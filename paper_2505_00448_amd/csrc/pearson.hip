@@ -587,6 +587,14 @@ constexpr int FLUSH_SLABS = 1024 / BK;
 }  // namespace bf3
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// two floats to bf16 (round to nearest even) in one conversion
+__device__ __forceinline__ bf16x2 to_bf16x2(float a, float b)
+{
+    return __builtin_convertvector((f32x2){a, b}, bf16x2);
+}
 
 __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
@@ -623,37 +631,47 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
             rawH[j] = (in && okH) ? X[i * ldx + colH] : __builtin_nanf("");
         }
     };
+    // LDS rows are 32 B (16 samples); the two 16-B halves of row c are
+    // swapped when bit 3 of c is set, so that the 16-lane phases of the
+    // row-wise 16-B reads below hit distinct banks
     auto store_lds = [&](int buf) {
         __bf16* base = lds + buf * BUF;
+        const int slot = (kq ^ (((sc >> 3) & 1) << 1)) * 4;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             bf16x4 pl[NPL];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float raw = side ? rawH[j] : rawG[j];
-                const bool miss = is_missing(raw, use_sent, sent);
-                const float x = miss ? 0.0f : raw - (side ? muH : muG);
-                // x = xh + xm + xl and q = qh + qm + ql exactly
-                const __bf16 xh = to_bf16(x);
-                const float x1 = x - from_bf16(xh);
-                const __bf16 xm = to_bf16(x1);
-                const __bf16 xl = to_bf16(x1 - from_bf16(xm));
-                const float q = x * x;
-                const __bf16 qh = to_bf16(q);
-                const float q1 = q - from_bf16(qh);
-                const __bf16 qm = to_bf16(q1);
-                const __bf16 ql = to_bf16(q1 - from_bf16(qm));
-                pl[0][j] = xh;
-                pl[1][j] = xm;
-                pl[2][j] = xl;
-                pl[3][j] = qh;
-                pl[4][j] = qm;
-                pl[5][j] = ql;
-                pl[6][j] = miss ? to_bf16(0.0f) : to_bf16(1.0f);
+            for (int jp = 0; jp < 2; ++jp) {
+                float x[2], q[2];
+                bool miss[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float raw = side ? rawH[2 * jp + u] : rawG[2 * jp + u];
+                    miss[u] = is_missing(raw, use_sent, sent);
+                    x[u] = miss[u] ? 0.0f : raw - (side ? muH : muG);
+                    q[u] = x[u] * x[u];
+                }
+                // x = xh + xm + xl and q = qh + qm + ql exactly, two samples
+                // per conversion
+                const bf16x2 xh = to_bf16x2(x[0], x[1]);
+                const float x10 = x[0] - (float)xh[0], x11 = x[1] - (float)xh[1];
+                const bf16x2 xm = to_bf16x2(x10, x11);
+                const bf16x2 xl = to_bf16x2(x10 - (float)xm[0], x11 - (float)xm[1]);
+                const bf16x2 qh = to_bf16x2(q[0], q[1]);
+                const float q10 = q[0] - (float)qh[0], q11 = q[1] - (float)qh[1];
+                const bf16x2 qm = to_bf16x2(q10, q11);
+                const bf16x2 ql = to_bf16x2(q10 - (float)qm[0], q11 - (float)qm[1]);
+                const bf16x2 mk = to_bf16x2(miss[0] ? 0.0f : 1.0f, miss[1] ? 0.0f : 1.0f);
+                const bf16x2 v[NPL] = {xh, xm, xl, qh, qm, ql, mk};
+#pragma unroll
+                for (int pp = 0; pp < NPL; ++pp) {
+                    pl[pp][2 * jp] = v[pp][0];
+                    pl[pp][2 * jp + 1] = v[pp][1];
+                }
             }
 #pragma unroll
             for (int pp = 0; pp < NPL; ++pp)
-                *(bf16x4*)(base + ((side * NPL + pp) * TILE + sc) * BK + kq * 4) = pl[pp];
+                *(bf16x4*)(base + ((side * NPL + pp) * TILE + sc) * BK + slot) = pl[pp];
         }
     };
 
@@ -665,7 +683,7 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     }
     auto compute = [&](int buf) {
         const __bf16* base = lds + buf * BUF;
-        const int rr = lane & 31, kk = (lane >> 5) * 8;
+        const int rr = lane & 31, kk = ((lane >> 5) ^ ((rr >> 3) & 1)) * 8;  // swizzled half
         // all seven planes of the G side; the H side's planes one at a time
         bf16x8 a[NPL];
 #pragma unroll
