@@ -620,21 +620,31 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     const float muG = okG ? mu32[colG] : 0.0f, muH = okH ? mu32[colH] : 0.0f;
 
     __shared__ __attribute__((aligned(16))) __bf16 lds[2 * BUF];
-    float rawG[4], rawH[4];
-    auto load_raw = [&](int slab) {
+    // raw values of two slabs in flight (sets A and B, alternating); loads
+    // are unconditional from a clamped address, out-of-range values become
+    // NaN (missing) afterwards, so the loop body has no branches
+    float rawG[4], rawH[4], nxtG[4], nxtH[4];
+    const int64_t cG = okG ? colG : 0, cH = okH ? colH : 0;
+    auto load_raw = [&](int slab, float (&rg)[4], float (&rh)[4]) {
         const int64_t i0 = kbeg + (int64_t)slab * BK + kq * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t i = i0 + j;
-            const bool in = i < kend;
-            rawG[j] = (in && okG) ? X[i * ldx + colG] : __builtin_nanf("");
-            rawH[j] = (in && okH) ? X[i * ldx + colH] : __builtin_nanf("");
+            const int64_t ic = i < kend ? i : kend - 1;
+            rg[j] = X[ic * ldx + cG];
+            rh[j] = X[ic * ldx + cH];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in = i0 + j < kend;
+            rg[j] = (in && okG) ? rg[j] : __builtin_nanf("");
+            rh[j] = (in && okH) ? rh[j] : __builtin_nanf("");
         }
     };
     // LDS rows are 32 B (16 samples); the two 16-B halves of row c are
     // swapped when bit 3 of c is set, so that the 16-lane phases of the
     // row-wise 16-B reads below hit distinct banks
-    auto store_lds = [&](int buf) {
+    auto store_lds = [&](int buf, const float (&rG)[4], const float (&rH)[4]) {
         __bf16* base = lds + buf * BUF;
         const int slot = (kq ^ (((sc >> 3) & 1) << 1)) * 4;
 #pragma unroll
@@ -646,7 +656,7 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
                 bool miss[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const float raw = side ? rawH[2 * jp + u] : rawG[2 * jp + u];
+                    const float raw = side ? rH[2 * jp + u] : rG[2 * jp + u];
                     miss[u] = is_missing(raw, use_sent, sent);
                     x[u] = miss[u] ? 0.0f : raw - (side ? muH : muG);
                     q[u] = x[u] * x[u];
@@ -757,20 +767,33 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
         flushed = true;
     };
 
-    // main loop: one barrier per slab; staging of slab s+1 overlaps the
-    // contractions of slab s
-    if (nslab > 0) {
-        load_raw(0);
-        store_lds(0);
-        __syncthreads();
-        for (int sl = 0; sl < nslab; ++sl) {
-            const bool more = sl + 1 < nslab;
-            if (more) load_raw(sl + 1);
-            compute(sl & 1);
-            if (more) store_lds((sl + 1) & 1);
-            if ((sl + 1) % FLUSH_SLABS == 0 && more) flush();
-            __syncthreads();
+    // main loop, one barrier per slab: the contractions of slab s overlap the
+    // staging of slab s+1, whose raw values were loaded one slab earlier
+    // (global latency is longer than one slab's contractions); the
+    // scheduling hints interleave the staging's VALU work with the MFMAs
+    auto step = [&](int sl, const float (&cG)[4], const float (&cH)[4], float (&lG)[4], float (&lH)[4]) {
+        load_raw(sl + 2, lG, lH);
+        compute(sl & 1);
+        store_lds((sl + 1) & 1, cG, cH);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // six VALU
         }
+        if ((sl + 1) % FLUSH_SLABS == 0 && sl + 1 < nslab) flush();
+        __syncthreads();
+    };
+    if (nslab > 0) {
+        load_raw(0, rawG, rawH);
+        store_lds(0, rawG, rawH);
+        load_raw(1, rawG, rawH);
+        __syncthreads();
+        int sl = 0;
+        for (; sl + 1 < nslab; sl += 2) {
+            step(sl, rawG, rawH, nxtG, nxtH);
+            step(sl + 1, nxtG, nxtH, rawG, rawH);
+        }
+        if (sl < nslab) step(sl, rawG, rawH, nxtG, nxtH);
     }
     flush();
     double* d0 = slice(0);
