@@ -383,6 +383,26 @@ def test_grouped_columns(gpu_device):
     _check_full("spearman", X, gpu_device, where="grouped-columns")
 
 
+def test_spearman_max_samples(gpu_device):
+    """S = 24,576, the largest sample count the 16-bit sorted orders hold:
+    untied, sparsely tied, grouped (few values) and densely tied columns,
+    one of them complete (positions and run ends up to 24,576)."""
+    rng = np.random.default_rng(77)
+    S = 24576
+    cols = [rng.standard_normal(S), rng.poisson(4, S).astype(np.float64), np.round(rng.standard_normal(S), 2),
+            rng.integers(0, 3, S).astype(np.float64), rng.standard_normal(S)]
+    d = rng.standard_normal(S)
+    for _ in range(40):
+        a, b = rng.choice(S, 2, replace=False)
+        d[b] = d[a]
+    cols.append(d)
+    X = np.column_stack(cols + [rng.standard_normal(S) for _ in range(4)])
+    X[rng.random(X.shape) < 0.3] = np.nan
+    X[:, 4] = rng.permutation(S)  # complete and untied
+    X[:, 3] = rng.integers(0, 3, S)  # complete, three runs, the last ending at S
+    _check_full("spearman", X.astype(np.float32), gpu_device, where="spearman-max-samples")
+
+
 def test_tie_runs_ranks_bit_exact(gpu_device):
     napy = _napy()
     X = _tie_stress_matrix(S=1500, seed=5)

@@ -199,6 +199,25 @@ def test_sentinel_and_default_ncat(gpu_device):
     _check("kw", _run("kw", Ls, Xs, gpu_device, missing=-7.0), orank.kruskal(L, X), "sentinel")
 
 
+def test_max_samples(gpu_device):
+    """S = 24,576 (the sorted orders' limit): untied, grouped and densely
+    tied continuous columns, one complete; labels with and without missing."""
+    print("rank tests max samples", flush=True)
+    rng = np.random.default_rng(88)
+    S = 24576
+    X = np.column_stack([rng.standard_normal(S), rng.poisson(4, S), np.round(rng.standard_normal(S), 1),
+                         rng.permutation(S)]).astype(np.float64)
+    X[rng.random(X.shape) < 0.3] = np.nan
+    X[:, 3] = rng.permutation(S)
+    L = rng.integers(0, 3, (S, 3)).astype(np.float64)
+    L[rng.random(L.shape) < 0.2] = np.nan
+    L[:, 2] = rng.integers(0, 3, S)
+    X, L = X.astype(np.float32), L.astype(np.float32)
+    D = np.where(np.isnan(L), np.nan, L >= 1).astype(np.float32)
+    _check("mwu", _run("mwu", D, X, gpu_device), orank.mannwhitney(D, X), "mwu max samples")
+    _check("kw", _run("kw", L, X, gpu_device, ncat=3), orank.kruskal(L, X, ncat=3), "kruskal max samples")
+
+
 @pytest.mark.parametrize("kind", ["mwu", "kw"])
 def test_full_size_sampled_pairs(gpu_device, kind):
     """10,000 samples, 30% missing on both sides; the oracle checks 300
