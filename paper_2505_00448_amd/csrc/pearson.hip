@@ -83,22 +83,32 @@ __global__ __launch_bounds__(256) void k_colstats_partial(
     }
 }
 
+// one wave per column: each lane sums the partials r = lane, lane + 64, ...
+// and a fixed butterfly adds the lanes (the same order on every call)
 __global__ __launch_bounds__(256) void k_colstats_final(
     int R, int64_t F, const int32_t* __restrict__ pcnt, const double* __restrict__ psum,
     int32_t* __restrict__ ncol, float* __restrict__ mu32, double* __restrict__ mu64)
 {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (c >= F) return;
     int32_t n = 0;
     double s = 0.0;
-    for (int r = 0; r < R; ++r) {
+    for (int r = lane; r < R; r += 64) {
         n += pcnt[(int64_t)r * F + c];
         s += psum[(int64_t)r * F + c];
     }
-    const double m = n > 0 ? s / (double)n : 0.0;
-    ncol[c] = n;
-    mu64[c] = m;
-    mu32[c] = (float)m;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        n += __shfl_xor(n, d, 64);
+        s += __shfl_xor(s, d, 64);
+    }
+    if (lane == 0) {
+        const double m = n > 0 ? s / (double)n : 0.0;
+        ncol[c] = n;
+        mu64[c] = m;
+        mu32[c] = (float)m;
+    }
 }
 
 int colstats_plan_chunks(int64_t S, int64_t F)
@@ -130,7 +140,7 @@ int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_s
     hipLaunchKernelGGL(k_colstats_partial, g1, dim3(256), 0, st, X, S, F, ldx, use_sent, sent,
                        rows_per, cs.pcnt, cs.psum);
     NAPY_TRY(check_launch("colstats_partial"));
-    hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, R, F,
+    hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, R, F,
                        cs.pcnt, cs.psum, cs.n, cs.mu32, cs.mu64);
     return check_launch("colstats_final");
 }
