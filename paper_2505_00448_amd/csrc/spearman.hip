@@ -638,28 +638,36 @@ __device__ __forceinline__ uint32_t ra_of_tied(const uint2* tab, const uint32_t*
     return ra_run(tab, rlA[pv & POS_MASK]);
 }
 
+// a's samples in LDS, and the code `miss` of a missing one: a grouped a
+// stores for every sample its index in the run-rank table (no flag bit),
+// miss = RUN_TABLE_MAX (the table's zero entry); an untied a stores
+// positions, miss = XS = 32 NW (the partner table's zero entry); a tied a
+// stores positions, a tied one with the flag bit, miss = 0xFFFF (clamped to
+// XS for a table lookup).
+constexpr uint32_t MISS_GROUPED = (uint32_t)RUN_TABLE_MAX;
+
 // One chunk of 64 positions of b's sorted order without tied b-positions.
-// b's C1 = carry1 + (complete samples at lower lanes) by mbcnt.  TA = 0 (a
-// untied) or 1 (a with ties): a's C1 from the partner table, 0 for missing
-// or tied a-positions (both map to the table's zero entry), whose products
-// are added separately.  TA = 2 (a grouped): every complete sample's R_a
-// from the run-rank table, no partner-table lookup and no branch.
+// b's C1 = carry1 + (complete samples at lower lanes) by mbcnt; a sample is
+// complete when its a-position is not `miss`.  TA = 0 (a untied) or 1 (a
+// with ties): a's C1 from the partner table, 0 for missing or tied
+// a-positions (TA = 1 clamps both to XS), whose products are added
+// separately; C1_a C1_b goes to t32.  TA = 2 (a grouped): every sample's R_a
+// from the run-rank table, no partner-table lookup and no branch; R_a C1_b
+// (below 2^31) goes to t32, which the caller empties every two chunks.
 template <int TA, bool DBG>
 __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, const uint2* tab, uint32_t XS,
-                                                  const uint32_t* __restrict__ rlA, const uint32_t* rrun,
-                                                  uint32_t& carry1, uint32_t& t32, uint64_t& sAt,
-                                                  int32_t* dbg_ra, int32_t* dbg_rb)
+                                                  uint32_t miss, const uint32_t* __restrict__ rlA,
+                                                  const uint32_t* rrun, uint32_t& carry1, uint32_t& t32,
+                                                  uint64_t& sAt, int32_t* dbg_ra, int32_t* dbg_rb)
 {
-    const bool kept = pv != 0xFFFFu;
+    const bool kept = pv != miss;
     const uint64_t mask = __ballot(kept);
     const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, carry1));
     if constexpr (TA == 2) {
-        // missing: 0x7FFF -> the zero entry
-        const uint32_t Ra = rrun[min(pv & POS_MASK, (uint32_t)RUN_TABLE_MAX)];
-        sAt += __umul24(Ra, cb1);
+        t32 += __umul24(rrun[pv], cb1);
     } else {
-        const uint32_t ca1 = cnt1(tab, min(pv, XS));
+        const uint32_t ca1 = cnt1(tab, TA == 0 ? pv : min(pv, XS));
         t32 += __umul24(ca1, cb1);
         bool tied = false;
         if constexpr (TA == 1) {
@@ -692,7 +700,8 @@ template <int TA, bool TB, bool DBG>
 __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ runsB,
                                           const uint64_t* __restrict__ tbB, const uint32_t* __restrict__ rlA,
                                           int nbv, const uint16_t* posA, const uint2* tab, const uint32_t* rrun,
-                                          uint32_t XS, int lane, int32_t* dbg_ra, int32_t* dbg_rb, WalkSums& ws)
+                                          uint32_t XS, uint32_t miss, int lane, int32_t* dbg_ra, int32_t* dbg_rb,
+                                          WalkSums& ws)
 {
     constexpr int U = WALK_U;
     const int ncb = (nbv + 63) >> 6;
@@ -725,10 +734,12 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
             for (int u = 0; u < U; ++u) iv[u] = ivn[u];
         }
         // prefetch the next group's sample indices into the same registers
-        // (rows are padded, so a whole group is always inside the row)
-        if (g + 1 < ngrp) {
+        // (rows are padded, so a whole group is always inside the row); the
+        // last group reloads its own, which keeps the loop body one block
+        {
+            const uint16_t* nx = ordB + (size_t)((g + 1 < ngrp) ? c0 + U : c0) * 64;  // wave-uniform
 #pragma unroll
-            for (int u = 0; u < U; ++u) ivn[u] = ordB[(c0 + U + u) * 64 + lane];
+            for (int u = 0; u < U; ++u) ivn[u] = nx[u * 64 + lane];
         }
         uint32_t dbits = 0;  // bit u: chunk c0 + u holds tied b-positions
         if constexpr (TB) {
@@ -743,8 +754,15 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
         uint32_t t32 = 0;
         if (!dirty) {
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
+            for (int u = 0; u < U; ++u) {
+                walk_chunk_untied<TA, DBG>(iv[u], pv[u], tab, XS, miss, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
+                if constexpr (TA == 2) {
+                    if (u & 1) {
+                        sAt += t32;
+                        t32 = 0;
+                    }
+                }
+            }
             sA4 += t32;
             continue;
         }
@@ -759,16 +777,25 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                 const uint32_t pvu = posA[ivu];
                 if (((dbits >> u) & 1u) == 0u) {
                     // no tied b-position here, and no run crosses into this chunk
-                    walk_chunk_untied<TA, DBG>(ivu, pvu, tab, XS, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
+                    walk_chunk_untied<TA, DBG>(ivu, pvu, tab, XS, miss, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
+                    if constexpr (TA == 2) {
+                        sAt += t32;
+                        t32 = 0;
+                    }
                     continue;
                 }
                 const uint32_t rb = ((int)k < nbv) ? runsB[k] : (k | ((k + 1u) << 16));
-                const bool kept = pvu != 0xFFFFu;
+                const bool kept = pvu != miss;
                 const uint64_t mask = __ballot(kept);
                 const uint32_t carry = carry1 - 1u;
-                uint32_t Ra = 2u * cnt1(tab, min(pvu, XS));
-                if constexpr (TA) {
-                    if (kept && (pvu & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pvu);
+                uint32_t Ra;
+                if constexpr (TA == 2) {
+                    Ra = rrun[pvu];
+                } else {
+                    Ra = 2u * cnt1(tab, min(pvu, XS));
+                    if constexpr (TA == 1) {
+                        if (kept && (pvu & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pvu);
+                    }
                 }
                 const uint32_t lo = (uint32_t)c * 64u;
                 const uint32_t rs = rb & 0xFFFFu, re = rb >> 16;
@@ -789,7 +816,7 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                             const uint32_t s0 = __builtin_amdgcn_readlane(rs, 0);
                             for (uint32_t kk = s0 + (uint32_t)lane; kk < e0; kk += 64u) {
                                 const uint32_t ii = ordB[kk];
-                                if (posA[ii] != 0xFFFFu) dbg_rb[ii] = (int32_t)r_open;
+                                if (posA[ii] != miss) dbg_rb[ii] = (int32_t)r_open;
                             }
                         }
                         pend_lane = 0;
@@ -840,8 +867,8 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
 template <int TA>
 __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__ ordB, const uint32_t* __restrict__ rlB,
                                                     int nrb, const uint16_t* posA, const uint2* tab,
-                                                    const uint32_t* __restrict__ rlA, const uint32_t* rrun, int lane,
-                                                    int64_t& corr, uint64_t& d3B)
+                                                    const uint32_t* __restrict__ rlA, const uint32_t* rrun,
+                                                    uint32_t miss, int lane, int64_t& corr, uint64_t& d3B)
 {
     for (int r = lane; r < nrb; r += 64) {
         const uint32_t rr = rlB[r];
@@ -850,10 +877,11 @@ __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__
         uint64_t sra = 0, sraj = 0;
         for (uint32_t k = s; k < e; ++k) {
             const uint32_t pv = posA[ordB[k]];
-            if (pv == 0xFFFFu) continue;
+            if (pv == miss) continue;
             ++t;
             uint32_t Ra;
-            if (TA != 0 && (pv & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pv);
+            if (TA == 2) Ra = rrun[pv];
+            else if (TA != 0 && (pv & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pv);
             else Ra = 2u * cnt1(tab, pv);
             sra += Ra;
             sraj += (uint64_t)Ra * t;
@@ -876,7 +904,8 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
                                                const uint32_t* __restrict__ rlB, int nrb,
                                                const uint16_t* __restrict__ sgB, int nsgB, const uint16_t* posA,
                                                const uint2* tab, const uint32_t* __restrict__ rlA,
-                                               const uint32_t* rrun, uint32_t XS, int lane, uint64_t& sum,
+                                               const uint32_t* rrun, uint32_t XS, uint32_t miss, int lane,
+                                               uint64_t& sum,
                                                uint32_t& n, uint64_t& d3B)
 {
     constexpr int U = WALK_U;
@@ -918,10 +947,10 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
             const uint32_t c0 = (uint32_t)((gi * U + u) * 64);
             const uint32_t k = c0 + (uint32_t)lane;
             const uint32_t p = pv[u];
-            const bool kept = p != 0xFFFFu;  // positions from nbv on hold the dummy sample
+            const bool kept = p != miss;  // positions from nbv on hold the dummy sample
             uint32_t Ra;
             if constexpr (TA == 2) {
-                Ra = rrun[min(p & POS_MASK, (uint32_t)RUN_TABLE_MAX)];
+                Ra = rrun[p];  // 0 for a missing sample
             } else {
                 Ra = 2u * cnt1(tab, min(p, XS));
                 if constexpr (TA == 1)
@@ -1006,6 +1035,34 @@ __device__ __forceinline__ void copy16_to_lds(uint4* dst, const uint4* __restric
         for (int u = 0; u < CU; ++u) {
             const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
             if (w < n16) dst[w] = v[u];
+        }
+    }
+}
+
+// copy16_to_lds for a column's sorted positions (u16, 0xFFFF for a missing
+// sample), each u16 v written as min(v & keep, clamp) (two u16 per packed
+// 16-bit min)
+__device__ __forceinline__ void copy_pos_to_lds(uint4* dst, const uint4* __restrict__ src, int n16, uint32_t keep,
+                                                uint32_t clamp)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    constexpr int CU = 4;
+    const u16x2 c2 = __builtin_bit_cast(u16x2, clamp | (clamp << 16));
+    const uint32_t k2 = keep | (keep << 16);
+    const auto fix = [c2, k2](uint32_t w) {
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, w & k2), c2));
+    };
+    for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
+        uint4 v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
+            v[u] = src[w < n16 ? w : n16 - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int w = w0 + u * PAIR_THREADS + (int)threadIdx.x;
+            if (w < n16) dst[w] = make_uint4(fix(v[u].x), fix(v[u].y), fix(v[u].z), fix(v[u].w));
         }
     }
 }
@@ -1133,8 +1190,15 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         }
     }
     __syncthreads();
-    // a's positions 0..S (S is the dummy) over the presence bytes
-    copy16_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8));
+    // a's positions 0..S (S is the dummy) over the presence bytes, with the
+    // missing code of a's class: untied, min(v, XS) turns 0xFFFF into XS;
+    // grouped, min(v & POS_MASK, RUN_TABLE_MAX) turns a tied sample's flagged
+    // run number into the run number and 0xFFFF into RUN_TABLE_MAX (untied
+    // samples get theirs below); tied, unchanged
+    const uint32_t XS = 32u * (uint32_t)NW;
+    const uint32_t miss = grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS;
+    copy_pos_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8),
+                    grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS);
     for (int j = wave; j < PB; j += PAIR_WAVES) {
         uint2* tj = tab + (size_t)j * L.nwp;
         uint32_t run = 1;
@@ -1153,7 +1217,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
         // (tie defect) with doubled average rank C(s) + C(e) + 1 (run-rank
         // table); a grouped a adds its untied positions as runs [s, s + 1)
         // after the runs, and its untied samples' positions become those
-        // runs' numbers
+        // runs' numbers (its tied samples' became their runs' numbers in
+        // the copy)
         const int nj = DBG ? 1 : PB;
         const int ngr = grouped ? nra + nsg : nra;
         for (int r = threadIdx.x; r < ngr; r += PAIR_THREADS) {
@@ -1165,7 +1230,7 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             } else {
                 s = sgA[r - nra];
                 e = s + 1u;
-                posA[ordA[s]] = (uint16_t)(POS_TIED | (uint32_t)r);
+                posA[ordA[s]] = (uint16_t)r;
             }
             for (int j = 0; j < nj; ++j) {
                 const uint2* tj = tab + (size_t)j * L.nwp;
@@ -1180,7 +1245,6 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     }
 
     // ---- step 2: one walk of each partner's sorted order ---------------------
-    const uint32_t XS = 32u * (uint32_t)NW;
     for (int j = wave; j < (DBG ? 1 : PB); j += PAIR_WAVES) {
         const int64_t lb = b0 + j;
         if (!DBG && (lb >= F || lb < la)) continue;
@@ -1205,12 +1269,12 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             const int nrb = bs.nruns[b];
             const uint16_t* sgB = bs.sing + b * RUN_GROUPS_MAX;
             uint32_t ng;
-            if (grouped) grouped_b_walk<2>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, lane, sA, ng, d3B);
-            else if (tA) grouped_b_walk<1>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, lane, sA, ng, d3B);
-            else grouped_b_walk<0>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, lane, sA, ng, d3B);
+            if (grouped) grouped_b_walk<2>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
+            else if (tA) grouped_b_walk<1>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
+            else grouped_b_walk<0>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
             w.n = ng;
         } else {
-#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, lane, po.dbg_ra, po.dbg_rb, w)
+#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, miss, lane, po.dbg_ra, po.dbg_rb, w)
             if (grouped) {
                 if (cB == 2) NAPY_WALK(2, true);
                 else NAPY_WALK(2, false);
@@ -1227,8 +1291,9 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             if (!DBG && cB == 1) {
                 const uint32_t* rlB = bs.rlist + b * (ld / 2);
                 const int nrb = bs.nruns[b];
-                if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
-                else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, lane, corr, d3s);
+                if (grouped) settle_short_runs_b<2>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
+                else if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
+                else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
             }
             sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au +
                  wave_sum_u64((uint64_t)corr);
