@@ -113,13 +113,15 @@ NAPY_HD inline double corr_pvalue(double r, int64_t n)
     const double lny = 2.0 * log(ar);
     // ln B(a, 1/2) = 0.5 ln(pi) - [ln G(a+1/2) - ln G(a)]
     const double lnB = 0.57236494292470008707 - lgamma_half_ratio(a);
-    if (x < (a + 1.0) / (a + 2.5)) {
-        const double lf = a * lnx + 0.5 * lny - log(a) - lnB;
-        return exp(lf) * betacf_lentz(a, 0.5, x);
-    }
-    // 1 - I_{r^2}(1/2, a)
-    const double lf = 0.5 * lny + a * lnx + 0.69314718055994530942 - lnB;
-    double p = 1.0 - exp(lf) * betacf_lentz(0.5, a, y);
+    // the direct tail I_x(a, 1/2), or 1 - I_{r^2}(1/2, a); the parameters are
+    // chosen first so that one continued-fraction loop serves both (lanes of
+    // a wave taking different tails do not run two loops)
+    const bool direct = x < (a + 1.0) / (a + 2.5);
+    const double lf = direct ? a * lnx + 0.5 * lny - log(a) - lnB
+                             : 0.5 * lny + a * lnx + 0.69314718055994530942 - lnB;
+    const double t = exp(lf) * betacf_lentz(direct ? a : 0.5, direct ? 0.5 : a, direct ? x : y);
+    if (direct) return t;
+    const double p = 1.0 - t;
     return p < 0.0 ? 0.0 : p;
 }
 
@@ -162,12 +164,12 @@ NAPY_HD inline double fdist_sf(double f, double d1, double d2)
     // with a large a would otherwise lose digits)
     const double lnx = y < 0.5 ? log1p(-y) : log(x);
     const double lny = x < 0.5 ? log1p(-x) : log(y);
-    if (x < (a + 1.0) / (a + b + 2.0)) {
-        const double lf = a * lnx + b * lny - log(a) - lnB;
-        return exp(lf) * betacf_lentz(a, b, x);
-    }
-    const double lf = b * lny + a * lnx - log(b) - lnB;
-    const double p = 1.0 - exp(lf) * betacf_lentz(b, a, y);
+    // one continued-fraction loop for either tail, as in corr_pvalue
+    const bool direct = x < (a + 1.0) / (a + b + 2.0);
+    const double lf = direct ? a * lnx + b * lny - log(a) - lnB : b * lny + a * lnx - log(b) - lnB;
+    const double t = exp(lf) * betacf_lentz(direct ? a : b, direct ? b : a, direct ? x : y);
+    if (direct) return t;
+    const double p = 1.0 - t;
     return p < 0.0 ? 0.0 : p;
 }
 
