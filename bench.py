@@ -5,8 +5,11 @@ Workload: 10,000 samples x 1,000 variables (rank-20 Gaussian factor model,
 10% Poisson(4) integer columns, 30% MCAR missingness plus 100 variables
 missing on one shared random half of the samples), float32 on the device
 before the timed region starts.  A step is one full r/p/n call of each
-method: napy_pearson (split-BF16 contractions by default) followed by
-napy_spearman.  value = F(F-1)/2 var-pairs / step time.
+method: napy_pearson (split-BF16 contractions by default) and napy_spearman,
+each on its own HIP stream (default priority) with its own workspace, so the
+MFMA-bound Pearson kernels run beside the VALU/LDS-bound Spearman scan
+(--one-stream issues both on one stream, one after the other).  value =
+F(F-1)/2 var-pairs / step time.
 
 The JSON line also carries the FP32-contraction Pearson time (the precision
 comparison), the stage times measured with HIP events on the call's stream,
@@ -146,6 +149,8 @@ def main() -> int:
                     help="pairs in the oracle's timed sample (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="headline: Pearson and Spearman on one stream, one after the other")
     ap.add_argument("--form", default="headline",
                     choices=["headline", "precision", "serving", "differentiation", "copy", "adjust", "groups"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
@@ -191,6 +196,12 @@ def main() -> int:
     assert not bool(torch.isinf(Xd).any())
     stream = torch.cuda.current_stream(dev)
     sh = ctypes.c_void_p(stream.cuda_stream)
+    # Pearson and Spearman streams (default priority) and workspaces
+    if args.one_stream:
+        sh_p = sh_s = sh
+    else:
+        st_p, st_s = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+        sh_p, sh_s = ctypes.c_void_p(st_p.cuda_stream), ctypes.c_void_p(st_s.cuda_stream)
 
     def P(t):
         return ctypes.c_void_p(t.data_ptr())
@@ -199,9 +210,10 @@ def main() -> int:
     opt_fp32 = _lib.make_opts("fp32")
     opt_sp = _lib.make_opts("fp32")
     ws_bytes = max(lib.napy_pearson_workspace(S, F, ctypes.byref(opt_main)),
-                   lib.napy_pearson_workspace(S, F, ctypes.byref(opt_fp32)),
-                   lib.napy_spearman_workspace(S, F, ctypes.byref(opt_sp)))
+                   lib.napy_pearson_workspace(S, F, ctypes.byref(opt_fp32)))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ws_s_bytes = lib.napy_spearman_workspace(S, F, ctypes.byref(opt_sp))
+    ws_s = torch.empty(ws_s_bytes, dtype=torch.uint8, device=dev)
     out = {k: (torch.empty((F, F), dtype=torch.float64, device=dev),
                torch.empty((F, F), dtype=torch.float64, device=dev),
                torch.empty((F, F), dtype=torch.int32, device=dev)) for k in ("pearson", "spearman", "fp32")}
@@ -220,22 +232,23 @@ def main() -> int:
     evs_a = [arr(e) for e in evs]
     evf_a = [arr(e) for e in evf]
 
-    def pearson_call(opts, o, ev):
+    def pearson_call(opts, o, ev, sh_call):
         r, p, n = o
         st = lib.napy_pearson_profiled(P(Xd), S, F, F, P(r), P(p), P(n), F, P(ws), ws_bytes,
-                                       ctypes.byref(opts), sh, ev)
+                                       ctypes.byref(opts), sh_call, ev)
         _lib.check(st, "napy_pearson")
 
     def spearman_call(o, ev):
         r, p, n = o
-        st = lib.napy_spearman_profiled(P(Xd), S, F, F, P(r), P(p), P(n), F, P(ws), ws_bytes,
-                                        ctypes.byref(opt_sp), sh, ev)
+        st = lib.napy_spearman_profiled(P(Xd), S, F, F, P(r), P(p), P(n), F, P(ws_s), ws_s_bytes,
+                                        ctypes.byref(opt_sp), sh_s, ev)
         _lib.check(st, "napy_spearman")
 
     def step(i, ev=True):
-        pearson_call(opt_main, out["pearson"], evp_a[i] if ev else None)
+        pearson_call(opt_main, out["pearson"], evp_a[i] if ev else None, sh_p)
         spearman_call(out["spearman"], evs_a[i] if ev else None)
 
+    torch.cuda.synchronize()  # the input is on the device before either stream reads it
     for _ in range(W):
         step(0, ev=False)
     torch.cuda.synchronize()
@@ -248,10 +261,10 @@ def main() -> int:
 
     # FP32-contraction Pearson, timed separately for the precision comparison
     for _ in range(W):
-        pearson_call(opt_fp32, out["fp32"], None)
+        pearson_call(opt_fp32, out["fp32"], None, sh)
     torch.cuda.synchronize()
     for i in range(K):
-        pearson_call(opt_fp32, out["fp32"], evf_a[i])
+        pearson_call(opt_fp32, out["fp32"], evf_a[i], sh)
     torch.cuda.synchronize()
 
     def stage_means(evl):
@@ -296,7 +309,9 @@ def main() -> int:
         "dtype": f"{args.precision} (Pearson contractions, fp32 accumulate, fp64 combine) + int (Spearman sums)",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "samples": S, "variables": F, "pearson_precision": args.precision,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "streams": "one (Pearson then Spearman)" if args.one_stream
+                   else "two (Pearson beside Spearman)"},
         "pearson_ms": pt,
         "spearman_ms": stt,
         "pearson_fp32_ms": ft,
