@@ -65,9 +65,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "9273be464fe8b51219ef25220a8887da339902dec55a5c73984b05320c1c342c",
-    "fetch_kib": 139982.2,
-    "write_kib": 25771.4,
+    "source_sha256": "708c0c227bde87883aaa4f9a25eaadab961e35be9974dae28f949edbe77e6491",
+    "fetch_kib": 139910.9,
+    "write_kib": 25676.3,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
