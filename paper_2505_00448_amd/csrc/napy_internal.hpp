@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <atomic>
+
 #include "../../include/napy.h"
 
 namespace napy {
@@ -20,6 +22,24 @@ int check_launch(const char* what);
         int _st = (expr);              \
         if (_st != NAPY_OK) return _st; \
     } while (0)
+
+// ---- kernel attributes ---------------------------------------------------------
+// Raises a kernel's dynamic LDS limit to `bytes` on the current device, once
+// per device: bit d of `done` (one flag word per kernel) records device d.
+// Threads that race here both set the attribute, which is idempotent; a
+// device index of 64 or more sets it on every call.
+inline int ensure_dyn_lds(std::atomic<uint64_t>& done, const void* fn, int bytes, const char* what)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    const uint64_t bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0ull;
+    if (bit != 0ull && (done.load(std::memory_order_acquire) & bit) != 0ull) return NAPY_OK;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return hip_status(e, what);
+    done.fetch_or(bit, std::memory_order_acq_rel);
+    return NAPY_OK;
+}
 
 // ---- workspace carving -------------------------------------------------------
 // Regions are carved in order from one caller buffer, each 256-byte aligned.

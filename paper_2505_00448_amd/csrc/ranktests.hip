@@ -482,13 +482,9 @@ static int walk_launch(const RankWs& w, int64_t S, int64_t FC, int64_t FQ, int t
 {
     const size_t smem = (size_t)round_up(w.base.ld, 16) + (size_t)RK_WAVES * ((S + 1 + 31) / 32 + 1) * 8 +
                         (NW > 2 ? (size_t)RK_WAVES * NW * 64 * 8 : 0);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_rank_walk<NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(160 * 1024 - sizeof(double) * RK_WAVES * 64));
-        if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_rank_walk)");
-        attr = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_rank_walk<NW>, (int)(160 * 1024 - sizeof(double) * RK_WAVES * 64),
+                            "hipFuncSetAttribute(k_rank_walk)"));
     hipLaunchKernelGGL(k_rank_walk<NW>, dim3((unsigned)FC, (unsigned)ceil_div(FQ, RK_WAVES)), dim3(RK_THREADS), smem,
                        st, w.base, w.lab, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo, w.nexact,
                        w.exact);

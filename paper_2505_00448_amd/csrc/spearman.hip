@@ -1531,13 +1531,9 @@ static int pairs_launch_t(const SpearBase& bs, const uint8_t* presb, int64_t S, 
                           hipStream_t st)
 {
     const size_t smem = pair_smem(bs.ld, S, PAIR_PB).bytes;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_spearman_pairs<PAIR_PB, DBG>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_spearman_pairs)");
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_spearman_pairs<PAIR_PB, DBG>, 160 * 1024,
+                            "hipFuncSetAttribute(k_spearman_pairs)"));
     if (smem > 160 * 1024) return NAPY_E_UNSUPPORTED;
     const int64_t nbp = round_up(ceil_div(F, PAIR_PB), 8);
     const int64_t nblk = DBG ? 1 : pair_grid_size(F, nbp, PAIR_PB);
@@ -1581,13 +1577,9 @@ static void spear_carve(Carver& c, int64_t S, int64_t F, SpearWs& w)
 template <int EPT>
 static int colsort_launch(const uint32_t* keys, int64_t S, int64_t F, const SpearBase& base, hipStream_t st)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_colsort<EPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)sort_smem_bytes(EPT));
-        if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_colsort)");
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_colsort<EPT>, (int)sort_smem_bytes(EPT),
+                            "hipFuncSetAttribute(k_colsort)"));
     hipLaunchKernelGGL(k_colsort<EPT>, dim3((unsigned)F), dim3(CS_THREADS), sort_smem_bytes(EPT), st, keys, S,
                        base.ld, base);
     return check_launch("colsort");
@@ -1725,13 +1717,9 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
     }
     {
         const size_t smem = compact_smem_bytes(b.ld);
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_compact, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)compact_smem_bytes(spear_ld(SPEARMAN_MAX_S)));
-            if (e != hipSuccess) return hip_status(e, "hipFuncSetAttribute(k_compact)");
-            attr = true;
-        }
+        static std::atomic<uint64_t> attr_done{0};
+        NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_compact, (int)compact_smem_bytes(spear_ld(SPEARMAN_MAX_S)),
+                                "hipFuncSetAttribute(k_compact)"));
         hipLaunchKernelGGL(k_compact, dim3((unsigned)Fq), dim3(CP_THREADS), smem, st, b, cols, rowmap, Sq, w.base);
         NAPY_TRY(check_launch("compact"));
     }
