@@ -65,9 +65,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "708c0c227bde87883aaa4f9a25eaadab961e35be9974dae28f949edbe77e6491",
-    "fetch_kib": 139910.9,
-    "write_kib": 25676.3,
+    "source_sha256": "b8e5742af64e0497d1bab6da015c82baa38e674693b42bf4c862e50b929b316d",
+    "fetch_kib": 139924.1,
+    "write_kib": 25740.2,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
