@@ -30,7 +30,10 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls are asynchronous: they enqueue kernels and return; no device to
  *     host traffic and no synchronisation happen inside a call.  Calls on
- *     different streams with distinct buffers may run concurrently.
+ *     different streams with distinct buffers may run concurrently, also
+ *     from different host threads (the only process-wide setting, a
+ *     kernel's dynamic-LDS limit, is made once per device under an atomic
+ *     flag).
  *   - `ws` is a caller-owned device workspace of at least the size returned
  *     by the matching *_workspace() query (pure host function), aligned to
  *     256 bytes.  Its contents on entry do not matter.
