@@ -383,6 +383,49 @@ def test_grouped_columns(gpu_device):
     _check_full("spearman", X, gpu_device, where="grouped-columns")
 
 
+def _value_groups(col):
+    """(tie runs, untied values) among a column's observed values."""
+    v = col[~np.isnan(col)]
+    _, counts = np.unique(v, return_counts=True)
+    return int((counts > 1).sum()), int((counts == 1).sum())
+
+
+def test_grouped_limit_23_groups(gpu_device):
+    """Columns at the grouped limit: exactly 23 value groups (tie runs plus
+    untied values), whose run-rank indices 0..22 sit next to the index 23 of
+    the table's zero entry that codes a missing sample; a column of 24
+    groups just past the limit; untied and sparsely tied partners; missing
+    values throughout, S = 1,000 (several walk groups and a ragged tail)."""
+    rng = np.random.default_rng(2323)
+    S = 1000
+
+    def runs_plus_singletons(nruns, singles):
+        x = rng.integers(0, nruns, S).astype(np.float64)
+        idx = rng.choice(S, len(singles), replace=False)
+        x[idx] = singles
+        return x, idx
+
+    c0, k0 = runs_plus_singletons(22, [99.0])                # 22 runs + 1 untied value
+    c1, k1 = runs_plus_singletons(23, [])                    # 23 runs
+    c2, k2 = runs_plus_singletons(21, [-5.0, 77.5])          # 21 runs + 2 untied values
+    c3, k3 = runs_plus_singletons(24, [])                    # 24 runs: past the limit
+    c4 = rng.standard_normal(S)                              # untied
+    c5 = rng.standard_normal(S)
+    for _ in range(3):                                       # a few duplicated pairs
+        a, b = rng.choice(S, 2, replace=False)
+        c5[b] = c5[a]
+    c6, k6 = runs_plus_singletons(23, [])                    # 23 runs, complete
+    X = np.column_stack([c0, c1, c2, c3, c4, c5, c6])
+    miss = rng.random(X.shape) < 0.3
+    miss[:, 6] = False
+    for j, keep in ((0, k0), (2, k2)):
+        miss[keep, j] = False                                # the untied values stay observed
+    X[miss] = np.nan
+    groups = [sum(_value_groups(X[:, j])) for j in range(X.shape[1])]
+    assert groups[0] == groups[1] == groups[2] == groups[6] == 23 and groups[3] == 24, groups
+    _check_full("spearman", X.astype(np.float32), gpu_device, where="grouped-limit-23")
+
+
 def test_spearman_max_samples(gpu_device):
     """S = 24,576, the largest sample count the 16-bit sorted orders hold:
     untied, sparsely tied, grouped (few values) and densely tied columns,
