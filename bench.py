@@ -5,11 +5,13 @@ Workload: 10,000 samples x 1,000 variables (rank-20 Gaussian factor model,
 10% Poisson(4) integer columns, 30% MCAR missingness plus 100 variables
 missing on one shared random half of the samples), float32 on the device
 before the timed region starts.  A step is one full r/p/n call of each
-method: napy_pearson (split-BF16 contractions by default) and napy_spearman,
-each on its own HIP stream (default priority) with its own workspace, so the
-MFMA-bound Pearson kernels run beside the VALU/LDS-bound Spearman scan
-(--one-stream issues both on one stream, one after the other).  value =
-F(F-1)/2 var-pairs / step time.
+method: napy_pearson (split-BF16 contractions by default), then
+napy_spearman, on one stream, so each call runs alone and
+value = F(F-1)/2 var-pairs / step time = F(F-1)/2 / (t_pearson + t_spearman).
+The same step with the two calls on their own HIP streams side by side
+(default priority, separate workspaces) is timed too and reported beside it
+(--two-streams makes that one the value).  Per-step times from HIP events are
+reported as median and spread.
 
 The JSON line also carries the FP32-contraction Pearson time (the precision
 comparison), the stage times measured with HIP events on the call's stream,
@@ -30,7 +32,8 @@ Two further forms print their own JSON line:
                     L = sum W o R, time and FP32-equivalent TFLOP/s of each;
   --form copy       a 256 MiB device copy, calibrating the HBM byte counters.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form headline|precision|serving]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--two-streams]
+                       [--form headline|precision|serving|differentiation|adjust|groups|copy]
 """
 
 from __future__ import annotations
@@ -120,23 +123,44 @@ class HipEvents:
         self.events = []
 
 
-def cpu_baseline(X, n_pairs: int, seed: int = 7):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(X, n_pairs: int, cores: int, repeats: int = 3, seed: int = 7):
     """The FP64 oracle (C + OpenMP, as it stands) on a bounded random sample of
     pairs of the same workload: Pearson and Spearman of every sampled pair,
-    p-values included.  Returns (var-pairs/s, cores, seconds, pairs)."""
+    p-values included, on `cores` threads.  Returns (median var-pairs/s over
+    `repeats` runs, list of run seconds, pairs)."""
     import numpy as np
     from oracle import oracle as orc
     F = X.shape[1]
     rng = np.random.default_rng(seed)
     g = rng.integers(0, F, n_pairs)
     h = rng.integers(0, F, n_pairs)
-    cores = len(os.sched_getaffinity(0))
     orc.pearson_pairs(X[:, :8], np.arange(4), np.arange(4), nthreads=cores)  # build + warm
-    t0 = time.perf_counter()
-    orc.pearson_pairs(X, g, h, nthreads=cores)
-    orc.spearman_pairs(X, g, h, nthreads=cores)
-    dt = time.perf_counter() - t0
-    return n_pairs / dt, cores, dt, n_pairs
+    secs = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        orc.pearson_pairs(X, g, h, nthreads=cores)
+        orc.spearman_pairs(X, g, h, nthreads=cores)
+        secs.append(time.perf_counter() - t0)
+    med = sorted(secs)[len(secs) // 2]
+    return n_pairs / med, secs, n_pairs
+
+
+def spread(a) -> dict:
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    return {"median": float(np.median(a)), "min": float(a.min()), "max": float(a.max()),
+            "p25": float(np.percentile(a, 25)), "p75": float(np.percentile(a, 75))}
 
 
 def main() -> int:
@@ -145,12 +169,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
-    ap.add_argument("--cpu-pairs", type=int, default=250000,
-                    help="pairs in the oracle's timed sample (about 10-30 s of host work)")
+    ap.add_argument("--cpu-pairs", type=int, default=96000,
+                    help="pairs in the oracle's timed sample on all cores (a few seconds per run)")
+    ap.add_argument("--cpu-pairs-1core", type=int, default=6000,
+                    help="pairs in the oracle's timed sample on one core")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--one-stream", action="store_true",
-                    help="headline: Pearson and Spearman on one stream, one after the other")
+    ap.add_argument("--two-streams", action="store_true",
+                    help="headline: time steps with Pearson and Spearman on two streams side by side "
+                         "(value then is that step's throughput)")
     ap.add_argument("--form", default="headline",
                     choices=["headline", "precision", "serving", "differentiation", "copy", "adjust", "groups"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: measured queries")
@@ -196,12 +223,9 @@ def main() -> int:
     assert not bool(torch.isinf(Xd).any())
     stream = torch.cuda.current_stream(dev)
     sh = ctypes.c_void_p(stream.cuda_stream)
-    # Pearson and Spearman streams (default priority) and workspaces
-    if args.one_stream:
-        sh_p = sh_s = sh
-    else:
-        st_p, st_s = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
-        sh_p, sh_s = ctypes.c_void_p(st_p.cuda_stream), ctypes.c_void_p(st_s.cuda_stream)
+    # streams of the two-stream step (default priority)
+    st_p, st_s = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+    sh_p2, sh_s2 = ctypes.c_void_p(st_p.cuda_stream), ctypes.c_void_p(st_s.cuda_stream)
 
     def P(t):
         return ctypes.c_void_p(t.data_ptr())
@@ -220,17 +244,16 @@ def main() -> int:
 
     hev = HipEvents()
     K, W = args.steps, args.warmup
-    evp = [[hev.new() for _ in range(4)] for _ in range(K)]
-    evs = [[hev.new() for _ in range(4)] for _ in range(K)]
-    evf = [[hev.new() for _ in range(4)] for _ in range(K)]
 
-    def arr(evl):
-        a = (ctypes.c_void_p * 4)(*[e.value for e in evl])
-        return a
+    def ev_set():
+        evl = [[hev.new() for _ in range(4)] for _ in range(K)]
+        return evl, [(ctypes.c_void_p * 4)(*[e.value for e in e4]) for e4 in evl]
 
-    evp_a = [arr(e) for e in evp]
-    evs_a = [arr(e) for e in evs]
-    evf_a = [arr(e) for e in evf]
+    evp, evp_a = ev_set()   # Pearson stage events of each timed step
+    evs, evs_a = ev_set()   # Spearman
+    evf, evf_a = ev_set()   # FP32-contraction Pearson
+    evp2, evp2_a = ev_set()  # two-stream steps
+    evs2, evs2_a = ev_set()
 
     def pearson_call(opts, o, ev, sh_call):
         r, p, n = o
@@ -238,26 +261,45 @@ def main() -> int:
                                        ctypes.byref(opts), sh_call, ev)
         _lib.check(st, "napy_pearson")
 
-    def spearman_call(o, ev):
+    def spearman_call(o, ev, sh_call):
         r, p, n = o
         st = lib.napy_spearman_profiled(P(Xd), S, F, F, P(r), P(p), P(n), F, P(ws_s), ws_s_bytes,
-                                        ctypes.byref(opt_sp), sh_s, ev)
+                                        ctypes.byref(opt_sp), sh_call, ev)
         _lib.check(st, "napy_spearman")
 
-    def step(i, ev=True):
-        pearson_call(opt_main, out["pearson"], evp_a[i] if ev else None, sh_p)
-        spearman_call(out["spearman"], evs_a[i] if ev else None)
+    # A step is one full r/p/n call of each method.  Sequential steps (the
+    # default): Pearson, then Spearman, on one stream, so each call runs alone
+    # and value = F(F-1)/2 / (t_pearson + t_spearman).  Two-stream steps:
+    # Pearson and Spearman on their own streams side by side.
+    def step_seq(i, ev=True):
+        pearson_call(opt_main, out["pearson"], evp_a[i] if ev else None, sh)
+        spearman_call(out["spearman"], evs_a[i] if ev else None, sh)
 
-    torch.cuda.synchronize()  # the input is on the device before either stream reads it
-    for _ in range(W):
-        step(0, ev=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        step(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / K
+    def step_two(i, ev=True):
+        pearson_call(opt_main, out["pearson"], evp2_a[i] if ev else None, sh_p2)
+        spearman_call(out["spearman"], evs2_a[i] if ev else None, sh_s2)
+
+    def timed(step_fn):
+        torch.cuda.synchronize()  # the input is on the device before any stream reads it
+        for _ in range(W):
+            step_fn(0, ev=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            step_fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / K
+
+    main_two = args.two_streams
+    # the measured configuration first, the other one beside it
+    if main_two:
+        ms_per_step = timed(step_two)
+        ms_seq = timed(step_seq)
+        ms_two = ms_per_step
+    else:
+        ms_per_step = timed(step_seq)
+        ms_two = timed(step_two)
+        ms_seq = ms_per_step
 
     # FP32-contraction Pearson, timed separately for the precision comparison
     for _ in range(W):
@@ -267,18 +309,27 @@ def main() -> int:
         pearson_call(opt_fp32, out["fp32"], evf_a[i], sh)
     torch.cuda.synchronize()
 
-    def stage_means(evl):
+    def stages(evl):
         st = np.array([[hev.ms(e[j], e[j + 1]) for j in range(3)] for e in evl])
         tot = np.array([hev.ms(e[0], e[3]) for e in evl])
-        return st.mean(0), float(tot.mean())
+        return st, tot
 
-    ps, pt = stage_means(evp)
-    ss, stt = stage_means(evs)
-    fs, ft = stage_means(evf)
+    ps, pt = stages(evp)
+    ss, stt = stages(evs)
+    fs, ft = stages(evf)
+    # per-step device time: sequential steps span the Pearson call's first
+    # event to the Spearman call's last; two-stream steps the earlier start to
+    # the later end
+    step_seq_ms = np.array([hev.ms(evp[i][0], evs[i][3]) for i in range(K)])
+    step_two_ms = np.array([max(hev.ms(evp2[i][0], evp2[i][3]), hev.ms(evp2[i][0], evs2[i][3]))
+                            - min(0.0, hev.ms(evp2[i][0], evs2[i][0])) for i in range(K)])
     hev.close()
 
     pairs = F * (F - 1) // 2
     value = pairs / (ms_per_step / 1e3)
+    t_p, t_s = float(np.median(pt)), float(np.median(stt))
+    med = lambda a: float(np.median(a, axis=0)) if np.ndim(a) == 1 else np.median(a, axis=0)
+    psm, ssm, fsm = med(ps), med(ss), med(fs)
 
     # dominant kernel: the per-pair re-ranking scan.  Algorithmic work per
     # pair (g, h) = n_g + n_h rank-steps (every present sample of each side is
@@ -286,7 +337,7 @@ def main() -> int:
     # accumulate); all F(F+1)/2 pairs including the diagonal are computed.
     ncol = (~np.isnan(X)).sum(0).astype(np.float64)
     rank_steps = float((F + 1) * ncol.sum())  # sum over g <= h of (n_g + n_h)
-    scan_s = ss[1] / 1e3
+    scan_s = float(ssm[1]) / 1e3
     ops = 4.0 * rank_steps
     achieved = ops / scan_s
     # streamed-bytes model of the same scan: 2 B index + 1/8 B tie bit per
@@ -310,19 +361,28 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "samples": S, "variables": F, "pearson_precision": args.precision,
                    "parallelism": "single GPU",
-                   "streams": "one (Pearson then Spearman)" if args.one_stream
-                   else "two (Pearson beside Spearman)"},
-        "pearson_ms": pt,
-        "spearman_ms": stt,
-        "pearson_fp32_ms": ft,
-        "stage_ms": {
-            "pearson_colstats": ps[0], "pearson_contract": ps[1], "pearson_combine_p": ps[2],
-            "pearson_fp32_contract": fs[1],
-            "spearman_sort": ss[0], "spearman_scan": ss[1], "spearman_combine_p": ss[2],
+                   "step": "two streams (Pearson beside Spearman)" if main_two
+                   else "one stream (Pearson, then Spearman: each call alone)"},
+        "value_is": ("F(F-1)/2 / two-stream step time" if main_two else
+                     "F(F-1)/2 / (t_pearson + t_spearman), each call alone on one stream (wall clock of K steps)"),
+        "headline_alone": {"value": pairs / ((t_p + t_s) / 1e3), "t_pearson_ms": t_p, "t_spearman_ms": t_s,
+                           "definition": "F(F-1)/2 / (median t_pearson + median t_spearman), HIP events, "
+                                         "each call alone"},
+        "two_stream": {"value": pairs / (ms_two / 1e3), "ms_per_step": ms_two,
+                       "step_ms": spread(step_two_ms)},
+        "one_stream": {"value": pairs / (ms_seq / 1e3), "ms_per_step": ms_seq,
+                       "step_ms": spread(step_seq_ms)},
+        "pearson_ms": spread(pt),
+        "spearman_ms": spread(stt),
+        "pearson_fp32_ms": spread(ft),
+        "stage_ms_median": {
+            "pearson_colstats": float(psm[0]), "pearson_contract": float(psm[1]),
+            "pearson_combine_p": float(psm[2]), "pearson_fp32_contract": float(fsm[1]),
+            "spearman_sort": float(ssm[0]), "spearman_scan": float(ssm[1]), "spearman_combine_p": float(ssm[2]),
         },
         "pearson_contract_tflops": {
-            args.precision: pearson_flop / (ps[1] / 1e3) / 1e12,
-            "fp32": pearson_flop / (fs[1] / 1e3) / 1e12,
+            args.precision: pearson_flop / (float(psm[1]) / 1e3) / 1e12,
+            "fp32": pearson_flop / (float(fsm[1]) / 1e3) / 1e12,
         },
         "roofline": {
             "kernel": "k_spearman_pairs",
@@ -333,6 +393,7 @@ def main() -> int:
             "frac": achieved / VALU_PEAK_OPS,
             "traffic": scan_traffic_bytes(),
             "work": f"{rank_steps:.4g} rank-steps x 4 ops per launch",
+            "time": "median HIP-event time of the scan stage, sequential steps",
         },
         "roofline_hbm_model": {
             "kernel": "k_spearman_pairs",
@@ -361,10 +422,17 @@ def main() -> int:
         del ws64
 
     if not args.no_cpu_baseline:
-        v, cores, dt, npairs = cpu_baseline(X, args.cpu_pairs)
+        cores = len(os.sched_getaffinity(0))
+        v, secs, npairs = cpu_baseline(X, args.cpu_pairs, cores)
+        v1, secs1, npairs1 = cpu_baseline(X, args.cpu_pairs_1core, 1)
         res["cpu_baseline"] = {"value": v, "unit": "var-pairs/s", "cores": cores, "kind": "oracle",
                                "sample": f"{npairs} random pairs of the same 10,000 x 1,000 matrix, "
-                                         f"Pearson + Spearman with p-values, {dt:.1f} s"}
+                                         f"Pearson + Spearman with p-values; median of 3 runs "
+                                         f"({', '.join(f'{t:.2f}' for t in secs)} s)",
+                               "cpu": cpu_model(),
+                               "one_core": {"value": v1, "unit": "var-pairs/s", "cores": 1,
+                                            "sample": f"{npairs1} random pairs, median of 3 runs "
+                                                      f"({', '.join(f'{t:.2f}' for t in secs1)} s)"}}
     print(json.dumps(res))
     return 0
 
@@ -403,7 +471,7 @@ def run_differentiation(args) -> int:
         wsb = torch.empty(lib.napy_pearson_backward_workspace(S, F, ctypes.byref(opts)), dtype=torch.uint8,
                           device=dev)
         r = torch.empty((F, F), dtype=torch.float64, device=dev)
-        saved = torch.empty((6, F, F), dtype=torch.float64, device=dev)
+        saved = torch.empty((7, F, F), dtype=torch.float64, device=dev)
         dX = torch.empty((S, F), dtype=torch.float32, device=dev)
 
         def step():

@@ -90,7 +90,12 @@ const char* napy_version(void);
  * [-1, 1], and p = I_{1-r^2}((n-2)/2, 1/2).  n <= 1 -> r = p = NaN;
  * n = 2 -> r = +-1, p = 1; zero variance of either side on I -> r = p = NaN.
  * Computed as masked dense contractions on the matrix cores after centring
- * every variable on its observed mean (r is shift invariant).
+ * every variable on its observed mean (r is shift invariant).  A pair whose
+ * variance about its own mean is below 0.9 of its second moment about the
+ * column mean on either side (complete samples far from the column mean,
+ * or a side constant on I) is recomputed from the raw values in FP64 by two
+ * passes about the pair's means, and its zero variance decided exactly
+ * (minimum = maximum on I); such pairs cost O(S) each.
  * Supported: 1 <= F <= 65535, 1 <= S <= 2^31 - 1.
  * ------------------------------------------------------------------------ */
 size_t napy_pearson_workspace(int64_t S, int64_t F, const napy_opts* opts);
@@ -139,16 +144,16 @@ int napy_spearman_profiled(const float* X, int64_t S, int64_t F, int64_t ldx,
  * derivative of the Section 3.5.2 definition).
  *
  * napy_pearson_fwd: napy_pearson plus `saved`, caller-owned float64
- * [6][F][F] (ld F): n, Sx, Sy, Sxx, Syy, Sxy per ordered pair (g, h), the
+ * [7][F][F] (ld F): n, Sx, Sy, Sxx, Syy, Sxy per ordered pair (g, h), the
  * sums over I(g,h) of 1, x_g, x_h, x_g^2, x_h^2 and x_g x_h, where x is the
- * data centred on each variable's observed mean.  Workspace as
- * napy_pearson_workspace.
+ * data centred on each variable's observed mean, then r (NaN where
+ * undefined).  Workspace as napy_pearson_workspace.
  *
  * napy_pearson_backward: given dR = dL/dR (float32, F x F, row-major, ld ldr;
  * entries (g, h) and (h, g) are both read, the diagonal is ignored because
  * r_gg is constant), writes dX = dL/dX (float32, S x F, ld lddx).  Missing
- * entries get exactly 0, as do entries whose pairs have undefined r.  X,
- * opts and S, F must be the forward's.
+ * entries get exactly 0, as do entries whose pairs have undefined r (NaN in
+ * saved's r plane).  X, opts and S, F must be the forward's.
  * ------------------------------------------------------------------------ */
 int napy_pearson_fwd(const float* X, int64_t S, int64_t F, int64_t ldx,
                      double* r, double* p, int32_t* n, int64_t ldo, double* saved,

@@ -291,7 +291,7 @@ class PearsonCorr(torch.autograd.Function):
         need = lib.napy_pearson_workspace(S, F, ctypes.byref(opts))
         ws = _workspace(need, Xc.device)
         r = torch.empty((F, F), dtype=torch.float64, device=Xc.device)
-        saved = torch.empty((6, F, F), dtype=torch.float64, device=Xc.device)
+        saved = torch.empty((7, F, F), dtype=torch.float64, device=Xc.device)
         st = lib.napy_pearson_fwd(_ptr(Xc), S, F, Xc.stride(0), _ptr(r), None, None, F, _ptr(saved),
                                   _ptr(ws), ws.numel(), ctypes.byref(opts), _stream_handle(Xc.device))
         _lib.check(st, "napy_pearson_fwd")

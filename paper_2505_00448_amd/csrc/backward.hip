@@ -15,10 +15,11 @@
 // with X0 the zero-filled centred data and M the presence mask: three
 // [S x F] x [F x F] products and an elementwise epilogue.  Because r is
 // invariant to the per-column centring, this is also the gradient for the raw
-// data.  Pairs with undefined r contribute nothing; missing entries get 0.
+// data.  Pairs whose forward r is undefined (NaN) contribute nothing; missing
+// entries get 0.
 //
-//   k_bwd_coef   FP64 per-pair coefficients from the saved forward sums,
-//                stored as FP32 [F][F] matrices.
+//   k_bwd_coef   FP64 per-pair coefficients from the saved forward sums and
+//                the forward's r, stored as FP32 [F][F] matrices.
 //   k_bwd_mfma   64 x 64 (samples x variables) output tiles on
 //                v_mfma_f32_16x16x4_f32, contraction over partners h.
 #include "napy_internal.hpp"
@@ -28,9 +29,8 @@ namespace napy {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_bwd_coef(const double* __restrict__ saved, const float* __restrict__ dR,
-                                                  int64_t ldr, int64_t F, double var_tol,
-                                                  float* __restrict__ Ac, float* __restrict__ Bc,
-                                                  float* __restrict__ Qc)
+                                                  int64_t ldr, int64_t F, float* __restrict__ Ac,
+                                                  float* __restrict__ Bc, float* __restrict__ Qc)
 {
     const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t g = blockIdx.y;
@@ -39,12 +39,12 @@ __global__ __launch_bounds__(256) void k_bwd_coef(const double* __restrict__ sav
     float a = 0.f, b = 0.f, q = 0.f;
     if (g != h) {
         const double n = saved[e], sx = saved[FF + e], sy = saved[2 * FF + e];
-        const double sxx = saved[3 * FF + e], syy = saved[4 * FF + e], sxy = saved[5 * FF + e];
+        const double sxx = saved[3 * FF + e], syy = saved[4 * FF + e];
+        const double r = saved[6 * FF + e];  // the forward's r (NaN: undefined)
         const double vx = n * sxx - sx * sx, vy = n * syy - sy * sy;
-        if (n >= 2.0 && vx > var_tol * n * sxx && vy > var_tol * n * syy) {
+        if (r == r && vx > 0.0 && vy > 0.0) {
             const double G = (double)dR[g * ldr + h] + (double)dR[h * ldr + g];
             const double rs = sqrt(vx * vy);
-            const double r = (n * sxy - sx * sy) / rs;
             a = (float)(G * n / rs);
             b = (float)(G * (-sy / rs + r * sx / vx));
             q = (float)(-G * r * n / vx);
@@ -179,10 +179,9 @@ int backward_run(const float* X, int64_t S, int64_t F, int64_t ldx, const double
     bwd_carve(c, S, F, w);
     const int us = opt_use_sent(opts);
     const float sv = opt_sent(opts);
-    const double tol = (opt_prec(opts) == NAPY_PREC_FP64) ? 1e-12 : 1e-5;
     NAPY_TRY(colstats_launch(X, S, F, ldx, us, sv, w.cs, st));
     hipLaunchKernelGGL(k_bwd_coef, dim3((unsigned)ceil_div(F, 256), (unsigned)F), dim3(256), 0, st, saved, dR,
-                       ldr, F, tol, w.Ac, w.Bc, w.Qc);
+                       ldr, F, w.Ac, w.Bc, w.Qc);
     NAPY_TRY(check_launch("bwd_coef"));
     if (S == 0) return NAPY_OK;
     hipLaunchKernelGGL(k_bwd_mfma, dim3((unsigned)ceil_div(S, BT), (unsigned)ceil_div(F, BT)), dim3(256), 0, st,

@@ -22,7 +22,12 @@
 //                    FLUSH samples; the FP64 partial sums go to the workspace.
 //   k_pearson_combine  sums the split-K partials in FP64, forms
 //                    C = n Sxy - Sx Sy, Vx = n Sxx - Sx^2, Vy = n Syy - Sy^2,
-//                    r = C / sqrt(Vx Vy) and p, and writes both triangles.
+//                    r = C / sqrt(Vx Vy) and p, and writes both triangles;
+//                    a pair whose complete samples sit far from a column's
+//                    mean (or that is constant on I(g,h)) is listed instead.
+//   k_pearson_recompute  the listed pairs from the raw values, two passes in
+//                    FP64 about the pair's own means, zero variance decided
+//                    exactly.
 //
 // Precisions (napy_opts.precision):
 //   FP32    v_mfma_f32_16x16x4_f32, 6 products per pair-sample.
@@ -183,13 +188,6 @@ struct TileCfg<NAPY_PREC_FP32> {
     static constexpr int RPT = 8;     // rows per thread in the staging step
 };
 template <>
-struct TileCfg<NAPY_PREC_BF16X3> {
-    static constexpr int BK = 32;
-    static constexpr int LDK = 40;
-    static constexpr int FLUSH = 1024;
-    static constexpr int RPT = 8;
-};
-template <>
 struct TileCfg<NAPY_PREC_FP64> {
     static constexpr int BK = 16;
     static constexpr int LDK = 18;
@@ -227,24 +225,18 @@ struct LdsPlan<NAPY_PREC_FP32> {
     static constexpr int ELEMS = 2 * TILE * TileCfg<NAPY_PREC_FP32>::LDK;  // floats per buffer
 };
 template <>
-struct LdsPlan<NAPY_PREC_BF16X3> {
-    static constexpr int NPL = 7;  // xh, xm, xl, qh, qm, ql, m
-    static constexpr int ELEMS = 2 * NPL * TILE * TileCfg<NAPY_PREC_BF16X3>::LDK;  // bf16 per buffer
-};
-template <>
 struct LdsPlan<NAPY_PREC_FP64> {
     static constexpr int ELEMS = 2 * TILE * TileCfg<NAPY_PREC_FP64>::LDK;  // doubles per buffer
 };
 
-__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
-__device__ __forceinline__ float from_bf16(__bf16 v) { return (float)v; }
-
+// FP32 and FP64 forms (the split-BF16 form is k_pearson_bf16 below).
 template <int PREC>
 __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
     const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
     const float* __restrict__ mu32, const double* __restrict__ mu64, int T, int ntiles, int nsplit,
     int64_t ksplit, double* __restrict__ part)
 {
+    static_assert(PREC == NAPY_PREC_FP32 || PREC == NAPY_PREC_FP64, "FP32 or FP64 tiles");
     using C = TileCfg<PREC>;
     constexpr int BK = C::BK, LDK = C::LDK, RPT = C::RPT;
 
@@ -268,8 +260,7 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
     const bool okG = colG < F, okH = colH < F;
 
     // ---- LDS ----------------------------------------------------------------
-    using LT = typename std::conditional<PREC == NAPY_PREC_FP64, double,
-               typename std::conditional<PREC == NAPY_PREC_FP32, float, __bf16>::type>::type;
+    using LT = typename std::conditional<PREC == NAPY_PREC_FP64, double, float>::type;
     constexpr int BUF = LdsPlan<PREC>::ELEMS;
     __shared__ __attribute__((aligned(16))) LT lds[2 * BUF];
 
@@ -321,60 +312,15 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
 #pragma unroll
                 for (int j = 0; j < RPT; ++j) dst[j] = v[j];
             }
-        } else {
-            // BF16X3: layout [side][plane][col][LDK], planes xh, xm, xl, qh, qm, ql, m
-            constexpr int NPL = LdsPlan<PREC>::NPL;
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                bf16x8 pl[NPL];
-#pragma unroll
-                for (int j = 0; j < RPT; ++j) {
-                    const float raw = side ? rawH[j] : rawG[j];
-                    const float mu = side ? muH32 : muG32;
-                    const bool miss = is_missing(raw, use_sent, sent);
-                    const float x = miss ? 0.0f : raw - mu;
-                    // x = xh + xm + xl exactly: each residual is exact in float32
-                    const __bf16 xh = to_bf16(x);
-                    const float x1 = x - from_bf16(xh);
-                    const __bf16 xm = to_bf16(x1);
-                    const __bf16 xl = to_bf16(x1 - from_bf16(xm));
-                    const float q = x * x;
-                    const __bf16 qh = to_bf16(q);
-                    const float q1 = q - from_bf16(qh);
-                    const __bf16 qm = to_bf16(q1);
-                    const __bf16 ql = to_bf16(q1 - from_bf16(qm));
-                    pl[0][j] = xh;
-                    pl[1][j] = xm;
-                    pl[2][j] = xl;
-                    pl[3][j] = qh;
-                    pl[4][j] = qm;
-                    pl[5][j] = ql;
-                    pl[6][j] = miss ? to_bf16(0.0f) : to_bf16(1.0f);
-                }
-#pragma unroll
-                for (int pp = 0; pp < NPL; ++pp)
-                    *(bf16x8*)(base + ((side * NPL + pp) * TILE + sc) * LDK + kg * RPT) = pl[pp];
-            }
         }
     };
 
-    // ---- accumulators ---------------------------------------------------------
-    // FP32/FP64: four 16x16 sub-blocks per wave, acc[sub][stat] x4.
-    // BF16X3: one 32x32 block per wave.  The matrix cores add each product
-    // block into the accumulator with one float32 rounding (toward zero), so
-    // the products of the leading pieces and the much smaller products of
-    // the trailing pieces go to separate accumulators: the leading ones then
-    // see one rounding per 16 samples, and the trailing ones' roundings are
-    // 2^-9 smaller.  Counts are exact in float32 and never flushed; the sums
-    // of centred values Sx, Sy stay small (their partial sums wander around
-    // zero), so only Sxx, Syy and Sxy, whose partial sums grow with the
-    // sample count, are flushed into FP64.
-    constexpr int NSUB = (PREC == NAPY_PREC_BF16X3) ? 1 : 4;
-    constexpr int NREG = (PREC == NAPY_PREC_BF16X3) ? 16 : 4;
-    constexpr int NACC = (PREC == NAPY_PREC_BF16X3) ? 11 : NSTAT;  // BF16X3: n, then (main, low) x 5
+    // ---- accumulators: four 16x16 sub-blocks per wave, acc[sub][stat] x4 ----
+    // FP32 sums are added into FP64 registers every FLUSH samples.
+    constexpr int NSUB = 4, NREG = 4, NACC = NSTAT;
     using AccT = typename std::conditional<PREC == NAPY_PREC_FP64, double, float>::type;
     AccT acc[NSUB][NACC][NREG];
-    constexpr int N64 = (PREC == NAPY_PREC_BF16X3) ? 3 : NSTAT;  // FP64 sums (BF16X3: Sxx, Syy, Sxy)
+    constexpr int N64 = (PREC == NAPY_PREC_FP32) ? NSTAT : 1;  // FP64 sums (unused in FP64 mode)
     double acc64[NSUB][N64][NREG];
 #pragma unroll
     for (int a = 0; a < NSUB; ++a) {
@@ -389,16 +335,7 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
     }
 
     auto flush = [&]() {
-        if constexpr (PREC == NAPY_PREC_BF16X3) {
-#pragma unroll
-            for (int s = 0; s < 3; ++s)
-#pragma unroll
-                for (int r = 0; r < NREG; ++r) {
-                    acc64[0][s][r] += (double)acc[0][5 + 2 * s][r] + (double)acc[0][6 + 2 * s][r];
-                    acc[0][5 + 2 * s][r] = 0.0f;
-                    acc[0][6 + 2 * s][r] = 0.0f;
-                }
-        } else if constexpr (PREC == NAPY_PREC_FP32) {
+        if constexpr (PREC == NAPY_PREC_FP32) {
 #pragma unroll
             for (int a = 0; a < NSUB; ++a)
 #pragma unroll
@@ -413,107 +350,60 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
 
     auto compute = [&](int buf) {
         const LT* base = lds + buf * BUF;
-        if constexpr (PREC == NAPY_PREC_BF16X3) {
-            constexpr int NPL = LdsPlan<PREC>::NPL;
-            const int rr = lane & 31, kq = (lane >> 5) * 8;
+        const int rr = lane & 15, kq = lane >> 4;
 #pragma unroll
-            for (int kk = 0; kk < BK / 16; ++kk) {
-                const int k = kk * 16 + kq;
-                bf16x8 a[NPL], b[NPL];
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const int k = kk * 4 + kq;
+            AccT xa[2], ma[2], qa[2], xb[2], mb[2], qb[2];
 #pragma unroll
-                for (int pp = 0; pp < NPL; ++pp) {
-                    a[pp] = *(const bf16x8*)(base + ((0 * NPL + pp) * TILE + wm * 32 + rr) * LDK + k);
-                    b[pp] = *(const bf16x8*)(base + ((1 * NPL + pp) * TILE + wn * 32 + rr) * LDK + k);
-                }
-                f32x16 c[11];
-#pragma unroll
-                for (int q = 0; q < 11; ++q)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) c[q][r] = acc[0][q][r];
-                // planes: 0 xh, 1 xm, 2 xl, 3 qh, 4 qm, 5 ql, 6 m
-                // accumulators: 0 n, 1/2 Sx, 3/4 Sy, 5/6 Sxx, 7/8 Syy, 9/10 Sxy (main/low)
-#define NAPY_MF(q, x, y) c[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c[q], 0, 0, 0)
-                NAPY_MF(0, a[6], b[6]);
-                NAPY_MF(1, a[0], b[6]);
-                NAPY_MF(3, a[6], b[0]);
-                NAPY_MF(5, a[3], b[6]);
-                NAPY_MF(7, a[6], b[3]);
-                NAPY_MF(9, a[0], b[0]);
-                NAPY_MF(2, a[1], b[6]);
-                NAPY_MF(4, a[6], b[1]);
-                NAPY_MF(6, a[4], b[6]);
-                NAPY_MF(8, a[6], b[4]);
-                NAPY_MF(10, a[0], b[1]);
-                NAPY_MF(2, a[2], b[6]);
-                NAPY_MF(4, a[6], b[2]);
-                NAPY_MF(6, a[5], b[6]);
-                NAPY_MF(8, a[6], b[5]);
-                NAPY_MF(10, a[1], b[0]);
-                NAPY_MF(10, a[0], b[2]);
-                NAPY_MF(10, a[1], b[1]);
-                NAPY_MF(10, a[2], b[0]);
-#undef NAPY_MF
-#pragma unroll
-                for (int q = 0; q < 11; ++q)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[0][q][r] = c[q][r];
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const AccT va = base[(0 * TILE + wm * 32 + s2 * 16 + rr) * LDK + k];
+                const AccT vb = base[(1 * TILE + wn * 32 + s2 * 16 + rr) * LDK + k];
+                const bool pa = va == va, pb = vb == vb;
+                xa[s2] = pa ? va : (AccT)0;
+                ma[s2] = pa ? (AccT)1 : (AccT)0;
+                qa[s2] = xa[s2] * xa[s2];
+                xb[s2] = pb ? vb : (AccT)0;
+                mb[s2] = pb ? (AccT)1 : (AccT)0;
+                qb[s2] = xb[s2] * xb[s2];
             }
-        } else {
-            const int rr = lane & 15, kq = lane >> 4;
 #pragma unroll
-            for (int kk = 0; kk < BK / 4; ++kk) {
-                const int k = kk * 4 + kq;
-                AccT xa[2], ma[2], qa[2], xb[2], mb[2], qb[2];
+            for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2) {
-                    const AccT va = base[(0 * TILE + wm * 32 + s2 * 16 + rr) * LDK + k];
-                    const AccT vb = base[(1 * TILE + wn * 32 + s2 * 16 + rr) * LDK + k];
-                    const bool pa = va == va, pb = vb == vb;
-                    xa[s2] = pa ? va : (AccT)0;
-                    ma[s2] = pa ? (AccT)1 : (AccT)0;
-                    qa[s2] = xa[s2] * xa[s2];
-                    xb[s2] = pb ? vb : (AccT)0;
-                    mb[s2] = pb ? (AccT)1 : (AccT)0;
-                    qb[s2] = xb[s2] * xb[s2];
-                }
+                for (int ib = 0; ib < 2; ++ib) {
+                    const int sub = ia * 2 + ib;
+                    if constexpr (PREC == NAPY_PREC_FP32) {
+                        f32x4 c[NSTAT];
 #pragma unroll
-                for (int ia = 0; ia < 2; ++ia)
+                        for (int s = 0; s < NSTAT; ++s)
+                            c[s] = f32x4{acc[sub][s][0], acc[sub][s][1], acc[sub][s][2], acc[sub][s][3]};
+                        c[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], mb[ib], c[0], 0, 0, 0);
+                        c[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ia], mb[ib], c[1], 0, 0, 0);
+                        c[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], xb[ib], c[2], 0, 0, 0);
+                        c[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[ia], mb[ib], c[3], 0, 0, 0);
+                        c[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], qb[ib], c[4], 0, 0, 0);
+                        c[5] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ia], xb[ib], c[5], 0, 0, 0);
 #pragma unroll
-                    for (int ib = 0; ib < 2; ++ib) {
-                        const int sub = ia * 2 + ib;
-                        if constexpr (PREC == NAPY_PREC_FP32) {
-                            f32x4 c[NSTAT];
+                        for (int s = 0; s < NSTAT; ++s)
 #pragma unroll
-                            for (int s = 0; s < NSTAT; ++s)
-                                c[s] = f32x4{acc[sub][s][0], acc[sub][s][1], acc[sub][s][2], acc[sub][s][3]};
-                            c[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], mb[ib], c[0], 0, 0, 0);
-                            c[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ia], mb[ib], c[1], 0, 0, 0);
-                            c[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], xb[ib], c[2], 0, 0, 0);
-                            c[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[ia], mb[ib], c[3], 0, 0, 0);
-                            c[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(ma[ia], qb[ib], c[4], 0, 0, 0);
-                            c[5] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[ia], xb[ib], c[5], 0, 0, 0);
+                            for (int r = 0; r < 4; ++r) acc[sub][s][r] = c[s][r];
+                    } else {
+                        f64x4 c[NSTAT];
 #pragma unroll
-                            for (int s = 0; s < NSTAT; ++s)
+                        for (int s = 0; s < NSTAT; ++s)
+                            c[s] = f64x4{acc[sub][s][0], acc[sub][s][1], acc[sub][s][2], acc[sub][s][3]};
+                        c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], mb[ib], c[0], 0, 0, 0);
+                        c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ia], mb[ib], c[1], 0, 0, 0);
+                        c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], xb[ib], c[2], 0, 0, 0);
+                        c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[ia], mb[ib], c[3], 0, 0, 0);
+                        c[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], qb[ib], c[4], 0, 0, 0);
+                        c[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ia], xb[ib], c[5], 0, 0, 0);
 #pragma unroll
-                                for (int r = 0; r < 4; ++r) acc[sub][s][r] = c[s][r];
-                        } else {
-                            f64x4 c[NSTAT];
+                        for (int s = 0; s < NSTAT; ++s)
 #pragma unroll
-                            for (int s = 0; s < NSTAT; ++s)
-                                c[s] = f64x4{acc[sub][s][0], acc[sub][s][1], acc[sub][s][2], acc[sub][s][3]};
-                            c[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], mb[ib], c[0], 0, 0, 0);
-                            c[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ia], mb[ib], c[1], 0, 0, 0);
-                            c[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], xb[ib], c[2], 0, 0, 0);
-                            c[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[ia], mb[ib], c[3], 0, 0, 0);
-                            c[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[ia], qb[ib], c[4], 0, 0, 0);
-                            c[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ia], xb[ib], c[5], 0, 0, 0);
-#pragma unroll
-                            for (int s = 0; s < NSTAT; ++s)
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) acc[sub][s][r] = c[s][r];
-                        }
+                            for (int r = 0; r < 4; ++r) acc[sub][s][r] = c[s][r];
                     }
-            }
+                }
         }
     };
 
@@ -541,37 +431,21 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
 #pragma unroll
     for (int s = 0; s < NSTAT; ++s) {
         double* dst = part + (((int64_t)split * NSTAT + s) * ntiles + t) * TILE_ELEMS;
-        if constexpr (PREC == NAPY_PREC_BF16X3) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int j = wn * 32 + (lane & 31);
-                double v;
-                if (s == 0)
-                    v = (double)acc[0][0][r];
-                else if (s <= 2)
-                    v = (double)acc[0][2 * s - 1][r] + (double)acc[0][2 * s][r];
-                else
-                    v = acc64[0][s - 3][r];
-                dst[i * TILE + j] = v;
-            }
-        } else {
+        for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-            for (int ia = 0; ia < 2; ++ia)
+            for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-                for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        // 16x16 blocks: f32 rows are 4*(lane/16) + r, f64 rows are
-                        // lane/16 + 4*r; columns are lane%16 in both
-                        const int ri = (PREC == NAPY_PREC_FP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
-                        const int i = wm * 32 + ia * 16 + ri;
-                        const int j = wn * 32 + ib * 16 + (lane & 15);
-                        const double v = (PREC == NAPY_PREC_FP64) ? (double)acc[ia * 2 + ib][s][r]
-                                                                   : acc64[ia * 2 + ib][s][r];
-                        dst[i * TILE + j] = v;
-                    }
-        }
+                for (int r = 0; r < 4; ++r) {
+                    // 16x16 blocks: f32 rows are 4*(lane/16) + r, f64 rows are
+                    // lane/16 + 4*r; columns are lane%16 in both
+                    const int ri = (PREC == NAPY_PREC_FP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
+                    const int i = wm * 32 + ia * 16 + ri;
+                    const int j = wn * 32 + ib * 16 + (lane & 15);
+                    const double v = (PREC == NAPY_PREC_FP64) ? (double)acc[ia * 2 + ib][s][r]
+                                                               : acc64[ia * 2 + ib][s][r];
+                    dst[i * TILE + j] = v;
+                }
     }
 }
 
@@ -821,10 +695,53 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
 // ---------------------------------------------------------------------------
 // K3: combine split-K partials, r, p, n; both triangles
 // ---------------------------------------------------------------------------
+// A pair is combined from its sums when, on both sides, the variance about
+// the pair's own mean is at least WELL_CENTRED of the second moment about the
+// column mean (n Sxx - Sx^2 >= WELL_CENTRED n Sxx): the rounding error of the
+// accumulated sums then reaches r amplified by at most 1 / WELL_CENTRED.
+// Every other pair with n >= 2 -- complete samples far from the column mean,
+// and every pair that is constant on I(g,h) -- goes to a list and is
+// recomputed from the raw values by k_pearson_recompute.
+constexpr double WELL_CENTRED = 0.9;
+constexpr int NSAVED = NSTAT + 1;  // saved sums n, Sx, Sy, Sxx, Syy, Sxy, then r
+
+__device__ __forceinline__ void write_pair(int64_t g, int64_t h, int64_t ldo, double rv, double pv, int64_t ni,
+                                           double* __restrict__ r, double* __restrict__ p,
+                                           int32_t* __restrict__ n)
+{
+    if (r) {
+        r[g * ldo + h] = rv;
+        r[h * ldo + g] = rv;
+    }
+    if (p) {
+        p[g * ldo + h] = pv;
+        p[h * ldo + g] = pv;
+    }
+    if (n) {
+        n[g * ldo + h] = (int32_t)ni;
+        n[h * ldo + g] = (int32_t)ni;
+    }
+}
+
+// saved[s][g][h] for the ordered pair (g, h) and its mirror (h, g), whose x
+// and y sides swap
+__device__ __forceinline__ void write_saved(double* __restrict__ saved, int64_t F, int64_t g, int64_t h,
+                                            const double (&st)[NSTAT], double rv)
+{
+    const int64_t FF = F * F;
+    const double vgh[NSAVED] = {st[0], st[1], st[2], st[3], st[4], st[5], rv};
+    const double vhg[NSAVED] = {st[0], st[2], st[1], st[4], st[3], st[5], rv};
+#pragma unroll
+    for (int s = 0; s < NSAVED; ++s) {
+        saved[s * FF + g * F + h] = vgh[s];
+        saved[s * FF + h * F + g] = vhg[s];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pearson_combine(
-    const double* __restrict__ part, int T, int ntiles, int nsplit, int64_t F, double var_tol,
+    const double* __restrict__ part, int T, int ntiles, int nsplit, int64_t F,
     double* __restrict__ r, double* __restrict__ p, int32_t* __restrict__ n, int64_t ldo,
-    double* __restrict__ saved)
+    double* __restrict__ saved, uint32_t* __restrict__ redo_count, uint32_t* __restrict__ redo)
 {
     const int t = blockIdx.x / (TILE_ELEMS / 256);
     const int e = (blockIdx.x % (TILE_ELEMS / 256)) * 256 + threadIdx.x;
@@ -847,34 +764,144 @@ __global__ __launch_bounds__(256) void k_pearson_combine(
     if (ni >= 2) {
         const double vx = cn * sxx - sx * sx;
         const double vy = cn * syy - sy * sy;
-        if (vx > var_tol * cn * sxx && vy > var_tol * cn * syy) {
+        if (vx >= WELL_CENTRED * cn * sxx && vy >= WELL_CENTRED * cn * syy && vx > 0.0 && vy > 0.0) {
             const double cxy = cn * sxy - sx * sy;
             rv = cxy / sqrt(vx * vy);
             rv = rv > 1.0 ? 1.0 : (rv < -1.0 ? -1.0 : rv);
             pv = (ni == 2) ? 1.0 : corr_pvalue(rv, ni);
+        } else {
+            const uint32_t slot = atomicAdd(redo_count, 1u);
+            redo[slot] = (uint32_t)(g * F + h);
         }
     }
-    if (r) {
-        r[g * ldo + h] = rv;
-        r[h * ldo + g] = rv;
-    }
-    if (p) {
-        p[g * ldo + h] = pv;
-        p[h * ldo + g] = pv;
-    }
-    if (n) {
-        n[g * ldo + h] = (int32_t)ni;
-        n[h * ldo + g] = (int32_t)ni;
-    }
-    if (saved) {
-        const int64_t FF = F * F;
-        const double vgh[NSTAT] = {cn, sx, sy, sxx, syy, sxy};
-        const double vhg[NSTAT] = {cn, sy, sx, syy, sxx, sxy};
+    write_pair(g, h, ldo, rv, pv, ni, r, p, n);
+    if (saved) write_saved(saved, F, g, h, st, rv);
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
+
+// Recomputation of the listed pairs from the raw values in FP64, one
+// workgroup per pair: a first pass over the samples takes n, the sums of
+// both sides and their minima and maxima over I(g,h); a second pass the
+// centred sums about the pair's own means (two-pass Pearson).  Zero variance
+// is decided exactly: the minimum equals the maximum on I(g,h).  With
+// `saved`, the six sums about the column means (the centring of the
+// contractions: mu32 in float arithmetic, or mu64 in the FP64 mode) are
+// recomputed in FP64 too.
+constexpr int RC_THREADS = 256;
+
+__device__ __forceinline__ double block_sum_f64(double v, double* red)
+{
+    v = wave_sum_f64(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
 #pragma unroll
-        for (int s = 0; s < NSTAT; ++s) {
-            saved[s * FF + g * F + h] = vgh[s];
-            saved[s * FF + h * F + g] = vhg[s];
+    for (int w = 0; w < RC_THREADS / 64; ++w) t += red[w];
+    return t;
+}
+
+__global__ __launch_bounds__(RC_THREADS) void k_pearson_recompute(
+    const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+    const float* __restrict__ mu32, const double* __restrict__ mu64, int center64,
+    const uint32_t* __restrict__ redo_count, const uint32_t* __restrict__ redo,
+    double* __restrict__ r, double* __restrict__ p, int64_t ldo, double* __restrict__ saved)
+{
+    __shared__ double red[RC_THREADS / 64];
+    __shared__ float mred[4][RC_THREADS / 64];
+    const uint32_t count = *redo_count;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
+        const uint32_t code = redo[k];
+        const int64_t g = code / (uint32_t)F, h = code % (uint32_t)F;
+        // pass 1: n, sums, extremes
+        double cnt = 0.0, s1x = 0.0, s1y = 0.0;
+        float mnx = __builtin_inff(), mxx = -__builtin_inff(), mny = __builtin_inff(), mxy = -__builtin_inff();
+        for (int64_t i = threadIdx.x; i < S; i += RC_THREADS) {
+            const float x = X[i * ldx + g], y = X[i * ldx + h];
+            if (!is_missing(x, use_sent, sent) && !is_missing(y, use_sent, sent)) {
+                cnt += 1.0;
+                s1x += (double)x;
+                s1y += (double)y;
+                mnx = fminf(mnx, x);
+                mxx = fmaxf(mxx, x);
+                mny = fminf(mny, y);
+                mxy = fmaxf(mxy, y);
+            }
         }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            mnx = fminf(mnx, __shfl_xor(mnx, d, 64));
+            mxx = fmaxf(mxx, __shfl_xor(mxx, d, 64));
+            mny = fminf(mny, __shfl_xor(mny, d, 64));
+            mxy = fmaxf(mxy, __shfl_xor(mxy, d, 64));
+        }
+        if (lane == 0) {
+            mred[0][wave] = mnx;
+            mred[1][wave] = mxx;
+            mred[2][wave] = mny;
+            mred[3][wave] = mxy;
+        }
+        const double nn = block_sum_f64(cnt, red);
+        const double sumx = block_sum_f64(s1x, red);
+        const double sumy = block_sum_f64(s1y, red);
+#pragma unroll
+        for (int w = 0; w < RC_THREADS / 64; ++w) {
+            mnx = fminf(mnx, mred[0][w]);
+            mxx = fmaxf(mxx, mred[1][w]);
+            mny = fminf(mny, mred[2][w]);
+            mxy = fmaxf(mxy, mred[3][w]);
+        }
+        const double mx = sumx / nn, my = sumy / nn;
+        const float cx32 = mu32[g], cy32 = mu32[h];
+        const double cx64 = mu64[g], cy64 = mu64[h];
+        // pass 2: centred sums about the pair means (r), and about the column
+        // means (the saved sums)
+        double sdd = 0.0, see = 0.0, sde = 0.0;
+        double tx = 0.0, ty = 0.0, txx = 0.0, tyy = 0.0, txy = 0.0;
+        for (int64_t i = threadIdx.x; i < S; i += RC_THREADS) {
+            const float x = X[i * ldx + g], y = X[i * ldx + h];
+            if (!is_missing(x, use_sent, sent) && !is_missing(y, use_sent, sent)) {
+                const double d = (double)x - mx, e = (double)y - my;
+                sdd += d * d;
+                see += e * e;
+                sde += d * e;
+                if (saved) {
+                    const double u = center64 ? (double)x - cx64 : (double)(x - cx32);
+                    const double v = center64 ? (double)y - cy64 : (double)(y - cy32);
+                    tx += u;
+                    ty += v;
+                    txx += u * u;
+                    tyy += v * v;
+                    txy += u * v;
+                }
+            }
+        }
+        const double Sdd = block_sum_f64(sdd, red);
+        const double See = block_sum_f64(see, red);
+        const double Sde = block_sum_f64(sde, red);
+        double st[NSTAT] = {nn, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (saved) {
+            st[1] = block_sum_f64(tx, red);
+            st[2] = block_sum_f64(ty, red);
+            st[3] = block_sum_f64(txx, red);
+            st[4] = block_sum_f64(tyy, red);
+            st[5] = block_sum_f64(txy, red);
+        }
+        if (threadIdx.x == 0) {
+            const int64_t ni = (int64_t)(nn + 0.5);
+            double rv = __builtin_nan(""), pv = __builtin_nan("");
+            if (ni >= 2 && mnx != mxx && mny != mxy && Sdd > 0.0 && See > 0.0) {
+                rv = Sde / sqrt(Sdd * See);
+                rv = rv > 1.0 ? 1.0 : (rv < -1.0 ? -1.0 : rv);
+                pv = (ni == 2) ? 1.0 : corr_pvalue(rv, ni);
+            }
+            write_pair(g, h, ldo, rv, pv, ni, r, p, nullptr);
+            if (saved) write_saved(saved, F, g, h, st, rv);
+        }
+        __syncthreads();  // red / mred reused by the next pair
     }
 }
 
@@ -925,19 +952,27 @@ static PearsonPlan pearson_plan(int64_t S, int64_t F, int prec)
     return pl;
 }
 
-static void pearson_carve(Carver& c, int64_t S, int64_t F, int prec, ColStats& cs, double** part)
+struct PearsonWs {
+    ColStats cs;
+    double* part;          // [nsplit][6][ntiles][64 x 64] split-K partial sums
+    uint32_t* redo_count;  // pairs listed for recomputation
+    uint32_t* redo;        // [F (F + 1) / 2] their codes g F + h
+};
+
+static void pearson_carve(Carver& c, int64_t S, int64_t F, int prec, PearsonWs& w)
 {
     PearsonPlan pl = pearson_plan(S, F, prec);
-    colstats_carve(c, S, F, cs);
-    *part = c.take<double>((size_t)pl.nsplit * NSTAT * pl.ntiles * TILE_ELEMS);
+    colstats_carve(c, S, F, w.cs);
+    w.part = c.take<double>((size_t)pl.nsplit * NSTAT * pl.ntiles * TILE_ELEMS);
+    w.redo_count = c.take<uint32_t>(1);
+    w.redo = c.take<uint32_t>((size_t)(F * (F + 1) / 2));
 }
 
 size_t pearson_ws_bytes(int64_t S, int64_t F, int prec)
 {
     Carver c(nullptr);
-    ColStats cs;
-    double* part;
-    pearson_carve(c, S, F, prec, cs, &part);
+    PearsonWs w;
+    pearson_carve(c, S, F, prec, w);
     return c.bytes();
 }
 
@@ -950,9 +985,10 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
     const float sv = opt_sent(opts);
     (void)ws_bytes;
     Carver c(ws);
-    ColStats cs;
-    double* part;
-    pearson_carve(c, S, F, prec, cs, &part);
+    PearsonWs w;
+    pearson_carve(c, S, F, prec, w);
+    const ColStats& cs = w.cs;
+    double* part = w.part;
     PearsonPlan pl = pearson_plan(S, F, prec);
 
     NAPY_TRY(record_stage(ev, 0, st));
@@ -975,10 +1011,18 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
     }
     NAPY_TRY(check_launch("pearson_tiles"));
     NAPY_TRY(record_stage(ev, 2, st));
-    const double tol = (prec == NAPY_PREC_FP64) ? 1e-12 : 1e-5;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w.redo_count);
+    NAPY_TRY(check_launch("zero"));
     hipLaunchKernelGGL(k_pearson_combine, dim3((unsigned)(pl.ntiles * (TILE_ELEMS / 256))), dim3(256), 0, st,
-                       part, pl.T, pl.ntiles, pl.nsplit, F, tol, r, p, n, ldo, saved);
+                       part, pl.T, pl.ntiles, pl.nsplit, F, r, p, n, ldo, saved, w.redo_count, w.redo);
     NAPY_TRY(check_launch("pearson_combine"));
+    // a fixed grid: workgroups whose index is at least the listed count
+    // return at once
+    const int64_t npairs = F * (F + 1) / 2;
+    const unsigned nrc = (unsigned)(npairs < 1024 ? npairs : 1024);
+    hipLaunchKernelGGL(k_pearson_recompute, dim3(nrc), dim3(RC_THREADS), 0, st, X, S, F, ldx, us, sv, cs.mu32,
+                       cs.mu64, prec == NAPY_PREC_FP64 ? 1 : 0, w.redo_count, w.redo, r, p, ldo, saved);
+    NAPY_TRY(check_launch("pearson_recompute"));
     return record_stage(ev, 3, st);
 }
 

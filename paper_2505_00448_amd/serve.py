@@ -10,11 +10,14 @@ matrices back at once.  Here that becomes a request loop on one GPU:
   Section 3.5.3 reused across queries);
 * a query is (row set, variable list, method) and returns r, p and n over
   X[rows][:, cols], exactly what the full call returns on that submatrix;
-* queries are admitted in arrival order as soon as a slot (one HIP stream
-  each) is free and the query's device memory (workspace, outputs, index
-  arrays) fits in the server's arena; queries that arrive while others run
-  are admitted as slots and memory free up, so their kernels overlap on the
-  device;
+* queries are admitted as soon as a slot (one HIP stream each) is free and
+  the query's device memory (workspace, outputs, index arrays) fits in the
+  server's arena; queries that arrive while others run are admitted as
+  slots and memory free up, so their kernels overlap on the device.  The
+  oldest waiting query goes first; when its memory does not fit yet, a few
+  younger ones that do fit may go ahead of it, a bounded number of times
+  (after that it waits for memory alone), so small queries are not held up
+  by a large one and a large one is not starved;
 * every kernel of a query runs on its own slot's stream with a tiling fixed
   by the query's own shape, so a result does not depend on which other
   queries share the device at the time.
@@ -134,15 +137,21 @@ class Scheduler:
         is_done(slot) -> bool       the slot's last launch has completed
         outputs(req, slot, offset)  views of the finished outputs
 
-    and optionally validate(req) (raises on a malformed request) and
-    retire(slot, completion) (bookkeeping when a query is retired).
+    and optionally validate(req) (raises on a malformed request),
+    retire(slot, completion) (bookkeeping when a query is retired) and
+    released() (called after a retired query's callback, before its memory
+    can be handed to another query).
 
-    Requests are admitted strictly in arrival order (no overtaking, so a large
-    query cannot starve); a request is admitted once a slot is free and its
-    bytes fit in the arena."""
+    Admission: a request is admitted once a slot is free and its bytes fit in
+    the arena.  The oldest waiting request (the head) goes first.  When the
+    head's bytes do not fit, the first of the next `lookahead` requests whose
+    bytes fit is admitted ahead of it, at most `max_overtakes` times per head;
+    after that nothing overtakes it, so it is admitted as soon as memory for
+    it frees up."""
 
     def __init__(self, executor, slots: int, capacity: int,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter,
+                 lookahead: int = 8, max_overtakes: int = 16):
         if slots < 1:
             raise ValueError("slots must be >= 1")
         self.ex = executor
@@ -152,6 +161,10 @@ class Scheduler:
         self.free_slots = list(range(slots - 1, -1, -1))
         self.running = {}          # slot -> (req, offset, nbytes, t_admit)
         self.max_running = 0
+        self.lookahead = max(0, int(lookahead))
+        self.max_overtakes = max(0, int(max_overtakes))
+        self.head_overtaken = 0    # times the current head has been overtaken
+        self.overtakes = 0         # total admissions ahead of an older request
 
     def submit(self, req: Request) -> None:
         if hasattr(self.ex, "validate"):
@@ -182,22 +195,47 @@ class Scheduler:
                     comp.outputs = self.ex.outputs(req, slot, off)
                     on_done(comp)
                     comp.outputs = {}
+                    if hasattr(self.ex, "released"):
+                        self.ex.released()
                 self.arena.release(off, nb)
                 self.free_slots.append(slot)
                 retired += 1
         while self.pending and self.free_slots:
-            req = self.pending[0]
-            nb = req.nbytes if req.nbytes >= 0 else self.ex.nbytes(req)
-            off = self.arena.alloc(nb)
-            if off is None:
+            pick, off, nb = self._choose()
+            if pick is None:
                 break
-            self.pending.popleft()
+            req = self.pending[pick]
+            del self.pending[pick]
+            if pick == 0:
+                self.head_overtaken = 0
+            else:
+                self.head_overtaken += 1
+                self.overtakes += 1
             slot = self.free_slots.pop()
             t_adm = self.clock()
             self.ex.launch(req, slot, off)
             self.running[slot] = (req, off, nb, t_adm)
             self.max_running = max(self.max_running, len(self.running))
         return retired
+
+    def _nbytes(self, req: Request) -> int:
+        return req.nbytes if req.nbytes >= 0 else self.ex.nbytes(req)
+
+    def _choose(self):
+        """(index in pending, arena offset, bytes) of the request to admit
+        next, or (None, None, None)."""
+        nb = self._nbytes(self.pending[0])
+        off = self.arena.alloc(nb)
+        if off is not None:
+            return 0, off, nb
+        if self.head_overtaken >= self.max_overtakes:
+            return None, None, None
+        for k in range(1, min(len(self.pending), 1 + self.lookahead)):
+            nb = self._nbytes(self.pending[k])
+            off = self.arena.alloc(nb)
+            if off is not None:
+                return k, off, nb
+        return None, None, None
 
 
 # ---------------------------------------------------------------------------
@@ -237,6 +275,10 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(slots)]
         self.events = [None] * slots
         self.t_events = [None] * slots
+        # work the result callbacks queued on torch's current stream (device
+        # copies of a finished query's outputs) must complete before the
+        # arena memory they read is written by a later query
+        self.fence = None
         self.spans = []
         self.staging = [torch.empty(self.S + self.F + 2, dtype=torch.int32).pin_memory()
                         for _ in range(slots)]
@@ -288,11 +330,18 @@ class GpuExecutor:
         if len(cols) == 0 or cols.min() < 0 or cols.max() >= self.F or len(np.unique(cols)) != len(cols):
             raise ValueError(f"query {req.qid}: cols must be non-empty, distinct and in [0, {self.F})")
 
+    def released(self) -> None:
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.dev))
+        self.fence = ev
+
     def launch(self, req: Request, slot: int, off: int) -> None:
         torch = self.torch
         Sq, Fq = len(req.rows), len(req.cols)
         rows, cols, r, p, n, ws, ws_bytes, _ = self._layout(req, off)
         s = self.streams[slot]
+        if self.fence is not None:
+            s.wait_event(self.fence)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev0.record(s)
         stg = self.staging[slot]
@@ -368,8 +417,10 @@ class Server:
     >>> stats = srv.serve(requests, on_done=callback)   # requests carry arrival offsets
 
     Results are handed to `on_done(completion)` as device views into the
-    arena, valid only during the callback (copy what must be kept); the
-    memory is released when the callback returns."""
+    arena, valid only during the callback: copy what must be kept (a device
+    copy queued on torch's current stream is fine; later queries wait for
+    that stream's work before they reuse the memory).  The memory is released
+    when the callback returns."""
 
     def __init__(self, X, slots: int = 4, capacity: int = 4 << 30, precision: str = "bf16x3",
                  missing: Optional[float] = None, spearman: bool = True):
@@ -419,6 +470,7 @@ class Server:
         wall = time.perf_counter() - t0
         torch.cuda.synchronize(self.ex.dev)
         out = summarize(comps, wall, sched)
+        out["overtakes"] = sched.overtakes
         if self.ex.spans:
             busy = self.ex.busy_ms(ref)
             out["device_busy_ms"] = busy

@@ -18,6 +18,7 @@ from .workloads import (  # noqa: F401
     paper_shape,
     heavy_ties,
     edge_matrix,
+    mode_selected,
     pvalue_matrix,
     categorical_continuous,
     categorical_matrix,

@@ -23,6 +23,10 @@ questionnaire modules and count variables of such a cohort):
 * ``paper_shape``       uniform [0, 1) values with an exact fraction of missing
                         entries per variable, as in the paper's simulated data
                         (Section 4.1.1).
+* ``mode_selected``     bimodal columns whose partners are observed on one
+                        mode only (missingness that depends on the value), so
+                        a pair's complete samples sit many of their own sds
+                        away from the column's observed mean.
 """
 
 from __future__ import annotations
@@ -192,6 +196,30 @@ def heavy_ties(S: int, F: int, levels: int = 5, missing: float = 0.2,
     X = np.clip(X, 0, levels - 1)
     _mcar(rng, X, missing)
     return X.astype(np.float32)
+
+
+def mode_selected(S: int = 2_000, mode_sds=(0.1, 0.01, 0.001), seed: int = SEED_BASE + 15) -> np.ndarray:
+    """For each mode sd s: a bimodal column A (modes at -1 and +1, sd s
+    around each, half the samples in each), a partner B observed only where A
+    is in its upper mode (B = A's deviation there plus independent noise of
+    the same size, so r(A, B) is about 0.7), and a partner C observed on
+    A's upper mode too but constant there (so C is constant on I(A, C) and
+    on I(B, C)); 10% MCAR on top.  Two complete standard normal columns close
+    the matrix.  Columns: A_s, B_s, C_s for each s, then the two normals."""
+    rng = _rng(seed)
+    cols = []
+    for sd in mode_sds:
+        upper = rng.random(S) < 0.5
+        dev = rng.standard_normal(S) * sd
+        a = np.where(upper, 1.0, -1.0) + dev
+        b = np.where(upper, dev + rng.standard_normal(S) * sd, np.nan)
+        c = np.where(upper, 5.0, np.nan)
+        for col in (a, b, c):
+            col[rng.random(S) < 0.10] = np.nan
+            cols.append(col)
+    cols.append(rng.standard_normal(S))
+    cols.append(rng.standard_normal(S))
+    return np.column_stack(cols).astype(np.float32)
 
 
 def edge_matrix() -> np.ndarray:

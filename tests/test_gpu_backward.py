@@ -58,12 +58,32 @@ def test_backward_small(gpu_device, precision):
     assert err <= 1e-4, err
 
 
-def test_backward_full_size(gpu_device):
+def test_backward_mode_selected(gpu_device):
+    """Pairs whose complete samples sit 10 and 100 of their own sds from the
+    column mean (the forward recomputes them in FP64, and the backward takes
+    their saved sums and r from there), and partners constant on the pair
+    (undefined r: no gradient)."""
+    X = synth.mode_selected(S=900, mode_sds=(0.1, 0.01))
+    F = X.shape[1]
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((F, F))
+    W = np.triu(W) + np.triu(W, 1).T
+    _, ref, _ = ograd.pearson_loss_grad(X.astype(np.float64), W)
+    for precision in ("fp32", "bf16x3", "fp64"):
+        g = _gpu_grad(X, W, gpu_device, precision)
+        assert np.all(g[np.isnan(X)] == 0.0)
+        err = np.abs(g - ref).max() / np.abs(ref).max()
+        assert err <= 1e-4, (precision, err)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_backward_full_size(gpu_device, precision):
     case = synth.cfg_differentiation()
     X = case.X
     W = case.W
+    print(f"[backward full size] {precision}", flush=True)
     _, ref, _ = ograd.pearson_loss_grad(X.astype(np.float64), W)
-    g = _gpu_grad(X, W, gpu_device, "fp32")
+    g = _gpu_grad(X, W, gpu_device, precision)
     miss = np.isnan(X)
     assert np.all(g[miss] == 0.0)
     for (i, c) in case.nan_entries:

@@ -91,6 +91,38 @@ def test_serving_alone_vs_mix_bit_identical(gpu_device):
         assert_p_close(got["p"], po, ro, no, max(worst, 1e-15), where)
 
 
+def test_serving_device_copies_in_callback(gpu_device):
+    """A callback that keeps its results as device copies queued on torch's
+    current stream (no host wait): the arena memory is reused by later
+    queries only after those copies, so every kept result still equals the
+    result of the query run alone."""
+    import torch
+    from paper_2505_00448_amd.serve import Server
+    S, F = 3000, 240
+    X = synth.cfg_serving_base(S=S, F=F)
+    Xd = torch.from_numpy(X).to(gpu_device)
+    reqs = _requests(S, F, 24, seed=303)
+    alone = {}
+    srv1 = Server(Xd, slots=1, capacity=512 << 20)
+    for q in reqs:
+        srv1.serve([q], on_done=_grab(alone), realtime=False)
+    big = max(srv1.ex.nbytes(q) for q in reqs)
+    kept = {}
+
+    def keep(c):
+        kept[c.qid] = {k: v.clone() for k, v in c.outputs.items()}
+
+    srv = Server(Xd, slots=4, capacity=int(2.5 * big))
+    stats = srv.serve(reqs, on_done=keep, realtime=False)
+    torch.cuda.synchronize(gpu_device)
+    assert stats["queries"] == len(reqs)
+    for q in reqs:
+        for k in ("r", "p", "n"):
+            a = alone[q.qid][k]
+            b = kept[q.qid][k].cpu().numpy()
+            assert np.array_equal(_bits(a), _bits(b)), (q.qid, q.method, k)
+
+
 def test_serving_realtime_stream(gpu_device):
     """Real-time replay of a short Poisson stream: every query completes,
     latencies are positive and queries overlap on the device."""

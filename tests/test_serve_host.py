@@ -81,7 +81,7 @@ def test_scheduler_admits_by_slots_and_memory_in_order():
     sizes = {0: 3000, 1: 3000, 2: 5000, 3: 100, 4: 100}
     ex = FakeExecutor(sizes)
     t = [0.0]
-    sch = Scheduler(ex, slots=2, capacity=8192, clock=lambda: t[0])
+    sch = Scheduler(ex, slots=2, capacity=8192, clock=lambda: t[0], max_overtakes=0)
     for i in range(5):
         sch.submit(_req(i))
     sch.step()
@@ -91,7 +91,8 @@ def test_scheduler_admits_by_slots_and_memory_in_order():
     sch.step(done.append)
     assert [c.qid for c in done] == [0]
     # query 2 (5000 B) does not fit beside query 1 (3072 B) in 8192 B:
-    # it waits, and the small queries behind it do not overtake it
+    # it waits, and with overtaking switched off the small queries behind it
+    # wait too
     assert [q for q, _, _ in ex.launched] == [0, 1]
     ex.finished.add(1)
     sch.step(done.append)
@@ -105,6 +106,45 @@ def test_scheduler_admits_by_slots_and_memory_in_order():
     assert sch.idle()
     assert sorted(c.qid for c in done) == [0, 1, 2, 3, 4]
     assert sch.arena.used == 0
+
+
+def test_scheduler_bounded_overtaking():
+    """When the head's memory does not fit, younger queries that fit go
+    ahead of it, at most max_overtakes times; then the head is admitted
+    first as soon as its memory frees up."""
+    sizes = {0: 6000, 1: 6000, 2: 100, 3: 100, 4: 100, 5: 100}
+    ex = FakeExecutor(sizes)
+    sch = Scheduler(ex, slots=4, capacity=8192, max_overtakes=2)
+    for i in range(6):
+        sch.submit(_req(i))
+    sch.step()
+    # 0 runs; 1 does not fit beside it; 2 and 3 overtake it (the bound)
+    assert [q for q, _, _ in ex.launched] == [0, 2, 3]
+    assert sch.overtakes == 2
+    ex.finished.update({2, 3})
+    done = []
+    sch.step(done.append)
+    # slots are free but 1 still does not fit and may not be overtaken again
+    assert [q for q, _, _ in ex.launched] == [0, 2, 3]
+    ex.finished.add(0)
+    sch.step(done.append)
+    # 1 first, then the rest in order (they fit beside it)
+    assert [q for q, _, _ in ex.launched] == [0, 2, 3, 1, 4, 5]
+    ex.finished.update({1, 4, 5})
+    sch.step(done.append)
+    assert sch.idle() and sch.arena.used == 0
+
+
+def test_scheduler_calls_released_after_callback():
+    ex = FakeExecutor({0: 100})
+    order = []
+    ex.released = lambda: order.append("released")
+    sch = Scheduler(ex, slots=1, capacity=1 << 20)
+    sch.submit(_req(0))
+    sch.step()
+    ex.finished.add(0)
+    sch.step(lambda c: order.append("callback"))
+    assert order == ["callback", "released"]
 
 
 def test_scheduler_admits_while_others_run():
