@@ -18,7 +18,8 @@
  *   - Every data pointer is a DEVICE pointer (hipMalloc'd or a PyTorch CUDA
  *     tensor's data) unless the comment says host.  The caller owns every
  *     buffer and the stream; the library never allocates device or host
- *     memory and keeps no state between calls.
+ *     memory and keeps no state between calls (napy_pearson_noalloc's fixed
+ *     scratch array, loaded with the library, is the one exception).
  *   - Input X is samples x variables, row-major, float32: element (i, c) at
  *     X[i * ldx + c], ldx >= F.  NaN marks a missing value; with
  *     opts->use_sentinel != 0 a value equal to opts->sentinel is missing too.
@@ -103,6 +104,26 @@ size_t napy_pearson_workspace(int64_t S, int64_t F, const napy_opts* opts);
 int napy_pearson(const float* X, int64_t S, int64_t F, int64_t ldx,
                  double* r, double* p, int32_t* n, int64_t ldo,
                  void* ws, size_t ws_bytes, const napy_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free Pearson, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): napy_pearson without a workspace argument.  Its scratch
+ * memory is a fixed array of 128 MiB inside the library, one per device the
+ * library runs on, held until the process ends; the call allocates nothing
+ * (no hipMalloc/hipFree or allocating library routine).  The caller still
+ * passes X and the outputs.  Results meet the same bars as napy_pearson's
+ * (the split of the samples, and so the order of the FP64 partial sums, may
+ * differ when the default split needs more than the array).  Shapes whose
+ * scratch need exceeds 128 MiB even unsplit return NAPY_E_UNSUPPORTED, with
+ * the sizes in napy_last_error() (about F <= 2,000 variables).  Every call on
+ * one device uses that device's array: calls that overlap in time on the same
+ * device (different streams or host threads) race and give undefined results;
+ * calls that follow each other in stream order are fine.
+ * ------------------------------------------------------------------------ */
+int napy_pearson_noalloc(const float* X, int64_t S, int64_t F, int64_t ldx,
+                         double* r, double* p, int32_t* n, int64_t ldo,
+                         const napy_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
  * Spearman (Sections 3.2, 3.5.3).  Each variable's observed values are sorted

@@ -24,7 +24,7 @@ PREC = {"fp32": 0, "bf16x3": 1, "fp64": 2}
 # Every symbol declared in include/napy.h.
 EXPORTS = [
     "napy_strerror", "napy_last_error", "napy_version",
-    "napy_pearson_workspace", "napy_pearson",
+    "napy_pearson_workspace", "napy_pearson", "napy_pearson_noalloc",
     "napy_spearman_workspace", "napy_spearman",
     "napy_pearson_profiled", "napy_spearman_profiled",
     "napy_pearson_fwd", "napy_pearson_backward_workspace", "napy_pearson_backward",
@@ -72,6 +72,7 @@ def load() -> ctypes.CDLL:
         "napy_version": (ctypes.c_char_p, []),
         "napy_pearson_workspace": (sz, [i64, i64, O]),
         "napy_pearson": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P]),
+        "napy_pearson_noalloc": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, O, P]),
         "napy_spearman_workspace": (sz, [i64, i64, O]),
         "napy_spearman": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P]),
         "napy_pearson_profiled": (ctypes.c_int, [P, i64, i64, i64, P, P, P, i64, P, sz, O, P, P]),

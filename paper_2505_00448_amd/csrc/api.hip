@@ -129,6 +129,16 @@ int napy_pearson(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, d
     return pearson_run(X, S, F, ldx, r, p, n, ldo, nullptr, ws, ws_bytes, opts, (hipStream_t)stream);
 }
 
+int napy_pearson_noalloc(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                         int64_t ldo, const napy_opts* opts, void* stream)
+{
+    if (!opts_ok(opts)) return NAPY_E_INVALID;
+    NAPY_TRY(check_shape(S, F));
+    if (!X && S > 0) return NAPY_E_INVALID;
+    if (ldx < F || ldo < F) return NAPY_E_INVALID;
+    return pearson_noalloc_run(X, S, F, ldx, r, p, n, ldo, opts, (hipStream_t)stream);
+}
+
 int napy_pearson_fwd(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
                      int64_t ldo, double* saved, void* ws, size_t ws_bytes, const napy_opts* opts,
                      void* stream)

@@ -163,6 +163,11 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
                 int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
                 const napy_opts* opts, hipStream_t st, void* const* ev = nullptr);
 
+// Pearson with its workspace in a fixed per-device array of the library (no
+// allocation by anyone); NAPY_E_UNSUPPORTED when (S, F) needs more.
+int pearson_noalloc_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                        int64_t ldo, const napy_opts* opts, hipStream_t st);
+
 inline int record_stage(void* const* ev, int i, hipStream_t st)
 {
     if (!ev || !ev[i]) return NAPY_OK;

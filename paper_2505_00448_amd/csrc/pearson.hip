@@ -39,6 +39,7 @@
 //           bits) perturbs r by more than 1e-6 on short or adversarial
 //           columns, so the third piece is kept.
 //   FP64    v_mfma_f64_16x16x4_f64 (validation mode).
+#include <mutex>
 #include <type_traits>
 
 #include "napy_internal.hpp"
@@ -959,37 +960,39 @@ struct PearsonWs {
     uint32_t* redo;        // [F (F + 1) / 2] their codes g F + h
 };
 
-static void pearson_carve(Carver& c, int64_t S, int64_t F, int prec, PearsonWs& w)
+static void pearson_carve(Carver& c, int64_t S, int64_t F, const PearsonPlan& pl, PearsonWs& w)
 {
-    PearsonPlan pl = pearson_plan(S, F, prec);
     colstats_carve(c, S, F, w.cs);
     w.part = c.take<double>((size_t)pl.nsplit * NSTAT * pl.ntiles * TILE_ELEMS);
     w.redo_count = c.take<uint32_t>(1);
     w.redo = c.take<uint32_t>((size_t)(F * (F + 1) / 2));
 }
 
-size_t pearson_ws_bytes(int64_t S, int64_t F, int prec)
+static size_t plan_bytes(int64_t S, int64_t F, const PearsonPlan& pl)
 {
     Carver c(nullptr);
     PearsonWs w;
-    pearson_carve(c, S, F, prec, w);
+    pearson_carve(c, S, F, pl, w);
     return c.bytes();
 }
 
-int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
-                int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
-                const napy_opts* opts, hipStream_t st, void* const* ev)
+size_t pearson_ws_bytes(int64_t S, int64_t F, int prec)
+{
+    return plan_bytes(S, F, pearson_plan(S, F, prec));
+}
+
+static int pearson_run_plan(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
+                            int32_t* n, int64_t ldo, double* saved, void* ws, const PearsonPlan& pl,
+                            const napy_opts* opts, hipStream_t st, void* const* ev)
 {
     const int prec = opt_prec(opts);
     const int us = opt_use_sent(opts);
     const float sv = opt_sent(opts);
-    (void)ws_bytes;
     Carver c(ws);
     PearsonWs w;
-    pearson_carve(c, S, F, prec, w);
+    pearson_carve(c, S, F, pl, w);
     const ColStats& cs = w.cs;
     double* part = w.part;
-    PearsonPlan pl = pearson_plan(S, F, prec);
 
     NAPY_TRY(record_stage(ev, 0, st));
     NAPY_TRY(colstats_launch(X, S, F, ldx, us, sv, cs, st));
@@ -1024,6 +1027,82 @@ int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, do
                        cs.mu64, prec == NAPY_PREC_FP64 ? 1 : 0, w.redo_count, w.redo, r, p, ldo, saved);
     NAPY_TRY(check_launch("pearson_recompute"));
     return record_stage(ev, 3, st);
+}
+
+int pearson_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p,
+                int32_t* n, int64_t ldo, double* saved, void* ws, size_t ws_bytes,
+                const napy_opts* opts, hipStream_t st, void* const* ev)
+{
+    (void)ws_bytes;
+    return pearson_run_plan(X, S, F, ldx, r, p, n, ldo, saved, ws, pearson_plan(S, F, opt_prec(opts)), opts, st,
+                            ev);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free Pearson: the workspace is a fixed device array
+// ---------------------------------------------------------------------------
+// Each device that loads the library holds its own copy of `scratch` until
+// the process ends.  Host code never passes the array's name to a kernel (in
+// host code it is a host-side stand-in): the device address is looked up
+// once per device with hipGetSymbolAddress and kept in scratch_dev.
+constexpr size_t PEARSON_NOALLOC_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[PEARSON_NOALLOC_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+static int scratch_address(void** out)
+{
+    int dev = 0;
+    NAPY_TRY(hip_status(hipGetDevice(&dev), "hipGetDevice"));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+        set_last_error("device %d: the allocation-free entry point supports devices 0..%d", dev,
+                       SCRATCH_MAX_DEVICES - 1);
+        return NAPY_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* ptr = nullptr;
+        NAPY_TRY(hip_status(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+        if (!ptr || ((uintptr_t)ptr & 255)) {
+            set_last_error("scratch array of device %d has no usable address", dev);
+            return NAPY_E_HIP;
+        }
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return NAPY_OK;
+}
+
+// The default plan when its workspace fits the array, else the same plan with
+// fewer sample splits (the split count only changes the order of the FP64
+// partial additions).
+static PearsonPlan noalloc_plan(int64_t S, int64_t F, int prec)
+{
+    PearsonPlan pl = pearson_plan(S, F, prec);
+    const int64_t BK = (prec == NAPY_PREC_BF16X3) ? bf3::BK : (prec == NAPY_PREC_FP64 ? 16 : 32);
+    while (plan_bytes(S, F, pl) > PEARSON_NOALLOC_BYTES && pl.nsplit > 1) {
+        pl.ksplit = round_up(ceil_div(S, (int64_t)pl.nsplit - 1), BK);
+        pl.nsplit = (int)ceil_div(S, pl.ksplit);
+        if (pl.nsplit < 1) pl.nsplit = 1;
+    }
+    return pl;
+}
+
+int pearson_noalloc_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, double* p, int32_t* n,
+                        int64_t ldo, const napy_opts* opts, hipStream_t st)
+{
+    const PearsonPlan pl = noalloc_plan(S, F, opt_prec(opts));
+    const size_t need = plan_bytes(S, F, pl);
+    if (need > PEARSON_NOALLOC_BYTES) {
+        set_last_error("S=%lld F=%lld needs %zu bytes of scratch; the allocation-free Pearson holds %zu",
+                       (long long)S, (long long)F, need, (size_t)PEARSON_NOALLOC_BYTES);
+        return NAPY_E_UNSUPPORTED;
+    }
+    void* ws = nullptr;
+    NAPY_TRY(scratch_address(&ws));
+    return pearson_run_plan(X, S, F, ldx, r, p, n, ldo, nullptr, ws, pl, opts, st, nullptr);
 }
 
 }  // namespace napy
