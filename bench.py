@@ -278,6 +278,10 @@ def main() -> int:
     def step_two(i, ev=True):
         pearson_call(opt_main, out["pearson"], evp2_a[i] if ev else None, sh_p2)
         spearman_call(out["spearman"], evs2_a[i] if ev else None, sh_s2)
+        # join: the next step starts on both streams after both calls of
+        # this one (steps do not run ahead of each other)
+        st_p.wait_stream(st_s)
+        st_s.wait_stream(st_p)
 
     def timed(step_fn):
         torch.cuda.synchronize()  # the input is on the device before any stream reads it
