@@ -994,26 +994,68 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
 // (v_writelane_b32).  Declared through the intrinsic so that the compiler
 // sees the instruction and inserts the wait states after the VALU write of
 // the scalar register it reads.
-extern "C" __device__ int napy_amdgcn_writelane(int v, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
-
-template <int LANE>
-__device__ __forceinline__ uint32_t write_lane(uint32_t old, uint32_t v)
+// 8 x 8 bit transpose of a 64-bit block held as (lo, hi): bit 8 t + j (byte
+// t, bit j) moves to bit 8 j + t, by three rounds of masked delta swaps
+// (distances 7, 14 and 28 bits)
+__device__ __forceinline__ void bit_transpose8(uint32_t& lo, uint32_t& hi)
 {
-    return (uint32_t)napy_amdgcn_writelane((int)v, LANE, (int)old);
+    uint32_t t;
+    t = ((lo >> 7) ^ lo) & 0x00AA00AAu;
+    lo ^= t ^ (t << 7);
+    t = ((hi >> 7) ^ hi) & 0x00AA00AAu;
+    hi ^= t ^ (t << 7);
+    t = ((lo >> 14) ^ lo) & 0x0000CCCCu;
+    lo ^= t ^ (t << 14);
+    t = ((hi >> 14) ^ hi) & 0x0000CCCCu;
+    hi ^= t ^ (t << 14);
+    t = ((hi << 4) ^ lo) & 0xF0F0F0F0u;
+    lo ^= t;
+    hi ^= t >> 4;
 }
 
-// lanes 2j and 2j + 1 of the result get the low and high halves of the
-// ballot of bit j of w, for j = J .. N - 1
-template <int J, int N>
-__device__ __forceinline__ uint32_t pack_ballots(uint32_t out, uint32_t w)
+// Presence of the block's 8 partners at a's sorted positions k0 .. k0 + 31
+// (k0 = 32 w), as one 32-bit word per partner: bit t of x[j] = partner j
+// present at position k0 + t.  Each position's presence byte (bit j =
+// partner j) is gathered from LDS; four 8 x 8 bit transposes give 8 bits per
+// partner and 8 positions, and two 4 x 4 byte transposes (byte permutes)
+// assemble each partner's word.  The debug form takes the single partner's
+// presence (bit 0) from its positions in global memory.
+template <bool DBG>
+__device__ __forceinline__ void presence_words(const uint16_t* __restrict__ ordw, const uint8_t* presL,
+                                               const uint16_t* __restrict__ posDbg, int k0, int na, uint32_t x[8])
 {
-    if constexpr (J == N) {
-        return out;
-    } else {
-        const uint64_t m = __ballot((w >> J) & 1u);
-        out = write_lane<2 * J>(out, (uint32_t)m);
-        out = write_lane<2 * J + 1>(out, (uint32_t)(m >> 32));
-        return pack_ballots<J + 1, N>(out, w);
+    uint32_t blk[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 iv = ((const uint4*)ordw)[q];
+        const uint32_t iw[4] = {iv.x, iv.y, iv.z, iv.w};
+        uint32_t by[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const uint32_t idx = (iw[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+            if constexpr (DBG)
+                by[t] = (k0 + 8 * q + t < na) ? (uint32_t)(posDbg[idx] != 0xFFFF) : 0u;
+            else
+                by[t] = presL[idx];
+        }
+        uint32_t lo = by[0] | (by[1] << 8) | (by[2] << 16) | (by[3] << 24);
+        uint32_t hi = by[4] | (by[5] << 8) | (by[6] << 16) | (by[7] << 24);
+        bit_transpose8(lo, hi);
+        blk[q][0] = lo;
+        blk[q][1] = hi;
+    }
+    // v_perm: selector byte values 0-3 pick bytes of the second operand, 4-7
+    // of the first
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t u0 = __builtin_amdgcn_perm(blk[1][h], blk[0][h], 0x05010400u);
+        const uint32_t u1 = __builtin_amdgcn_perm(blk[1][h], blk[0][h], 0x07030602u);
+        const uint32_t v0 = __builtin_amdgcn_perm(blk[3][h], blk[2][h], 0x05010400u);
+        const uint32_t v1 = __builtin_amdgcn_perm(blk[3][h], blk[2][h], 0x07030602u);
+        x[4 * h + 0] = __builtin_amdgcn_perm(v0, u0, 0x05040100u);
+        x[4 * h + 1] = __builtin_amdgcn_perm(v0, u0, 0x07060302u);
+        x[4 * h + 2] = __builtin_amdgcn_perm(v1, u1, 0x05040100u);
+        x[4 * h + 3] = __builtin_amdgcn_perm(v1, u1, 0x07060302u);
     }
 }
 
@@ -1150,7 +1192,6 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const bool grouped = nsg >= 0;  // implies rtab (runs + untied positions <= RUN_TABLE_MAX)
     const uint16_t* sgA = bs.sing + a * RUN_GROUPS_MAX;
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
-    const int nc64 = (NW + 1) >> 1;
     // the partner block's presence bytes go where a's positions will be
     // (they are needed only while the tables are built); lane-wise gathers
     // from LDS instead of global memory
@@ -1161,35 +1202,59 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     __syncthreads();
 
     // ---- step 1: partner tables along a's order, PB partners at once --------
-    // Positions p < 64 * nc64 stay inside a's padded order (nc64 * 64 <=
-    // round_up(na + 1, 64) <= ld) and positions from na on hold the sentinel
-    // S, whose presence byte is zero: no guard on the loads.  Partner j's
-    // 64 bits for a chunk are one ballot; lanes 2j and 2j + 1 take its halves
-    // and lanes 0..15 store the chunk's 16 table words at once.
+    // Thread t builds table word w = t (+ PAIR_THREADS per pass) of all PB
+    // partners: the masks from presence_words, the counts y by a block scan
+    // of the masks' popcounts (two partners' counts per 32-bit value, each
+    // half at most na < 2^16).  Positions below 32 NW <= round_up(na + 1, 64) <= ld stay
+    // inside a's padded order, and positions from na on hold the sentinel S,
+    // whose presence byte is zero; lanes past NW read word NW - 1 and store
+    // nothing.  The run-rank table's space holds the per-wave scan totals.
     const uint16_t* posDbg = bs.pos + (int64_t)po.dbg_b * ld;
-    const int jw = lane >> 1, hw = lane & 1;
-    uint32_t* tword = (uint32_t*)(tab + (size_t)(jw < PB ? jw : 0) * L.nwp + hw);
-    constexpr int Q = 16;  // chunks per wave in flight
-    for (int cq = wave; cq < nc64; cq += PAIR_WAVES * Q) {
-        uint32_t idx[Q], word[Q];
+    uint32_t* wtot = rrun;  // [PAIR_WAVES][4]
+    uint32_t carry[4] = {0u, 0u, 0u, 0u};
+    for (int w0 = 0; w0 < NW; w0 += PAIR_THREADS) {
+        const int w = w0 + (int)threadIdx.x;
+        const bool valid = w < NW;
+        uint32_t x[8] = {};
+        if (w0 + wave * 64 < NW) {  // wave-uniform
+            const int wl = valid ? w : NW - 1;
+            presence_words<DBG>(ordA + 32 * wl, presL, posDbg, 32 * wl, na, x);
+            if (!valid) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) idx[q] = (ordA + (cq + q * PAIR_WAVES) * 64)[lane];  // wave-uniform base
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            if constexpr (DBG)  // the single partner's presence, from its positions
-                word[q] = ((cq + q * PAIR_WAVES) * 64 + lane < na) ? (uint32_t)(posDbg[idx[q]] != 0xFFFF) : 0u;
-            else
-                word[q] = presL[idx[q]];
+                for (int j = 0; j < 8; ++j) x[j] = 0u;
+            }
         }
+        uint32_t pc[4], incl[4];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int c = cq + q * PAIR_WAVES;
-            if (c >= nc64) break;
-            const uint32_t out = pack_ballots<0, PB>(0u, word[q]);
-            if (lane < 2 * PB && 2 * c + hw < NW) tword[4 * c] = out;
+        for (int h = 0; h < 4; ++h) {
+            pc[h] = (uint32_t)__popc(x[2 * h]) | ((uint32_t)__popc(x[2 * h + 1]) << 16);
+            incl[h] = wave_incl_scan_u32(pc[h]);
         }
+        if (lane == 63) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) wtot[wave * 4 + h] = incl[h];
+        }
+        __syncthreads();
+        uint32_t base[4] = {carry[0], carry[1], carry[2], carry[3]};
+#pragma unroll
+        for (int v = 0; v < PAIR_WAVES; ++v) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const uint32_t tv = wtot[v * 4 + h];
+                if (v < wave) base[h] += tv;
+                carry[h] += tv;
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const uint32_t ex = base[j >> 1] + incl[j >> 1] - pc[j >> 1];
+                tab[(size_t)j * L.nwp + w] = make_uint2(x[j], 1u + ((ex >> (16 * (j & 1))) & 0xFFFFu));
+            }
+        }
+        __syncthreads();  // wtot is rewritten by the next pass
     }
-    __syncthreads();
+    if (threadIdx.x < PB) tab[(size_t)threadIdx.x * L.nwp + NW] = make_uint2(0u, 0u);
     // a's positions 0..S (S is the dummy) over the presence bytes, with the
     // missing code of a's class: untied, min(v, XS) turns 0xFFFF into XS;
     // grouped, min(v & POS_MASK, RUN_TABLE_MAX) turns a tied sample's flagged
@@ -1199,18 +1264,6 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const uint32_t miss = grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS;
     copy_pos_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8),
                     grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS);
-    for (int j = wave; j < PB; j += PAIR_WAVES) {
-        uint2* tj = tab + (size_t)j * L.nwp;
-        uint32_t run = 1;
-        for (int w0 = 0; w0 < NW; w0 += 64) {
-            const int w = w0 + lane;
-            const uint32_t v = (w < NW) ? (uint32_t)__popc(tj[w].x) : 0u;
-            const uint32_t incl = wave_incl_scan_u32(v);
-            if (w < NW) tj[w].y = run + incl - v;
-            run += __shfl(incl, 63, 64);
-        }
-        if (lane == 0) tj[NW] = make_uint2(0u, 0u);
-    }
     __syncthreads();
     if (tA) {
         // per tie run [s, e) of a and partner: C(e) - C(s) complete samples
