@@ -83,31 +83,21 @@ __global__ __launch_bounds__(256) void k_sort_keys(const float* __restrict__ X, 
 // ---------------------------------------------------------------------------
 // per-column sort
 // ---------------------------------------------------------------------------
-// LDS of the column sort, sized by the samples per thread E.  The keys and
-// sample indices of CS_THREADS * E slots share their space with the digit
-// counters of a pass: cnt[k][t] holds thread t's counts of digits 2k (low 16
-// bits) and 2k + 1 (high 16 bits).  Then the per-wave digit totals and the
-// small scan arrays.
+// LDS of the column sort for E keys per thread: the keys and sample indices
+// of CS_THREADS * E slots, each wave's 256 digit counters (16-bit), and the
+// per-wave values of the block scans.
 struct SortSmem {
-    uint32_t* key;
-    uint16_t* idx;
-    uint32_t* cnt;        // [8][CS_THREADS], over key/idx
-    uint32_t (*wtot)[8];  // [CS_WAVES][8] per-wave totals, then per-wave bases
-    int32_t* red;         // [CS_WAVES]
-    uint32_t* pbase;      // [8] packed digit bases
+    uint32_t* key;    // [CS_THREADS * E]
+    uint16_t* idx;    // [CS_THREADS * E]
+    uint16_t* wcnt;   // [CS_WAVES][256]
+    uint32_t* red;    // [4][CS_WAVES]
 };
-
-__host__ __device__ inline size_t sort_union_bytes(int E)
-{
-    const size_t cap = (size_t)CS_THREADS * (size_t)E;
-    const size_t kv = (size_t)round_up((int64_t)(cap * 6), 16);
-    const size_t cn = (size_t)8 * CS_THREADS * 4;
-    return kv > cn ? kv : cn;
-}
 
 __host__ __device__ inline size_t sort_smem_bytes(int E)
 {
-    return sort_union_bytes(E) + (size_t)CS_WAVES * 8 * 4 + (size_t)CS_WAVES * 4 + 8 * 4;
+    const size_t cap = (size_t)CS_THREADS * (size_t)E;
+    return (size_t)round_up((int64_t)(cap * 4), 16) + (size_t)round_up((int64_t)(cap * 2), 16) +
+           (size_t)CS_WAVES * 256 * 2 + 4 * CS_WAVES * 4;
 }
 
 __device__ inline SortSmem sort_smem(unsigned char* raw, int E)
@@ -115,269 +105,301 @@ __device__ inline SortSmem sort_smem(unsigned char* raw, int E)
     const size_t cap = (size_t)CS_THREADS * (size_t)E;
     SortSmem m;
     m.key = (uint32_t*)raw;
-    m.idx = (uint16_t*)(raw + cap * 4);
-    m.cnt = (uint32_t*)raw;
-    unsigned char* p = raw + sort_union_bytes(E);
-    m.wtot = (uint32_t(*)[8])p;
-    m.red = (int32_t*)(p + (size_t)CS_WAVES * 8 * 4);
-    m.pbase = (uint32_t*)(p + (size_t)CS_WAVES * 8 * 4 + (size_t)CS_WAVES * 4);
+    unsigned char* p = raw + round_up((int64_t)(cap * 4), 16);
+    m.idx = (uint16_t*)p;
+    p += round_up((int64_t)(cap * 2), 16);
+    m.wcnt = (uint16_t*)p;
+    m.red = (uint32_t*)(p + CS_WAVES * 256 * 2);
     return m;
 }
 
-// One column per workgroup: an LSD radix sort of the keys (8 stable passes of
-// 4-bit digits) with the sample indices as payload, then the tie runs.
-// Thread t holds positions t*E .. t*E+E-1 of the current order (slots past S
-// hold the "missing" key and sort last).  A pass: each thread counts its
-// digits in its own LDS counters (the returned old count is the element's
-// rank among the thread's earlier elements of that digit), the counters are
-// scanned in (digit, thread) order (a wave scan per counter word, the
-// per-wave totals and digit bases by one wave), and each element moves to
-// digit base + count of its digit in earlier threads + its rank.
+// lanes whose 8-bit digit equals this lane's: the complement of the lanes
+// that differ in some bit, where lanes differing in bit b are the ballot of
+// bit b XOR (this lane's bit b, spread over all 32 bits)
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d)
+{
+    uint32_t nlo = 0u, nhi = 0u;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);  // 0 or all ones
+        const uint64_t bl = __ballot(sb != 0u);
+        nlo |= (uint32_t)bl ^ sb;
+        nhi |= (uint32_t)(bl >> 32) ^ sb;
+    }
+    return ((uint64_t)~nhi << 32) | (uint64_t)~nlo;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// inclusive max-scan over the 64 lanes (values >= 0)
+__device__ __forceinline__ int wave_incl_max_scan(int x)
+{
+    constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 1, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 2, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 4, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 8, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, ROW_BCAST15, 0xA, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, ROW_BCAST31, 0xC, 0xF, false));
+    return x;
+}
+
+// One column per workgroup.  The observed keys (sample index as payload) are
+// compacted, then sorted by an LSD radix sort in LDS: 4 stable passes of
+// 8-bit digits.  Wave w holds sorted slots w 64 E' .. (w + 1) 64 E' - 1,
+// lane l at step e slot w 64 E' + 64 e + l (E' = observed keys per thread,
+// rounded up), so within a wave the slots run in (step, lane) order.  A
+// pass ranks each step's keys among the wave's equal digits (lanes matched
+// on the digit by ballots; a 16-bit counter per digit and wave carries the
+// count across steps), scans the 256 x 16 counters in (digit, wave) order
+// into destinations, scatters the keys in LDS and reloads them.  The tail
+// derives tie runs from the sorted keys: ord, pos, runs, the tie-run list,
+// tie bits and counts.
 template <int EPT>
-__global__ __launch_bounds__(CS_THREADS) void k_colsort(const uint32_t* __restrict__ keys, int64_t S,
+__global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const uint32_t* __restrict__ keys, int64_t S,
                                                           int64_t ld, SpearBase out)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char sort_raw[];
+    constexpr int E = EPT;
     const int col = blockIdx.x;
     const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    constexpr int E = EPT;
     const SortSmem sm = sort_smem(sort_raw, E);
     const uint32_t* kc = keys + (int64_t)col * ld;
-
-    uint32_t key[EPT];
-    uint32_t pk[EPT];  // sample index (low 16 bits) | rank or destination (high 16 bits)
-    int present = 0;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int64_t j = (int64_t)e * CS_THREADS + t;  // striped load, coalesced
-        key[e] = j < S ? kc[j] : 0xFFFFFFFFu;
-        pk[e] = (uint32_t)(j < S ? j : 0xFFFF);
-        present += key[e] != 0xFFFFFFFFu;
-    }
-    // n_c
-    {
-        int v = present;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-        if (lane == 0) sm.red[wave] = v;
-    }
-    __syncthreads();
-    const int ncount = __builtin_amdgcn_readlane(
-        (int)wave_incl_scan_u32(lane < CS_WAVES ? (uint32_t)sm.red[lane] : 0u), CS_WAVES - 1);
-
-    // The initial order is arbitrary (order among equal keys does not affect
-    // average ranks); each pass below is stable with respect to the blocked
-    // order.
-    uint32_t* const mycnt = sm.cnt + t;  // word k at mycnt[k * CS_THREADS]
-    // Register pressure: the empty volatile asm statements below keep the
-    // compiler from hoisting per-element LDS addresses out of the pass loop
-    // and from keeping per-element temporaries alive across the barriers.
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 4 * pass;
-        uint32_t tb = (uint32_t)t * E;  // first blocked slot of the thread
-        asm volatile("" : "+v"(tb));
-        // own counters: private to the thread until the scan
-#pragma unroll
-        for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = 0u;
-        {
-            // all increments issued before the first returned count is used
-            uint32_t old[EPT];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const uint32_t d = (key[e] >> shift) & 15u;
-                old[e] = atomicAdd(&mycnt[(d >> 1) * CS_THREADS], 1u << ((d & 1u) << 4));
-            }
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                uint32_t kk = key[e];
-                asm volatile("" : "+v"(kk));  // field shift recomputed, not kept
-                const uint32_t h = ((kk >> shift) & 1u) << 4;
-                pk[e] = (pk[e] & 0xFFFFu) | (((old[e] >> h) & 0xFFFFu) << 16);
-            }
-        }
-        {
-            // own counters -> exclusive prefix over the wave's threads
-            // (packed pairs: no field exceeds 16 bits)
-            uint32_t own[8], incl[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) own[k] = mycnt[k * CS_THREADS];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) incl[k] = wave_incl_scan_u32(own[k]);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) mycnt[k * CS_THREADS] = incl[k] - own[k];
-            if (lane == 63) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) sm.wtot[wave][k] = incl[k];
-            }
-        }
-        __syncthreads();
-        if (wave == 0) {
-            // lane = 16 r + w (w: wave, r: word pair), words k = r and r + 4:
-            // inclusive prefix over the waves within rows of 16 lanes
-            const int w = lane & 15, r = lane >> 4;
-            const uint32_t v0 = sm.wtot[w][r], v1 = sm.wtot[w][r + 4];
-            const uint32_t s0 = row16_incl_scan_u32(v0), s1 = row16_incl_scan_u32(v1);
-            // word totals (last lane of each row), packed digit bases
-            uint32_t pb[8];
-            uint32_t run = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t tk = (uint32_t)__builtin_amdgcn_readlane((int)(k < 4 ? s0 : s1), ((k & 3) << 4) | 15);
-                const uint32_t lo = tk & 0xFFFFu, hi = tk >> 16;
-                pb[k] = run | ((run + lo) << 16);
-                run += lo + hi;
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) sm.pbase[k] = pb[k];
-            }
-            // (the wave's own LDS accesses complete in order)
-            sm.wtot[w][r] = sm.pbase[r] + s0 - v0;
-            sm.wtot[w][r + 4] = sm.pbase[r + 4] + s1 - v1;
-        }
-        __syncthreads();
-        // offset of digit d for thread t: digit base + earlier waves (wtot)
-        // + earlier threads of the wave (own counters)
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            uint32_t kk = key[e];
-            asm volatile("" : "+v"(kk));  // recompute the digit's address
-            const uint32_t d = (kk >> shift) & 15u;
-            const uint32_t pw = mycnt[(d >> 1) * CS_THREADS] + sm.wtot[wave][d >> 1];
-            const uint32_t off = (pw >> ((d & 1u) << 4)) & 0xFFFFu;
-            pk[e] += off << 16;  // rank + offset: the destination
-        }
-        __syncthreads();  // counters (over the key slots) read
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t dst = pk[e] >> 16;
-            sm.key[dst] = key[e];
-            sm.idx[dst] = (uint16_t)pk[e];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            key[e] = sm.key[tb + e];
-            pk[e] = sm.idx[tb + e];
-        }
-        __syncthreads();  // key slots read before the next pass's counters
-    }
-    // The sorted keys stay in sm.key (predecessor comparisons below).  From
-    // here pk[e] holds the sample index (low 16 bits) and 1 + the start of
-    // the element's tie run (high 16 bits; 0 while the start lies in an
-    // earlier thread).
     uint16_t* ordc = out.ord + (int64_t)col * ld;
     uint16_t* posc = out.pos + (int64_t)col * ld;
     uint32_t* runc = out.runs + (int64_t)col * ld;
-    // run starts: s(k) = max{j <= k : j == 0 or key[j] != key[j-1]}
-    int last = -1;
+
+    // ---- compaction of the observed keys (striped, coalesced loads) ------
+    uint32_t key[E], pk[E];  // pk: sample index (low 16 bits) | rank in the wave (high 16)
+    uint32_t nobs = 0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int k = t * E + e;
-        const bool start = (k == 0) || (k < ncount && key[e] != sm.key[k - 1]);
-        if (k < ncount && start) last = k;
-        pk[e] = (pk[e] & 0xFFFFu) | ((uint32_t)(last + 1) << 16);
+    for (int e = 0; e < E; ++e) {
+        const int64_t j = (int64_t)e * CS_THREADS + t;
+        key[e] = j < S ? kc[j] : 0xFFFFFFFFu;
+        const bool obs = key[e] != 0xFFFFFFFFu;
+        if (!obs && j < S) posc[j] = 0xFFFF;  // missing sample
+        nobs += obs;
     }
-    // block exclusive max-scan of `last`
-    int v = last;
+    const uint32_t oincl = wave_incl_scan_u32(nobs);
+    if (lane == 63) sm.red[wave] = oincl;
+    __syncthreads();
+    uint32_t obase = 0, ncount = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int o = __shfl_up(v, d, 64);
-        if (lane >= d) v = max(v, o);
+    for (int v = 0; v < CS_WAVES; ++v) {
+        const uint32_t tv = sm.red[v];
+        obase += v < wave ? tv : 0u;
+        ncount += tv;
+    }
+    obase += oincl - nobs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (key[e] != 0xFFFFFFFFu) {
+            sm.key[obase] = key[e];
+            sm.idx[obase] = (uint16_t)(e * CS_THREADS + t);
+            ++obase;
+        }
+    }
+    const int Ee = (int)((ncount + CS_THREADS - 1) / CS_THREADS);  // steps per wave
+    const int slots = Ee * CS_THREADS;
+    for (int k = (int)ncount + t; k < slots; k += CS_THREADS) {
+        sm.key[k] = 0xFFFFFFFFu;  // padding sorts last
+        sm.idx[k] = 0xFFFF;
     }
     __syncthreads();
-    if (lane == 63) sm.red[wave] = v;
-    __syncthreads();
-    // max over the earlier waves (lanes 0..wave-1 hold their values)
-    int before = lane < wave ? sm.red[lane] : -1;
+    const int wbase = wave * 64 * Ee;
 #pragma unroll
-    for (int d = 8; d >= 1; d >>= 1) before = max(before, __shfl_xor(before, d, 16));
-    before = __builtin_amdgcn_readfirstlane(before);
-    int excl = __shfl_up(v, 1, 64);
-    if (lane == 0) excl = -1;
-    before = max(before, excl);
+    for (int e = 0; e < E; ++e) {
+        if (e < Ee) {
+            key[e] = sm.key[wbase + 64 * e + lane];
+            pk[e] = sm.idx[wbase + 64 * e + lane];
+        }
+    }
+
+    // bits in which some observed key differs from the first: a pass whose
+    // digit is the same for every observed key leaves the order as it is
+    // (integer-valued columns have zero low mantissa bytes)
+    uint32_t diff = 0u;
+    {
+        const uint32_t k0 = ncount > 0 ? sm.key[0] : 0u;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e)
-        if ((pk[e] >> 16) == 0u) pk[e] |= (uint32_t)(before + 1) << 16;
-    __syncthreads();
-    uint32_t* END = sm.key;  // reused: END[run start] = run end
-    bool tie_here = false;
-    // A run ends at k when k+1 == ncount or s(k+1) != s(k).  s of the
-    // successor is held by the same thread (e+1) or by thread t+1 (e = 0).
-    uint32_t rs_next_first = __shfl_down(pk[0] >> 16, 1, 64);
-    __syncthreads();
-    if (lane == 0) sm.red[wave] = (int32_t)(pk[0] >> 16);
-    __syncthreads();
-    if (lane == 63) rs_next_first = (wave + 1 < CS_WAVES) ? (uint32_t)sm.red[wave + 1] : 0xFFFFFFFFu;
+        for (int e = 0; e < E; ++e)
+            if (e < Ee && wbase + 64 * e + lane < (int)ncount) diff |= key[e] ^ k0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int k = t * E + e;
-        if (k < ncount) {
-            const uint32_t r1 = pk[e] >> 16;  // 1 + run start
-            const uint32_t rn = (k + 1 == ncount) ? 0xFFFFFFFFu : (e + 1 < E ? pk[e + 1] >> 16 : rs_next_first);
-            if (rn != r1) {
-                END[r1 - 1] = (uint32_t)(k + 1);
-                if ((uint32_t)k > r1 - 1) tie_here = true;
+        for (int dd = 32; dd >= 1; dd >>= 1) diff |= (uint32_t)__shfl_xor((int)diff, dd, 64);
+        // (slots CS_WAVES.. are next written after a pass's first barrier)
+        if (lane == 0) sm.red[CS_WAVES + wave] = diff;
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < CS_WAVES; ++v) diff |= sm.red[CS_WAVES + v];
+    }
+
+    // ---- 4 passes of 8-bit digits ------------------------------------------
+    uint16_t* wc = sm.wcnt + wave * 256;
+    for (int pass = 0; pass < 4 && Ee > 0; ++pass) {
+        const int shift = 8 * pass;
+        if (((diff >> shift) & 255u) == 0u) continue;  // uniform over the block
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wc[q * 64 + lane] = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e < Ee) {
+                const uint32_t d = (key[e] >> shift) & 255u;
+                const uint64_t peers = match_digit8(d);
+                const uint32_t below = lanes_below(peers);
+                const uint32_t cnt = (uint32_t)__popcll(peers);
+                const uint32_t b = wc[d];
+                if (below + 1u == cnt) wc[d] = (uint16_t)(b + cnt);  // last of the peers
+                pk[e] = (pk[e] & 0xFFFFu) | ((b + below) << 16);
+            }
+        }
+        __syncthreads();
+        // thread t: digit t / 4, waves 4 (t % 4) .. 4 (t % 4) + 3
+        {
+            const int dd = t >> 2, q = t & 3;
+            uint32_t c4[4], sum = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                c4[i] = sm.wcnt[(4 * q + i) * 256 + dd];
+                sum += c4[i];
+            }
+            const uint32_t incl = wave_incl_scan_u32(sum);
+            if (lane == 63) sm.red[CS_WAVES + wave] = incl;
+            __syncthreads();
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int v = 0; v < CS_WAVES; ++v) run += v < wave ? sm.red[CS_WAVES + v] : 0u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sm.wcnt[(4 * q + i) * 256 + dd] = (uint16_t)run;
+                run += c4[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e < Ee) {
+                const uint32_t d = (key[e] >> shift) & 255u;
+                const uint32_t dst = (uint32_t)wc[d] + (pk[e] >> 16);
+                sm.key[dst] = key[e];
+                sm.idx[dst] = (uint16_t)pk[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e < Ee) {
+                key[e] = sm.key[wbase + 64 * e + lane];
+                pk[e] = sm.idx[wbase + 64 * e + lane];
             }
         }
     }
-    __syncthreads();
-    // tie runs (length > 1) numbered in position order: a block scan of the
-    // run starts each thread holds
-    uint32_t nstart = 0;
+
+    // ---- tie runs ------------------------------------------------------------
+    // start: the key differs from its predecessor; last: from its successor.
+    // s(k) = the latest start <= k (a max-scan: within the wave, carried
+    // across steps, then across waves); a tie run is a start that is not also
+    // a last, and tie runs are numbered in position order (within a wave:
+    // by step, then lane).  The last of each run records its end at the
+    // run's start.
+    // From here key[e] holds the element's run start (low 30 bits) and its
+    // flags (bit 30: start, bit 31: last).
+    const int nc = (int)ncount;
+    int carry = 0;
+    uint32_t ntr = 0;  // tie runs starting in the wave's slots (wave-uniform)
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int k = t * E + e;
-        if (k < ncount && (pk[e] >> 16) == (uint32_t)k + 1u && END[k] - (uint32_t)k > 1u) ++nstart;
+    for (int e = 0; e < E; ++e) {
+        if (e < Ee) {
+            const int k = wbase + 64 * e + lane;
+            uint32_t f = 0;
+            if (k < nc) {
+                const bool st = k == 0 || sm.key[k - 1] != key[e];
+                const bool ls = k + 1 == nc || sm.key[k + 1] != key[e];
+                f = (st ? 1u : 0u) | (ls ? 2u : 0u);
+            }
+            ntr += (uint32_t)__popcll(__ballot(f == 1u));
+            const int x = max(wave_incl_max_scan((f & 1u) ? k : 0), carry);
+            carry = __builtin_amdgcn_readlane(x, 63);
+            key[e] = (uint32_t)x | (f << 30);
+        }
     }
-    const uint32_t sincl = wave_incl_scan_u32(nstart);
-    if (lane == 63) sm.red[wave] = (int32_t)sincl;
-    __syncthreads();
-    // runs of earlier waves and of the column: a scan of the wave counts
-    // held by lanes 0..CS_WAVES-1
-    const uint32_t rsc = wave_incl_scan_u32(lane < CS_WAVES ? (uint32_t)sm.red[lane] : 0u);
-    const uint32_t nrun = (uint32_t)__builtin_amdgcn_readlane((int)rsc, CS_WAVES - 1);
-    uint32_t rid = sincl - nstart + (wave > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)rsc, wave - 1) : 0u);
-    uint16_t* RID = sm.idx;  // reused: RID[run start] = run index
+    if (lane == 0) {
+        sm.red[2 * CS_WAVES + wave] = (uint32_t)carry;
+        sm.red[3 * CS_WAVES + wave] = ntr;
+    }
+    __syncthreads();  // also: every neighbour key has been read
+    int cin = 0;
+    uint32_t rid = 0, nrun = 0;
+#pragma unroll
+    for (int v = 0; v < CS_WAVES; ++v) {
+        const uint32_t c = sm.red[2 * CS_WAVES + v], r = sm.red[3 * CS_WAVES + v];
+        if (v < wave) {
+            cin = max(cin, (int)c);
+            rid += r;
+        }
+        nrun += r;
+    }
+    uint16_t* END = sm.idx;             // END[s] = end of the run starting at s
+    uint16_t* RID = (uint16_t*)sm.key;  // RID[s] = index of the tie run starting at s
     uint32_t* rlc = out.rlist + (int64_t)col * (ld / 2);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int k = t * E + e;
-        if (k < ncount && (pk[e] >> 16) == (uint32_t)k + 1u && END[k] - (uint32_t)k > 1u) {
-            RID[k] = (uint16_t)rid;
-            rlc[rid] = (uint32_t)k | (END[k] << 16);
-            ++rid;
+    for (int e = 0; e < E; ++e) {
+        if (e < Ee) {
+            const uint32_t f = key[e] >> 30;
+            const int sp = max((int)(key[e] & 0x3FFFFFFFu), cin);
+            key[e] = (uint32_t)sp;
+            const int k = wbase + 64 * e + lane;
+            if (f & 2u) END[sp] = (uint16_t)(k + 1);
+            const uint64_t m = __ballot(f == 1u);
+            if (f == 1u) RID[k] = (uint16_t)(rid + lanes_below(m));
+            rid += (uint32_t)__popcll(m);
         }
     }
     __syncthreads();
+    uint32_t ntied = 0;
+    const int64_t nwords = ld / 64;
+    uint64_t* tbc = out.tbits + (int64_t)col * nwords;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int k = t * E + e;
-        const uint32_t ix = pk[e] & 0xFFFFu;
-        if (k < ncount) {
-            ordc[k] = (uint16_t)ix;
-            // a tied sample's position entry holds the flag bit and its
-            // run index instead of the sorted position
-            const uint32_t rs = (pk[e] >> 16) - 1u;
-            const uint32_t run_end = END[rs];
-            const bool tied = run_end - rs > 1u;
-            posc[ix] = (uint16_t)(tied ? (0x8000u | RID[rs]) : (uint32_t)k);
-            runc[k] = rs | (run_end << 16);
-        } else if (ix != 0xFFFFu) {
-            posc[ix] = 0xFFFF;  // missing sample
+    for (int e = 0; e < E; ++e) {
+        if (e < Ee) {
+            const int k = wbase + 64 * e + lane;
+            bool tied = false;
+            if (k < nc) {
+                const uint32_t s0 = key[e], e0 = END[s0];
+                tied = e0 - s0 > 1u;
+                ordc[k] = (uint16_t)pk[e];
+                // a tied sample's position entry holds the flag bit and its
+                // run index instead of the sorted position
+                const uint32_t r0 = tied ? (uint32_t)RID[s0] : 0u;
+                posc[pk[e]] = (uint16_t)(tied ? (0x8000u | r0) : (uint32_t)k);
+                runc[k] = s0 | (e0 << 16);
+                if (tied && (uint32_t)k == s0) rlc[r0] = s0 | (e0 << 16);
+            }
+            const uint64_t m = __ballot(tied);
+            // (the slots may run past the row's words; tied positions never do)
+            if (lane == 0 && (wbase >> 6) + e < nwords) tbc[(wbase >> 6) + e] = m;
+            ntied += (uint32_t)__popcll(m);
         }
     }
     // padding: sorted positions past the observed count hold the dummy
-    // sample S, whose position is "missing"
-    for (int64_t k = ncount + t; k < ld; k += CS_THREADS) ordc[k] = (uint16_t)S;
+    // sample S, whose position is "missing"; tie-bit words past the slots
+    // are zero
+    for (int64_t k = nc + t; k < ld; k += CS_THREADS) ordc[k] = (uint16_t)S;
     for (int64_t i = S + t; i < ld; i += CS_THREADS) posc[i] = 0xFFFF;
+    for (int64_t w = (int64_t)(slots >> 6) + t; w < nwords; w += CS_THREADS) tbc[w] = 0ull;
     if (col == (int)gridDim.x - 1)
         for (int64_t k = t; k < ORD_TAIL; k += CS_THREADS) ordc[ld + k] = (uint16_t)S;
-    const int anytie = __syncthreads_or(tie_here ? 1 : 0);
+    if (lane == 0) sm.red[wave] = ntied;
+    __syncthreads();
     if (t == 0) {
-        out.ncol[col] = ncount;
-        out.hasties[col] = anytie ? 1 : 0;
+        uint32_t tc = 0;
+        for (int v = 0; v < CS_WAVES; ++v) tc += sm.red[v];
+        out.ncol[col] = nc;
+        out.hasties[col] = tc > 0 ? 1 : 0;
         out.nruns[col] = (int32_t)nrun;
+        out.tcount[col] = (int32_t)tc;
     }
 }
 
@@ -532,12 +554,16 @@ __global__ __launch_bounds__(256) void k_perm(SpearBase bs, int64_t F)
     if (lane == 0) bs.perm[rank] = (int32_t)c;
 }
 
-static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st)
+// Tie classes and processing order; with_bits: first the tie bits and counts
+// from the run arrays (the column sort writes them itself)
+static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st, bool with_bits = true)
 {
-    hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, bs.tcount, F);
-    NAPY_TRY(check_launch("fill"));
-    hipLaunchKernelGGL(k_tiebits, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)F), dim3(256), 0, st, bs);
-    NAPY_TRY(check_launch("tiebits"));
+    if (with_bits) {
+        hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)ceil_div(F, 256)), dim3(256), 0, st, bs.tcount, F);
+        NAPY_TRY(check_launch("fill"));
+        hipLaunchKernelGGL(k_tiebits, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)F), dim3(256), 0, st, bs);
+        NAPY_TRY(check_launch("tiebits"));
+    }
     hipLaunchKernelGGL(k_tcls, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, bs, F);
     NAPY_TRY(check_launch("tie classes"));
     hipLaunchKernelGGL(k_perm, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, bs, F);
@@ -1654,7 +1680,7 @@ static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us
     else if (E <= 16) NAPY_TRY(colsort_launch<16>(keys, S, F, base, st));
     else if (E <= 20) NAPY_TRY(colsort_launch<20>(keys, S, F, base, st));
     else NAPY_TRY(colsort_launch<CS_EPT_MAX>(keys, S, F, base, st));
-    return tiebits_launch(base, F, st);
+    return tiebits_launch(base, F, st, false);
 }
 
 static int final_launch(const SpearWs& w, int64_t F, double* r, double* p, int32_t* n, int64_t ldo,
