@@ -44,6 +44,7 @@
 
 #include "napy_internal.hpp"
 #include "pvalue.hpp"
+#include "tilefin.hpp"
 
 namespace napy {
 
@@ -195,19 +196,6 @@ struct TileCfg<NAPY_PREC_FP64> {
     static constexpr int FLUSH = 0;
     static constexpr int RPT = 4;
 };
-
-// tile index -> (tg, th), tg <= th, row-major over the upper triangle of T x T
-__device__ __forceinline__ void tile_coords(int t, int T, int& tg, int& th)
-{
-    // start(g) = g*T - g*(g-1)/2
-    int g = (int)((2.0f * T + 1.0f - sqrtf((2.0f * T + 1.0f) * (2.0f * T + 1.0f) - 8.0f * t)) * 0.5f);
-    if (g < 0) g = 0;
-    if (g > T - 1) g = T - 1;
-    while (g > 0 && g * T - g * (g - 1) / 2 > t) --g;
-    while (g + 1 < T && (g + 1) * T - (g + 1) * g / 2 <= t) ++g;
-    tg = g;
-    th = g + (t - (g * T - g * (g - 1) / 2));
-}
 
 // Maps the hardware block index to a logical work index so that every XCD
 // (blocks are dealt to the 8 XCDs round-robin) receives a contiguous range of
@@ -739,44 +727,58 @@ __device__ __forceinline__ void write_saved(double* __restrict__ saved, int64_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_pearson_combine(
-    const double* __restrict__ part, int T, int ntiles, int nsplit, int64_t F,
+// One workgroup per 32 x 32 tile of the upper triangle (a quarter of one
+// 64 x 64 contraction tile): the split-K partials summed in FP64, r, n and
+// the redo list, then p and both triangles.
+__global__ __launch_bounds__(FT_THREADS) void k_pearson_combine(
+    const double* __restrict__ part, int T, int ntiles, int nsplit, int64_t F, int T32,
     double* __restrict__ r, double* __restrict__ p, int32_t* __restrict__ n, int64_t ldo,
     double* __restrict__ saved, uint32_t* __restrict__ redo_count, uint32_t* __restrict__ redo)
 {
-    const int t = blockIdx.x / (TILE_ELEMS / 256);
-    const int e = (blockIdx.x % (TILE_ELEMS / 256)) * 256 + threadIdx.x;
+    __shared__ FinSmem f;
     int tg, th;
-    tile_coords(t, T, tg, th);
-    const int i = e / TILE, j = e % TILE;
-    const int64_t g = (int64_t)tg * TILE + i, h = (int64_t)th * TILE + j;
-    if (g >= F || h >= F) return;
-    if (tg == th && i > j) return;
-    double st[NSTAT];
+    tile_coords((int)blockIdx.x, T32, tg, th);
+    const int64_t g0 = (int64_t)tg * FT, h0 = (int64_t)th * FT;
+    const int t = tile_index(tg >> 1, th >> 1, T);
+    const int ro = (tg & 1) * FT, co = (th & 1) * FT;  // the quarter inside the 64 x 64 tile
+    const int j = ft_col();
+    bool valid[FT_K];
 #pragma unroll
-    for (int s = 0; s < NSTAT; ++s) st[s] = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp)
+    for (int k = 0; k < FT_K; ++k) {
+        valid[k] = ft_valid(g0, h0, F, k);
+        if (!valid[k]) continue;
+        const int i = ft_row(k);
+        const int64_t g = g0 + i, h = h0 + j;
+        const int e = (ro + i) * TILE + co + j;
+        double st[NSTAT];
 #pragma unroll
-        for (int s = 0; s < NSTAT; ++s)
-            st[s] += part[(((int64_t)sp * NSTAT + s) * ntiles + t) * TILE_ELEMS + e];
-    const double cn = st[0], sx = st[1], sy = st[2], sxx = st[3], syy = st[4], sxy = st[5];
-    const int64_t ni = (int64_t)(cn + 0.5);
-    double rv = __builtin_nan(""), pv = __builtin_nan("");
-    if (ni >= 2) {
-        const double vx = cn * sxx - sx * sx;
-        const double vy = cn * syy - sy * sy;
-        if (vx >= WELL_CENTRED * cn * sxx && vy >= WELL_CENTRED * cn * syy && vx > 0.0 && vy > 0.0) {
-            const double cxy = cn * sxy - sx * sy;
-            rv = cxy / sqrt(vx * vy);
-            rv = rv > 1.0 ? 1.0 : (rv < -1.0 ? -1.0 : rv);
-            pv = (ni == 2) ? 1.0 : corr_pvalue(rv, ni);
-        } else {
-            const uint32_t slot = atomicAdd(redo_count, 1u);
-            redo[slot] = (uint32_t)(g * F + h);
+        for (int s = 0; s < NSTAT; ++s) st[s] = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp)
+#pragma unroll
+            for (int s = 0; s < NSTAT; ++s)
+                st[s] += part[(((int64_t)sp * NSTAT + s) * ntiles + t) * TILE_ELEMS + e];
+        const double cn = st[0], sx = st[1], sy = st[2], sxx = st[3], syy = st[4], sxy = st[5];
+        const int64_t ni = (int64_t)(cn + 0.5);
+        double rv = __builtin_nan("");
+        if (ni >= 2) {
+            const double vx = cn * sxx - sx * sx;
+            const double vy = cn * syy - sy * sy;
+            if (vx >= WELL_CENTRED * cn * sxx && vy >= WELL_CENTRED * cn * syy && vx > 0.0 && vy > 0.0) {
+                const double cxy = cn * sxy - sx * sy;
+                rv = cxy / sqrt(vx * vy);
+                rv = rv > 1.0 ? 1.0 : (rv < -1.0 ? -1.0 : rv);
+            } else {
+                const uint32_t slot = atomicAdd(redo_count, 1u);
+                redo[slot] = (uint32_t)(g * F + h);
+            }
         }
+        f.r[i][j] = rv;
+        f.n[i][j] = (int32_t)ni;
+        if (saved) write_saved(saved, F, g, h, st, rv);
     }
-    write_pair(g, h, ldo, rv, pv, ni, r, p, n);
-    if (saved) write_saved(saved, F, g, h, st, rv);
+    ft_pvalues(f, valid, true);  // n = 2: p = 1 (listed pairs get theirs from the recomputation)
+    __syncthreads();
+    ft_write(f, g0, h0, F, r, p, n, ldo);
 }
 
 __global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
@@ -1016,8 +1018,9 @@ static int pearson_run_plan(const float* X, int64_t S, int64_t F, int64_t ldx, d
     NAPY_TRY(record_stage(ev, 2, st));
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w.redo_count);
     NAPY_TRY(check_launch("zero"));
-    hipLaunchKernelGGL(k_pearson_combine, dim3((unsigned)(pl.ntiles * (TILE_ELEMS / 256))), dim3(256), 0, st,
-                       part, pl.T, pl.ntiles, pl.nsplit, F, r, p, n, ldo, saved, w.redo_count, w.redo);
+    const int T32 = (int)ceil_div(F, FT);
+    hipLaunchKernelGGL(k_pearson_combine, dim3((unsigned)(T32 * (T32 + 1) / 2)), dim3(FT_THREADS), 0, st, part,
+                       pl.T, pl.ntiles, pl.nsplit, F, T32, r, p, n, ldo, saved, w.redo_count, w.redo);
     NAPY_TRY(check_launch("pearson_combine"));
     // a fixed grid: workgroups whose index is at least the listed count
     // return at once

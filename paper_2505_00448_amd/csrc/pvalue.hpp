@@ -13,7 +13,8 @@
 // evaluated with the modified Lentz algorithm (Lentz 1976; Thompson & Barnett
 // 1986).  It converges fast for x < (a + 1) / (a + b + 2); otherwise the
 // symmetry I_x(a, b) = 1 - I_{1-x}(b, a) is used, so the tail that is computed
-// directly is always the small one.  The prefactor x^a (1-x)^b / (a B(a,b)) is
+// directly is the small one (for p the complement is kept a little beyond
+// that point, see corr_p_params).  The prefactor x^a (1-x)^b / (a B(a,b)) is
 // formed in logs.  ln B(a, 1/2) = ln(sqrt(pi)) - [ln G(a + 1/2) - ln G(a)];
 // for a >= 20 the bracket is evaluated as 0.5 ln a plus the asymptotic series
 // obtained from Stirling's series of both log-gammas (so no two large
@@ -64,75 +65,159 @@ NAPY_HD inline double recip(double x)
 #endif
 }
 
-// Continued fraction part of I_x(a, b) (modified Lentz).  Returns h with
-// I_x(a, b) = x^a (1-x)^b / (a B(a, b)) * h.  Each half step takes 1/c and
-// 1/D (D = 1 + aa d) from one reciprocal of c D, so an iteration needs four
-// reciprocals, not six.  (Sharing one reciprocal between the two coefficient
+// Continued fraction of I_x(a, b) (A&S 26.5.8): I_x(a, b) = x^a (1-x)^b /
+// (a B(a, b)) * 1 / (1 + e_1 / (1 + e_2 / (1 + ...))), with the partial
+// numerators e_{2k} = k (b - k) x / ((a + 2k - 1)(a + 2k)) and e_{2k+1} =
+// -(a + k)(a + b + k) x / ((a + 2k)(a + 2k + 1)).  It is evaluated forwards
+// by the modified Lentz method (Lentz 1976; Thompson & Barnett 1986): with
+// the ratios C_j = A_j / A_{j-1} and 1/D_j = B_{j-1} / B_j of successive
+// numerators and denominators, C_j = 1 + e_j / C_{j-1}, D_j = 1 + e_j /
+// D_{j-1}, and the value is the product of the C_j / D_j; ratios that come
+// out near zero are replaced by a tiny number.  CfLentz holds the product
+// (prod), the last C (cr) and 1/D (id), and the index k of the next pair of
+// terms, so a caller can interleave the steps of several evaluations.  A
+// term pair takes 1/C and 1/D from one reciprocal of C D (four reciprocals
+// per pair instead of six; sharing one between the two coefficient
 // denominators as well costs about a third more rounding error in the slow
-// cases near the tail switch at large a.)
+// cases near the tail switch at large a).
+struct CfLentz {
+    double a, b, x;
+    double prod, cr, id;
+    int k;
+};
+
+constexpr double CF_TINY = 1e-300;
+constexpr double CF_EPS = 1e-16;
+constexpr int CF_MAXK = 2000;
+
+NAPY_HD inline void cf_start(CfLentz& s, double a, double b, double x)
+{
+    s.a = a;
+    s.b = b;
+    s.x = x;
+    s.cr = 1.0;
+    double d0 = 1.0 - (a + b) * x * recip(a + 1.0);  // D_1 (e_1 / C_0 with C_0 = 1 folded in)
+    if (fabs(d0) < CF_TINY) d0 = CF_TINY;
+    s.id = recip(d0);
+    s.prod = s.id;
+    s.k = 1;
+}
+
+// one Lentz update with partial numerator e: D = 1 + e / D_prev, C = 1 + e /
+// C_prev; returns C / D
+NAPY_HD inline double cf_term(CfLentz& s, double e)
+{
+    double den = 1.0 + e * s.id;
+    if (fabs(den) < CF_TINY) den = CF_TINY;
+    const double inv = recip(s.cr * den);
+    double num = 1.0 + e * (den * inv);  // 1 + e / C_prev
+    if (fabs(num) < CF_TINY) num = CF_TINY;
+    s.id = s.cr * inv;  // 1 / den
+    s.cr = num;
+    return s.id * num;
+}
+
+// terms 2k and 2k + 1; true once the last ratio is within CF_EPS of one (or
+// after CF_MAXK pairs)
+NAPY_HD inline bool cf_advance(CfLentz& s)
+{
+    const double kk = (double)s.k, k2 = 2.0 * kk;
+    const double a = s.a, b = s.b, x = s.x;
+    s.prod *= cf_term(s, kk * (b - kk) * x * recip((a - 1.0 + k2) * (a + k2)));
+    const double ratio = cf_term(s, -(a + kk) * (a + b + kk) * x * recip((a + k2) * (a + 1.0 + k2)));
+    s.prod *= ratio;
+    ++s.k;
+    return fabs(ratio - 1.0) < CF_EPS || s.k > CF_MAXK;
+}
+
+// the continued-fraction factor h of I_x(a, b) = x^a (1-x)^b / (a B(a, b)) h
 NAPY_HD inline double betacf_lentz(double a, double b, double x)
 {
-    const double tiny = 1e-300;
-    const double eps = 1e-16;
-    const double qab = a + b, qap = a + 1.0, qam = a - 1.0;
-    double c = 1.0;
-    double d = 1.0 - qab * x * recip(qap);
-    if (fabs(d) < tiny) d = tiny;
-    d = recip(d);
-    double h = d;
-    for (int m = 1; m <= 2000; ++m) {
-        const double dm = (double)m;
-        const double m2 = 2.0 * dm;
-        // even step: aa = m (b - m) x / ((a-1+2m)(a+2m))
-        double aa = dm * (b - dm) * x * recip((qam + m2) * (a + m2));
-        double D = 1.0 + aa * d;
-        if (fabs(D) < tiny) D = tiny;
-        double rcD = recip(c * D);
-        double C = 1.0 + aa * (D * rcD);  // 1 + aa / c
-        if (fabs(C) < tiny) C = tiny;
-        d = c * rcD;  // 1 / D
-        h *= d * C;
-        c = C;
-        // odd step: aa = -(a + m)(a + b + m) x / ((a+2m)(a+1+2m))
-        aa = -(a + dm) * (qab + dm) * x * recip((a + m2) * (qap + m2));
-        D = 1.0 + aa * d;
-        if (fabs(D) < tiny) D = tiny;
-        rcD = recip(c * D);
-        C = 1.0 + aa * (D * rcD);
-        if (fabs(C) < tiny) C = tiny;
-        d = c * rcD;
-        const double del = d * C;
-        h *= del;
-        c = C;
-        if (fabs(del - 1.0) < eps) break;
+    CfLentz s;
+    cf_start(s, a, b, x);
+    while (!cf_advance(s)) {
     }
-    return h;
+    return s.prod;
+}
+
+// Setup of p = I_{1-r^2}((n-2)/2, 1/2) for n >= 3 and finite r: either a
+// value that needs no continued fraction (done), or the fraction's
+// parameters (a, b, x), the log of its prefactor and the tail (direct: p is
+// the prefactor times the fraction; otherwise 1 minus it).  The parameters
+// are chosen first so that one continued-fraction loop serves both tails
+// (lanes of a wave taking different tails do not run two loops).
+struct CorrPSetup {
+    double a, b, x, lf, value;
+    bool done, direct;
+};
+
+// The fraction's parameters and the tail alone (no logarithms): what a
+// caller needs to start the continued fraction; lf is left zero.
+NAPY_HD inline CorrPSetup corr_p_params(double r, int64_t n)
+{
+    CorrPSetup q;
+    q.a = q.b = q.x = q.lf = 0.0;
+    q.direct = true;
+    q.done = true;
+    q.value = NAN;
+    if (!(r == r) || n < 3) return q;
+    const double ar = fabs(r);
+    if (ar >= 1.0) {
+        q.value = 0.0;
+        return q;
+    }
+    if (ar == 0.0) {
+        q.value = 1.0;
+        return q;
+    }
+    const double a = 0.5 * (double)(n - 2);
+    const double y = ar * ar;                 // r^2
+    const double x = (1.0 - ar) * (1.0 + ar); // 1 - r^2 without cancellation
+    // the direct tail I_x(a, 1/2), or 1 - I_{r^2}(1/2, a).  The usual switch,
+    // direct for x < (a + 1) / (a + b + 2), i.e. r^2 (a + 2.5) > 1.5, leaves
+    // the direct fraction's slowest region (up to about 48 steps at large a)
+    // just above it.  For a >= 4 the complement is kept up to r^2 (a + 2.5)
+    // = 3.75: its fraction takes at most about 15 steps there and the direct
+    // one above at most about 25, while p stays above about 5e-3, so that
+    // forming 1 - I loses at most two to three digits.
+    const bool direct = (a >= 4.0) ? (y * (a + 2.5) >= 3.75) : (x < (a + 1.0) / (a + 2.5));
+    q.a = direct ? a : 0.5;
+    q.b = direct ? 0.5 : a;
+    q.x = direct ? x : y;
+    q.direct = direct;
+    q.done = false;
+    return q;
+}
+
+NAPY_HD inline CorrPSetup corr_p_setup(double r, int64_t n)
+{
+    CorrPSetup q = corr_p_params(r, n);
+    if (q.done) return q;
+    const double ar = fabs(r);
+    const double a = 0.5 * (double)(n - 2);
+    const double lnx = log1p(-(ar * ar));
+    const double lny = 2.0 * log(ar);
+    // ln B(a, 1/2) = 0.5 ln(pi) - [ln G(a+1/2) - ln G(a)]
+    const double lnB = 0.57236494292470008707 - lgamma_half_ratio(a);
+    q.lf = q.direct ? a * lnx + 0.5 * lny - log(a) - lnB : 0.5 * lny + a * lnx + 0.69314718055994530942 - lnB;
+    return q;
+}
+
+// p from the setup and the fraction's value h
+NAPY_HD inline double corr_p_finish(const CorrPSetup& q, double h)
+{
+    const double t = exp(q.lf) * h;
+    if (q.direct) return t;
+    const double p = 1.0 - t;
+    return p < 0.0 ? 0.0 : p;
 }
 
 // p = I_{1-r^2}((n-2)/2, 1/2) for n >= 3 and finite r; NaN otherwise.
 NAPY_HD inline double corr_pvalue(double r, int64_t n)
 {
-    if (!(r == r) || n < 3) return NAN;
-    const double ar = fabs(r);
-    if (ar >= 1.0) return 0.0;
-    if (ar == 0.0) return 1.0;
-    const double a = 0.5 * (double)(n - 2);
-    const double y = ar * ar;                 // r^2
-    const double x = (1.0 - ar) * (1.0 + ar); // 1 - r^2 without cancellation
-    const double lnx = log1p(-y);
-    const double lny = 2.0 * log(ar);
-    // ln B(a, 1/2) = 0.5 ln(pi) - [ln G(a+1/2) - ln G(a)]
-    const double lnB = 0.57236494292470008707 - lgamma_half_ratio(a);
-    // the direct tail I_x(a, 1/2), or 1 - I_{r^2}(1/2, a); the parameters are
-    // chosen first so that one continued-fraction loop serves both (lanes of
-    // a wave taking different tails do not run two loops)
-    const bool direct = x < (a + 1.0) / (a + 2.5);
-    const double lf = direct ? a * lnx + 0.5 * lny - log(a) - lnB
-                             : 0.5 * lny + a * lnx + 0.69314718055994530942 - lnB;
-    const double t = exp(lf) * betacf_lentz(direct ? a : 0.5, direct ? 0.5 : a, direct ? x : y);
-    if (direct) return t;
-    const double p = 1.0 - t;
-    return p < 0.0 ? 0.0 : p;
+    const CorrPSetup q = corr_p_setup(r, n);
+    if (q.done) return q.value;
+    return corr_p_finish(q, betacf_lentz(q.a, q.b, q.x));
 }
 
 // ln G(a + b) - ln G(a) for a, b > 0.  For a >= 20 from Stirling's series of

@@ -41,6 +41,7 @@
 #include "napy_internal.hpp"
 #include "pvalue.hpp"
 #include "rankbase.hpp"
+#include "tilefin.hpp"
 
 namespace napy {
 
@@ -408,7 +409,6 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
 // ---------------------------------------------------------------------------
 struct PairOut {
     double4* sums;  // [npairs] (n, A, B_a, B_b)
-    int2* ab;       // [npairs]
     int32_t* dbg_ra;
     int32_t* dbg_rb;
     int dbg_a, dbg_b;
@@ -1386,45 +1386,45 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             const int64_t g = a < b ? a : b, h = a < b ? b : a;
             const int64_t pid = pair_index(g, h, F);
             po.sums[pid] = make_double4((double)nn, (double)sA, Ba, Bb);
-            po.ab[pid] = make_int2((int)a, (int)b);
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_spearman_final(const double4* __restrict__ sums,
-                                                        const int2* __restrict__ ab, int64_t npairs,
-                                                        double* __restrict__ r, double* __restrict__ p,
-                                                        int32_t* __restrict__ n, int64_t ldo)
+// One workgroup per 32 x 32 tile of the upper triangle: rho and n from the
+// exact integer sums of each pair (g <= h), then p and both triangles.
+__global__ __launch_bounds__(FT_THREADS) void k_spearman_final(const double4* __restrict__ sums, int64_t F, int T32,
+                                                              double* __restrict__ r, double* __restrict__ p,
+                                                              int32_t* __restrict__ n, int64_t ldo)
 {
-    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (id >= npairs) return;
-    const double4 s = sums[id];
-    const int2 q = ab[id];
-    const int64_t nn = (int64_t)s.x;
-    const int64_t A = (int64_t)s.y, Ba = (int64_t)s.z, Bb = (int64_t)s.w;
-    const int64_t K = nn * (nn + 1) * (nn + 1);
-    const int64_t num = A - K, Da = Ba - K, Db = Bb - K;
-    double rho = __builtin_nan(""), pv = __builtin_nan("");
-    if (nn >= 2 && Da > 0 && Db > 0) {
-        // sqrt of the product (not the product of roots) so that identical
-        // rank vectors give exactly 1
-        rho = (double)num / sqrt((double)Da * (double)Db);
-        rho = rho > 1.0 ? 1.0 : (rho < -1.0 ? -1.0 : rho);
-        if (nn >= 3) pv = corr_pvalue(rho, nn);
+    __shared__ FinSmem f;
+    int tg, th;
+    tile_coords((int)blockIdx.x, T32, tg, th);
+    const int64_t g0 = (int64_t)tg * FT, h0 = (int64_t)th * FT;
+    const int j = ft_col();
+    bool valid[FT_K];
+#pragma unroll
+    for (int k = 0; k < FT_K; ++k) {
+        valid[k] = ft_valid(g0, h0, F, k);
+        if (!valid[k]) continue;
+        const int i = ft_row(k);
+        const double4 s = sums[pair_index(g0 + i, h0 + j, F)];
+        const int64_t nn = (int64_t)s.x;
+        const int64_t A = (int64_t)s.y, Ba = (int64_t)s.z, Bb = (int64_t)s.w;
+        const int64_t K = nn * (nn + 1) * (nn + 1);
+        const int64_t num = A - K, Da = Ba - K, Db = Bb - K;
+        double rho = __builtin_nan("");
+        if (nn >= 2 && Da > 0 && Db > 0) {
+            // sqrt of the product (not the product of roots) so that identical
+            // rank vectors give exactly 1
+            rho = (double)num / sqrt((double)Da * (double)Db);
+            rho = rho > 1.0 ? 1.0 : (rho < -1.0 ? -1.0 : rho);
+        }
+        f.r[i][j] = rho;
+        f.n[i][j] = (int32_t)nn;
     }
-    const int64_t g = q.x, h = q.y;
-    if (r) {
-        r[g * ldo + h] = rho;
-        r[h * ldo + g] = rho;
-    }
-    if (p) {
-        p[g * ldo + h] = pv;
-        p[h * ldo + g] = pv;
-    }
-    if (n) {
-        n[g * ldo + h] = (int32_t)nn;
-        n[h * ldo + g] = (int32_t)nn;
-    }
+    ft_pvalues(f, valid, false);  // n = 2: p undefined
+    __syncthreads();
+    ft_write(f, g0, h0, F, r, p, n, ldo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1639,7 +1639,6 @@ struct SpearWs {
     SpearBase base;
     uint32_t* pres;  // ceil(F/32) * ld words: ceil(F/8) planes of ld presence bytes
     double4* sums;
-    int2* ab;
 };
 
 static void spear_carve(Carver& c, int64_t S, int64_t F, SpearWs& w)
@@ -1650,7 +1649,6 @@ static void spear_carve(Carver& c, int64_t S, int64_t F, SpearWs& w)
     w.pres = c.take<uint32_t>((size_t)ceil_div(F, 32) * ld);
     const int64_t npairs = F * (F + 1) / 2;
     w.sums = c.take<double4>(npairs);
-    w.ab = c.take<int2>(npairs);
 }
 
 template <int EPT>
@@ -1686,9 +1684,9 @@ static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us
 static int final_launch(const SpearWs& w, int64_t F, double* r, double* p, int32_t* n, int64_t ldo,
                         hipStream_t st)
 {
-    const int64_t npairs = F * (F + 1) / 2;
-    hipLaunchKernelGGL(k_spearman_final, dim3((unsigned)ceil_div(npairs, 256)), dim3(256), 0, st, w.sums,
-                       w.ab, npairs, r, p, n, ldo);
+    const int T32 = (int)ceil_div(F, FT);
+    hipLaunchKernelGGL(k_spearman_final, dim3((unsigned)(T32 * (T32 + 1) / 2)), dim3(FT_THREADS), 0, st, w.sums, F,
+                       T32, r, p, n, ldo);
     return check_launch("spearman_final");
 }
 
@@ -1709,7 +1707,7 @@ int spearman_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, d
     NAPY_TRY(record_stage(ev, 0, st));
     NAPY_TRY(sort_launch(X, S, F, ldx, opt_use_sent(opts), opt_sent(opts), w.keys, w.base, st));
     NAPY_TRY(record_stage(ev, 1, st));
-    PairOut po{w.sums, w.ab, nullptr, nullptr, 0, 0};
+    PairOut po{w.sums, nullptr, nullptr, 0, 0};
     NAPY_TRY(pairs_launch(w.base, w.pres, S, F, po, st));
     NAPY_TRY(record_stage(ev, 2, st));
     NAPY_TRY(final_launch(w, F, r, p, n, ldo, st));
@@ -1733,7 +1731,7 @@ int spearman_pair_ranks_run(const float* X, int64_t S, int64_t F, int64_t ldx, i
     NAPY_TRY(check_launch("fill"));
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, st, rh, S, -1);
     NAPY_TRY(check_launch("fill"));
-    PairOut po{w.sums, w.ab, rg, rh, g, h};
+    PairOut po{w.sums, rg, rh, g, h};
     return pairs_launch(w.base, w.pres, S, F, po, st);
 }
 
@@ -1784,7 +1782,6 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
     w.pres = c.take<uint32_t>((size_t)ceil_div(Fq, 32) * spear_ld(Sq));
     const int64_t npairs = Fq * (Fq + 1) / 2;
     w.sums = c.take<double4>(npairs);
-    w.ab = c.take<int2>(npairs);
     w.keys = nullptr;
     if (S > 0) {
         hipLaunchKernelGGL(k_rowmap, dim3((unsigned)ceil_div(S, 256)), dim3(256), 0, st, rows, Sq, S, rowmap);
@@ -1803,7 +1800,7 @@ int spearman_subset_run(const void* basebuf, int64_t S, int64_t F, const int32_t
         NAPY_TRY(check_launch("compact"));
     }
     NAPY_TRY(tiebits_launch(w.base, Fq, st));
-    PairOut po{w.sums, w.ab, nullptr, nullptr, 0, 0};
+    PairOut po{w.sums, nullptr, nullptr, 0, 0};
     NAPY_TRY(pairs_launch(w.base, w.pres, Sq, Fq, po, st));
     return final_launch(w, Fq, r, p, n, ldo, st);
 }

@@ -1,0 +1,100 @@
+// Output tiles of the correlation matrices: r, p and n of 32 x 32 pairs per
+// workgroup, the p-value (NApy, arXiv 2505.00448, Sections 3.5.2 and 3.5.3)
+// of every pair, and both triangles of the symmetric outputs.
+//
+// A workgroup of FT_THREADS threads owns the pairs (g0 + i, h0 + j) of one
+// tile on or above the diagonal; thread t holds the pairs (i, j) = (t / 32 +
+// (FT_THREADS / 32) k, t mod 32), k = 0..FT_K-1.  The tile (row g0 + i) is
+// written directly and its mirror (row h0 + j) through a transpose in LDS,
+// so both writes are whole rows of 32 values.
+#pragma once
+
+#include "napy_internal.hpp"
+#include "pvalue.hpp"
+
+namespace napy {
+
+constexpr int FT = 32;
+constexpr int FT_THREADS = 1024;
+constexpr int FT_K = FT * FT / FT_THREADS;  // pairs per thread
+
+struct FinSmem {
+    double r[FT][FT + 1];
+    double v[FT][FT + 1];  // p
+    int32_t n[FT][FT + 1];
+};
+
+// tile index -> (tg, th), tg <= th, row-major over the upper triangle of T x T
+__host__ __device__ inline void tile_coords(int t, int T, int& tg, int& th)
+{
+    // start(g) = g*T - g*(g-1)/2
+    int g = (int)((2.0f * T + 1.0f - sqrtf((2.0f * T + 1.0f) * (2.0f * T + 1.0f) - 8.0f * t)) * 0.5f);
+    if (g < 0) g = 0;
+    if (g > T - 1) g = T - 1;
+    while (g > 0 && g * T - g * (g - 1) / 2 > t) --g;
+    while (g + 1 < T && (g + 1) * T - (g + 1) * g / 2 <= t) ++g;
+    tg = g;
+    th = g + (t - (g * T - g * (g - 1) / 2));
+}
+
+// (tg, th), tg <= th -> tile index
+__host__ __device__ inline int tile_index(int tg, int th, int T)
+{
+    return tg * T - tg * (tg - 1) / 2 + (th - tg);
+}
+
+__device__ __forceinline__ int ft_row(int k) { return (int)(threadIdx.x >> 5) + (FT_THREADS / 32) * k; }
+__device__ __forceinline__ int ft_col() { return (int)(threadIdx.x & 31); }
+
+// pair k of the thread lies in the matrix and on or above the diagonal
+__device__ __forceinline__ bool ft_valid(int64_t g0, int64_t h0, int64_t F, int k)
+{
+    const int64_t g = g0 + ft_row(k), h = h0 + ft_col();
+    return g < F && h < F && (g0 != h0 || ft_row(k) <= ft_col());
+}
+
+// p-values of the thread's valid pairs, from r and n in f (n2one: a pair of
+// two samples with a defined r has p = 1, the Pearson rule; otherwise NaN),
+// left in f.v.  No barrier inside.
+__device__ inline void ft_pvalues(FinSmem& f, const bool (&valid)[FT_K], bool n2one)
+{
+    const int j = ft_col();
+#pragma unroll
+    for (int k = 0; k < FT_K; ++k) {
+        if (!valid[k]) continue;
+        const int i = ft_row(k);
+        const int64_t n = f.n[i][j];
+        const double rv = f.r[i][j];
+        f.v[i][j] = (n2one && n == 2 && rv == rv) ? 1.0 : corr_pvalue(rv, n);
+    }
+}
+
+// Writes r (f.r), p (f.v) and n (f.n) of the tile and of its mirror.  Call
+// after a barrier that follows every thread's last write of f.
+__device__ inline void ft_write(const FinSmem& f, int64_t g0, int64_t h0, int64_t F, double* __restrict__ r,
+                                double* __restrict__ p, int32_t* __restrict__ n, int64_t ldo)
+{
+    const int j = ft_col();
+#pragma unroll
+    for (int k = 0; k < FT_K; ++k) {
+        const int i = ft_row(k);
+        // the tile: pair (i, j) at (g0 + i, h0 + j)
+        if (ft_valid(g0, h0, F, k)) {
+            const int64_t o = (g0 + i) * ldo + h0 + j;
+            if (r) r[o] = f.r[i][j];
+            if (p) p[o] = f.v[i][j];
+            if (n) n[o] = f.n[i][j];
+        }
+        // the mirror: pair (j, i) at (h0 + i, g0 + j); on a diagonal tile
+        // only below the diagonal
+        const int64_t hm = h0 + i, gm = g0 + j;
+        if (hm < F && gm < F && (g0 != h0 || j < i)) {
+            const int64_t o = hm * ldo + gm;
+            if (r) r[o] = f.r[j][i];
+            if (p) p[o] = f.v[j][i];
+            if (n) n[o] = f.n[j][i];
+        }
+    }
+}
+
+}  // namespace napy

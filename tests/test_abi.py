@@ -152,20 +152,23 @@ def test_pvalue_arithmetic_against_mpmath():
 
 
 def test_pvalue_near_the_tail_switch():
-    """The continued fraction converges slowest where the routine switches
+    """The continued fraction converges slowest just above the usual switch
     between the direct tail and its complement, x = 1 - r^2 near
     (a + 1) / (a + 2.5) with a = (n - 2) / 2, i.e. r^2 near 1.5 / (a + 2.5);
-    there the rounding of many iterations accumulates.  A sweep across that
-    point at three sample counts, against the 50-digit reference: relative
+    the routine keeps the complement up to r^2 = 3.75 / (a + 2.5) when
+    a >= 4, where 1 - I cancels two to three digits.  Sweeps across both
+    points (and the a = 4 boundary), against the 50-digit reference: relative
     1e-11 (the parity tests allow 1e-10)."""
     from oracle import oracle as orc
     rs, ns = [], []
-    for n in (1000, 6650, 24576):
+    for n in (9, 10, 11, 50, 1000, 6650, 24576):
         a = (n - 2) / 2.0
-        r0 = math.sqrt(1.5 / (a + 2.5))
-        for f in np.linspace(0.6, 1.4, 41):
-            rs.append(r0 * f)
-            ns.append(n)
+        for c in (1.5, 3.75):
+            r0 = math.sqrt(c / (a + 2.5))
+            for f in np.linspace(0.6, 1.4, 41):
+                if r0 * f < 1.0:
+                    rs.append(r0 * f)
+                    ns.append(n)
     p = _host_p(np.array(rs), np.array(ns))
     for r, n, pv in zip(rs, ns, p):
         ref = orc.pvalue_mp(float(r), int(n))
