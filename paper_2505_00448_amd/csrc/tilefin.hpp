@@ -3,8 +3,12 @@
 // of every pair, and both triangles of the symmetric outputs.
 //
 // A workgroup of FT_THREADS threads owns the pairs (g0 + i, h0 + j) of one
-// tile on or above the diagonal; thread t holds the pairs (i, j) = (t / 32 +
-// (FT_THREADS / 32) k, t mod 32), k = 0..FT_K-1.  The tile (row g0 + i) is
+// tile on or above the diagonal; thread t holds the pair (i, j) = (t / 32,
+// t mod 32) for r and n.  The p-values' continued fractions take from 2 to
+// about 28 steps, and a wave runs its slowest lane's count: the tile's
+// pairs are therefore handed to the threads for p grouped by the expected
+// count (a counting sort on six classes of the tail and of r^2 (a + 2.5)),
+// so that a wave's lanes take similar counts.  The tile (row g0 + i) is
 // written directly and its mirror (row h0 + j) through a transpose in LDS,
 // so both writes are whole rows of 32 values.
 #pragma once
@@ -22,7 +26,11 @@ struct FinSmem {
     double r[FT][FT + 1];
     double v[FT][FT + 1];  // p
     int32_t n[FT][FT + 1];
+    uint16_t order[FT * FT];  // pairs i * FT + j grouped by class
+    uint32_t cls[8];          // per class: count, then first slot
 };
+
+static_assert(FT_THREADS == FT * FT, "one pair per thread");
 
 // tile index -> (tg, th), tg <= th, row-major over the upper triangle of T x T
 __host__ __device__ inline void tile_coords(int t, int T, int& tg, int& th)
@@ -53,19 +61,52 @@ __device__ __forceinline__ bool ft_valid(int64_t g0, int64_t h0, int64_t F, int 
     return g < F && h < F && (g0 != h0 || ft_row(k) <= ft_col());
 }
 
-// p-values of the thread's valid pairs, from r and n in f (n2one: a pair of
+// class of the continued fraction's expected step count: 0 none, 1-2 the
+// complement tail (r^2 (a + 2.5) below or above 1.5), 3-5 the direct tail
+// (above 10, 6 to 10, below 6)
+__device__ __forceinline__ uint32_t ft_class(double r, int64_t n, bool n2one)
+{
+    if (n2one && n == 2 && r == r) return 0u;
+    const CorrPSetup q = corr_p_params(r, n);
+    if (q.done) return 0u;
+    const double u = r * r * (0.5 * (double)(n - 2) + 2.5);
+    if (!q.direct) return u < 1.5 ? 1u : 2u;
+    return u >= 10.0 ? 3u : (u >= 6.0 ? 4u : 5u);
+}
+
+// p-values of the tile's valid pairs, from r and n in f (n2one: a pair of
 // two samples with a defined r has p = 1, the Pearson rule; otherwise NaN),
-// left in f.v.  No barrier inside.
+// left in f.v.  Every thread of the workgroup calls it after writing its
+// pair's r and n; it contains barriers, the caller synchronises again
+// before reading f.v.
 __device__ inline void ft_pvalues(FinSmem& f, const bool (&valid)[FT_K], bool n2one)
 {
-    const int j = ft_col();
-#pragma unroll
-    for (int k = 0; k < FT_K; ++k) {
-        if (!valid[k]) continue;
-        const int i = ft_row(k);
-        const int64_t n = f.n[i][j];
-        const double rv = f.r[i][j];
-        f.v[i][j] = (n2one && n == 2 && rv == rv) ? 1.0 : corr_pvalue(rv, n);
+    const int t = threadIdx.x, i = ft_row(0), j = ft_col();
+    if (t < 8) f.cls[t] = 0u;
+    __syncthreads();
+    uint32_t c = 7u, rank = 0u;  // class 7: invalid pair
+    if (valid[0]) {
+        c = ft_class(f.r[i][j], (int64_t)f.n[i][j], n2one);
+        rank = atomicAdd(&f.cls[c], 1u);
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0u;
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t cnt = f.cls[k];
+            f.cls[k] = run;
+            run += cnt;
+        }
+    }
+    __syncthreads();
+    if (valid[0]) f.order[f.cls[c] + rank] = (uint16_t)(i * FT + j);
+    const uint32_t nvalid = f.cls[7];
+    __syncthreads();
+    if ((uint32_t)t < nvalid) {
+        const int at = f.order[t], ii = at / FT, jj = at % FT;
+        const int64_t n = f.n[ii][jj];
+        const double rv = f.r[ii][jj];
+        f.v[ii][jj] = (n2one && n == 2 && rv == rv) ? 1.0 : corr_pvalue(rv, n);
     }
 }
 
