@@ -116,9 +116,8 @@ __device__ __forceinline__ double normal_sf(double z) { return 0.5 * erfc(z * 0.
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    // DPP scan read at lane 63: no LDS traffic; the result is uniform
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(v), 63);
 }
 
 // One walk of h's sorted order for the labels g0 .. g0 + NA - 1: every kept

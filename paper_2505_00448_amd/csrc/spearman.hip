@@ -450,18 +450,29 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
     if (i < count) a[i] = 0;
 }
 
+// Wave totals by DPP row shifts and broadcasts (an inclusive scan, read at
+// lane 63): no LDS traffic, unlike lane shuffles.  The result is uniform.
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+    const auto step = [&v](int ctrl, int rmask) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, ctrl, rmask, 0xF, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), ctrl, rmask, 0xF, false);
+        v += ((uint64_t)hi << 32) | lo;
+    };
+    step(ROW_SHR + 1, 0xF);
+    step(ROW_SHR + 2, 0xF);
+    step(ROW_SHR + 4, 0xF);
+    step(ROW_SHR + 8, 0xF);
+    step(ROW_BCAST15, 0xA);
+    step(ROW_BCAST31, 0xC);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(v), 63);
 }
 
 // Tie class of each column, from its run list: 0 no ties; 1 few short runs
@@ -1374,8 +1385,9 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
                 else if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
                 else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
             }
-            sA = 4ull * wave_sum_u64(w.A4) + 2ull * wave_sum_u64(w.At) + wave_sum_u64(w.Af) + w.Au +
-                 wave_sum_u64((uint64_t)corr);
+            // one reduction of the lane's combined sums (the tie corrections
+            // may be negative: the sum is taken modulo 2^64)
+            sA = wave_sum_u64(4ull * w.A4 + 2ull * w.At + w.Af + (uint64_t)corr) + w.Au;
             d3B = tB ? wave_sum_u64(w.d3B + d3s) : 0ull;
         }
         if (lane == 0 && !DBG) {
