@@ -6,6 +6,7 @@
 
 #include "napy_internal.hpp"
 #include "pvalue.hpp"
+#include "rankbase.hpp"
 
 namespace napy {
 
@@ -66,7 +67,13 @@ int backward_run(const float* X, int64_t S, int64_t F, int64_t ldx, const double
 
 constexpr int64_t MAX_F = 65535;
 constexpr int64_t MAX_S = 2147483647;
-constexpr int64_t MAX_S_SPEARMAN = 24576;
+// Spearman and the rank tests: 16-bit sample indices and sorted positions.
+// Query subsets of a resident base compact the base's LDS-sorted orders (tie
+// flags in the positions), so the base is limited to the LDS sort's column
+// length.
+constexpr int64_t MAX_S_SPEARMAN = SPEAR_MAX_S;
+constexpr int64_t MAX_S_SUBSET = SORT_LDS_MAX_S;
+constexpr int64_t MAX_S_RANKTESTS = SPEAR_MAX_S;
 
 static int check_shape(int64_t S, int64_t F)
 {
@@ -239,7 +246,7 @@ int napy_pearson_subset(const float* X, int64_t S, int64_t F, int64_t ldx, const
 
 size_t napy_spearman_base_bytes(int64_t S, int64_t F)
 {
-    if (S < 0 || F < 1 || F > MAX_F || S > MAX_S_SPEARMAN) return 0;
+    if (S < 0 || F < 1 || F > MAX_F || S > MAX_S_SUBSET) return 0;
     return spearman_base_bytes(S, F);
 }
 
@@ -248,7 +255,7 @@ int napy_spearman_base_prepare(const float* X, int64_t S, int64_t F, int64_t ldx
 {
     if (!opts_ok(opts)) return NAPY_E_INVALID;
     NAPY_TRY(check_shape(S, F));
-    if (S > MAX_S_SPEARMAN) return NAPY_E_UNSUPPORTED;
+    if (S > MAX_S_SUBSET) return NAPY_E_UNSUPPORTED;
     if ((!X && S > 0) || ldx < F) return NAPY_E_INVALID;
     if (!base || base_bytes < spearman_base_bytes(S, F) || ((uintptr_t)base & 255)) return NAPY_E_WORKSPACE;
     return spearman_base_prepare_run(X, S, F, ldx, base, opts, (hipStream_t)stream);
@@ -256,7 +263,7 @@ int napy_spearman_base_prepare(const float* X, int64_t S, int64_t F, int64_t ldx
 
 size_t napy_spearman_subset_workspace(int64_t S, int64_t Sq, int64_t Fq, const napy_opts* opts)
 {
-    if (S < 0 || Sq < 0 || Sq > S || Fq < 1 || Fq > MAX_F || S > MAX_S_SPEARMAN || !opts_ok(opts)) return 0;
+    if (S < 0 || Sq < 0 || Sq > S || Fq < 1 || Fq > MAX_F || S > MAX_S_SUBSET || !opts_ok(opts)) return 0;
     return spearman_subset_ws_bytes(S, Sq, Fq);
 }
 
@@ -267,7 +274,7 @@ int napy_spearman_subset(const void* base, int64_t S, int64_t F, const int32_t* 
     if (!opts_ok(opts)) return NAPY_E_INVALID;
     NAPY_TRY(check_shape(S, F));
     NAPY_TRY(check_shape(Sq, Fq));
-    if (S > MAX_S_SPEARMAN) return NAPY_E_UNSUPPORTED;
+    if (S > MAX_S_SUBSET) return NAPY_E_UNSUPPORTED;
     if (!base || (!rows && Sq > 0) || !cols) return NAPY_E_INVALID;
     if (ldo < Fq || Sq > S || Fq > F) return NAPY_E_INVALID;
     if (!ws || ws_bytes < spearman_subset_ws_bytes(S, Sq, Fq) || ((uintptr_t)ws & 255)) return NAPY_E_WORKSPACE;
@@ -341,8 +348,8 @@ int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
 static int check_ranks(int64_t S, int64_t FC, int64_t FQ, int ncat)
 {
     NAPY_TRY(check_groups(S, FC, FQ, ncat));
-    if (S > MAX_S_SPEARMAN) {
-        set_last_error("rank tests support S <= %lld samples (got %lld)", (long long)MAX_S_SPEARMAN, (long long)S);
+    if (S > MAX_S_RANKTESTS) {
+        set_last_error("rank tests support S <= %lld samples (got %lld)", (long long)MAX_S_RANKTESTS, (long long)S);
         return NAPY_E_UNSUPPORTED;
     }
     return NAPY_OK;

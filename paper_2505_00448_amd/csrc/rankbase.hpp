@@ -32,6 +32,15 @@ struct SpearBase {
 inline int64_t spear_ld(int64_t S) { return round_up(S + 1, 256); }
 // sorted orders may be read up to this many entries past the last row
 constexpr int64_t ORD_TAIL = 512;
+// Columns of up to SORT_LDS_MAX_S samples are sorted in LDS (their sorted
+// positions keep a tie flag in bit 15); longer ones, up to SPEAR_MAX_S (16-bit
+// sample indices and positions, 0xFFFF meaning "missing"), over global
+// memory, with positions only.
+constexpr int64_t SORT_LDS_MAX_S = 24576;
+constexpr int64_t SPEAR_MAX_S = 65535;
+// 32-bit words of the keys buffer the sort uses: one plane of F x ld keys, or
+// four (keys and sample indices, twice) for long columns
+inline int64_t sort_keys_words(int64_t S, int64_t F) { return F * spear_ld(S) * (S > SORT_LDS_MAX_S ? 4 : 1); }
 // value groups (tie runs plus untied positions) of a column whose ranks the
 // pair scan takes from a per-partner table in LDS
 constexpr int RUN_GROUPS_MAX = 23;

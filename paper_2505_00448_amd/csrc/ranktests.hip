@@ -59,7 +59,7 @@ static int64_t rk_dmax(int64_t S) { return (int64_t)RK_EXACT_MAXM * (S > 0 ? S :
 static void rk_carve(Carver& c, int64_t S, int64_t FC, int64_t FQ, bool mwu, RankWs& w)
 {
     base_carve(c, S, FQ, w.base);
-    c.take<uint32_t>((size_t)FQ * spear_ld(S));  // keys buffer of the sort
+    c.take<uint32_t>((size_t)sort_keys_words(S, FQ));  // keys buffer of the sort
     w.lab = c.take<uint8_t>((size_t)FC * spear_ld(S));
     w.catmask = c.take<uint64_t>(FC);
     w.bad = c.take<int32_t>(FC);
@@ -118,6 +118,28 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
     // DPP scan read at lane 63: no LDS traffic; the result is uniform
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(v), 63);
+}
+
+template <int CTRL, int RMASK>
+__device__ __forceinline__ uint64_t rk_dpp_step_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RMASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RMASK, 0xF, false);
+    return v + (((uint64_t)hi << 32) | lo);
+}
+
+// 64-bit wave total by DPP scans (modulo 2^64); uniform
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+    constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+    v = rk_dpp_step_u64<ROW_SHR + 1, 0xF>(v);
+    v = rk_dpp_step_u64<ROW_SHR + 2, 0xF>(v);
+    v = rk_dpp_step_u64<ROW_SHR + 4, 0xF>(v);
+    v = rk_dpp_step_u64<ROW_SHR + 8, 0xF>(v);
+    v = rk_dpp_step_u64<ROW_BCAST15, 0xA>(v);
+    v = rk_dpp_step_u64<ROW_BCAST31, 0xC>(v);
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
 }
 
 // One walk of h's sorted order for the labels g0 .. g0 + NA - 1: every kept
@@ -190,7 +212,7 @@ __device__ __forceinline__ uint32_t rank_walk(const uint16_t* __restrict__ ordH,
 // t + 1 - 2 j.  Adds t^3 - t per run to `tie` when `tieterm`.
 template <int NA>
 __device__ __forceinline__ void rank_short_runs(const uint16_t* __restrict__ ordH, const uint32_t* __restrict__ rl,
-                                                int nr, const uint8_t* labL, int g0, int lane, uint32_t (&acc)[NA],
+                                                int nr, const uint8_t* labL, int g0, int lane, int64_t (&corr)[NA],
                                                 bool tieterm, double& tie)
 {
     for (int r = lane; r < nr; r += 64) {
@@ -213,7 +235,7 @@ __device__ __forceinline__ void rank_short_runs(const uint16_t* __restrict__ ord
             }
         }
 #pragma unroll
-        for (int k = 0; k < NA; ++k) acc[k] += nkr[k] * (t + 1u) - 2u * jsum[k];  // modulo 2^32
+        for (int k = 0; k < NA; ++k) corr[k] += (int64_t)nkr[k] * (t + 1u) - 2 * (int64_t)jsum[k];
         if (tieterm) {
             const double td = (double)t;
             tie += td * td * td - td;
@@ -225,7 +247,7 @@ __device__ __forceinline__ void rank_short_runs(const uint16_t* __restrict__ ord
 // The labels are summed in windows of NW (one walk per window), which bounds
 // the per-lane accumulators (in LDS for NW > 2) for up to 32 categories.  With two labels only
 // label 0 is summed: label 1 holds the rest of n (n + 1) and of n.
-template <int NW>
+template <int NW, bool LABG>
 __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const uint8_t* __restrict__ lab, int64_t S,
                                                           int64_t FC, int64_t FQ, int test, int ncat,
                                                           const uint64_t* __restrict__ catmask,
@@ -240,14 +262,16 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
     __shared__ double res[RK_WAVES][2][32];  // per wave: doubled rank sums, counts
     const int64_t ld = bs.ld;
     const int nwp = (int)((S + 1 + 31) / 32) + 1;  // table entries per wave
-    uint8_t* labL = rk_smem;
-    uint2* tabs = (uint2*)(rk_smem + round_up(ld, 16));
     const int64_t g = blockIdx.x;
+    // labels: copied to LDS, or read from global memory when the tables of
+    // long columns leave no room for them (LABG)
+    const uint8_t* labL = LABG ? lab + g * ld : rk_smem;
+    uint2* tabs = (uint2*)(rk_smem + (LABG ? 0 : round_up(ld, 16)));
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    {
+    if constexpr (!LABG) {
         const uint4* src = (const uint4*)(lab + g * ld);
-        uint4* dst = (uint4*)labL;
+        uint4* dst = (uint4*)rk_smem;
         for (int64_t k = threadIdx.x; k < ld / 16; k += RK_THREADS) dst[k] = src[k];
     }
     __syncthreads();
@@ -296,10 +320,14 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
 
     uint32_t ntot = 0;
     for (int g0 = 0; g0 < ncat; g0 += NW) {
-        uint32_t acc[NA];  // doubled rank sums (or their corrections) of this lane, modulo 2^32
-        uint32_t cnt[NA];  // wave-uniform counts
+        uint32_t acc[NA];   // doubled rank sums of this lane (each below 2^32)
+        int64_t corr[NA];   // this lane's corrections for short tie runs
+        uint32_t cnt[NA];   // wave-uniform counts
 #pragma unroll
-        for (int k = 0; k < NA; ++k) acc[k] = cnt[k] = 0u;
+        for (int k = 0; k < NA; ++k) {
+            acc[k] = cnt[k] = 0u;
+            corr[k] = 0;
+        }
         if constexpr (LDSACC) {
 #pragma unroll
             for (int k = 0; k < NA; ++k) accw[k * 64 + lane] = 0ull;
@@ -309,7 +337,7 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
             ntot = rank_walk<NA, true, LDSACC>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt, accw);
         } else {
             ntot = rank_walk<NA, false, LDSACC>(ordH, runsH, tbH, labL, tab, nch, g0, lane, acc, cnt, accw);
-            if (mode == 1) rank_short_runs<NA>(ordH, rl, nr, labL, g0, lane, acc, g0 == 0, tie);
+            if (mode == 1) rank_short_runs<NA>(ordH, rl, nr, labL, g0, lane, corr, g0 == 0, tie);
         }
         if constexpr (LDSACC) {
             wave_sync_lds();
@@ -322,8 +350,8 @@ __global__ __launch_bounds__(RK_THREADS) void k_rank_walk(SpearBase bs, const ui
         }
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
-            // the label's total is below 2^32, so the modular sum is exact
-            const uint32_t r2sum = wave_sum_u32(acc[k]);
+            // 64-bit totals (the corrections may be negative: modulo 2^64)
+            const uint64_t r2sum = wave_sum_u64((uint64_t)acc[k]) + wave_sum_u64((uint64_t)corr[k]);
             if (lane == 0 && g0 + k < 32) {
                 res[wave][0][g0 + k] = (double)r2sum;
                 res[wave][1][g0 + k] = (double)cnt[k];
@@ -475,19 +503,31 @@ __global__ __launch_bounds__(RK_EX_THREADS) void k_mwu_exact(const uint32_t* __r
     }
 }
 
+template <int NW, bool LABG>
+static int walk_launch_t(const RankWs& w, int64_t S, int64_t FC, int64_t FQ, int test, int ncat, double* stat,
+                         double* p, int32_t* n, int64_t ldo, size_t smem, hipStream_t st)
+{
+    static std::atomic<uint64_t> attr_done{0};
+    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_rank_walk<NW, LABG>,
+                            (int)(160 * 1024 - sizeof(double) * RK_WAVES * 64), "hipFuncSetAttribute(k_rank_walk)"));
+    hipLaunchKernelGGL((k_rank_walk<NW, LABG>), dim3((unsigned)FC, (unsigned)ceil_div(FQ, RK_WAVES)), dim3(RK_THREADS),
+                       smem, st, w.base, w.lab, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo, w.nexact,
+                       w.exact);
+    return check_launch("rank walk");
+}
+
 template <int NW>
 static int walk_launch(const RankWs& w, int64_t S, int64_t FC, int64_t FQ, int test, int ncat, double* stat,
                        double* p, int32_t* n, int64_t ldo, hipStream_t st)
 {
-    const size_t smem = (size_t)round_up(w.base.ld, 16) + (size_t)RK_WAVES * ((S + 1 + 31) / 32 + 1) * 8 +
-                        (NW > 2 ? (size_t)RK_WAVES * NW * 64 * 8 : 0);
-    static std::atomic<uint64_t> attr_done{0};
-    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_rank_walk<NW>, (int)(160 * 1024 - sizeof(double) * RK_WAVES * 64),
-                            "hipFuncSetAttribute(k_rank_walk)"));
-    hipLaunchKernelGGL(k_rank_walk<NW>, dim3((unsigned)FC, (unsigned)ceil_div(FQ, RK_WAVES)), dim3(RK_THREADS), smem,
-                       st, w.base, w.lab, S, FC, FQ, test, ncat, w.catmask, w.bad, stat, p, n, ldo, w.nexact,
-                       w.exact);
-    return check_launch("rank walk");
+    const size_t tables =
+        (size_t)RK_WAVES * ((S + 1 + 31) / 32 + 1) * 8 + (NW > 2 ? (size_t)RK_WAVES * NW * 64 * 8 : 0);
+    const size_t with_labels = (size_t)round_up(w.base.ld, 16) + tables;
+    const size_t limit = 160 * 1024 - sizeof(double) * RK_WAVES * 64;
+    if (with_labels <= limit)
+        return walk_launch_t<NW, false>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, with_labels, st);
+    if (tables > limit) return NAPY_E_UNSUPPORTED;
+    return walk_launch_t<NW, true>(w, S, FC, FQ, test, ncat, stat, p, n, ldo, tables, st);
 }
 
 int ranktests_run(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t S, int64_t FC, int64_t FQ,

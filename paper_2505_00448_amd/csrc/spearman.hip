@@ -45,7 +45,7 @@
 
 namespace napy {
 
-constexpr int SPEARMAN_MAX_S = 24576;
+constexpr int SPEARMAN_MAX_S = (int)SORT_LDS_MAX_S;  // longest column of the LDS sort
 // column sort: 1024 threads (16 waves) and up to CS_EPT_MAX keys per thread
 constexpr int CS_THREADS = 1024;
 constexpr int CS_WAVES = CS_THREADS / 64;
@@ -405,6 +405,293 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
 }
 
 // ---------------------------------------------------------------------------
+// per-column sort of long columns (more than SPEARMAN_MAX_S samples)
+// ---------------------------------------------------------------------------
+// The same LSD radix sort (4 stable passes of 8-bit digits, keys ranked
+// within each wave by ballot digit matching) over global memory, one
+// workgroup per column, in tiles of BS_TILE sorted slots taken in order:
+// a key's destination is its digit's base in the whole column (from the
+// column's histograms of all four digits, taken while the observed keys are
+// compacted), plus the keys of that digit in earlier tiles, plus those in
+// earlier waves of its tile, plus its rank in its wave.  Keys and sample
+// indices alternate between two buffers (u32 each: the keys buffer's four
+// planes A, B, I, J).  The tail takes two sweeps: the first finds each
+// position's run start (a max-scan carried across steps, waves and tiles),
+// records each run's end at its start and numbers the tie runs in position
+// order; the second writes ord, pos (positions only: no tie flag, which the
+// 16-bit positions of these lengths need all their bits for), runs, the
+// tie-run list and the tie bits.  Between phases each thread's global
+// writes are made visible to the workgroup's later reads (device fence).
+constexpr int BS_ET = 8;                     // sorted slots per thread and tile
+constexpr int BS_TILE = CS_THREADS * BS_ET;  // 8192
+
+__global__ __launch_bounds__(CS_THREADS) void k_colsort_big(uint32_t* __restrict__ keys, int64_t S, int64_t ld,
+                                                            int64_t F, SpearBase out)
+{
+    __shared__ uint16_t wcnt[CS_WAVES][256];
+    __shared__ uint32_t hist[4][256];  // digit counts, then each pass's digit bases
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t red[4][CS_WAVES];
+    const int col = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t plane = F * ld;
+    uint32_t* kA = keys + (int64_t)col * ld;  // raw keys, then the compacted keys
+    uint32_t* kB = kA + plane;
+    uint32_t* iA = kA + 2 * plane;
+    uint32_t* iB = kA + 3 * plane;
+    uint16_t* ordc = out.ord + (int64_t)col * ld;
+    uint16_t* posc = out.pos + (int64_t)col * ld;
+    uint32_t* runc = out.runs + (int64_t)col * ld;
+    uint32_t* rlc = out.rlist + (int64_t)col * (ld / 2);
+    const int64_t nwords = ld / 64;
+    uint64_t* tbc = out.tbits + (int64_t)col * nwords;
+
+    for (int i = t; i < 4 * 256; i += CS_THREADS) (&hist[0][0])[i] = 0u;
+    __syncthreads();
+    // ---- compaction (in place: a tile's keys are read before any of its
+    // compacted keys are written, and those land below the tile's end) ----
+    uint32_t n = 0u, kor = 0u, kand = 0xFFFFFFFFu;
+    for (int64_t t0 = 0; t0 < S; t0 += BS_TILE) {
+        uint32_t key[BS_ET];
+        uint32_t nobs = 0u;
+#pragma unroll
+        for (int e = 0; e < BS_ET; ++e) {
+            const int64_t j = t0 + (int64_t)e * CS_THREADS + t;
+            key[e] = j < S ? kA[j] : 0xFFFFFFFFu;
+            const bool obs = key[e] != 0xFFFFFFFFu;
+            if (!obs && j < S) posc[j] = 0xFFFF;  // missing sample
+            if (obs) {
+                ++nobs;
+                kor |= key[e];
+                kand &= key[e];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) atomicAdd(&hist[p][(key[e] >> (8 * p)) & 255u], 1u);
+            }
+        }
+        const uint32_t incl = wave_incl_scan_u32(nobs);
+        if (lane == 63) red[0][wave] = incl;
+        __syncthreads();
+        uint32_t base = n + incl - nobs, tot = 0u;
+#pragma unroll
+        for (int v = 0; v < CS_WAVES; ++v) {
+            const uint32_t tv = red[0][v];
+            base += v < wave ? tv : 0u;
+            tot += tv;
+        }
+#pragma unroll
+        for (int e = 0; e < BS_ET; ++e) {
+            if (key[e] != 0xFFFFFFFFu) {
+                kA[base] = key[e];
+                iA[base] = (uint32_t)(t0 + (int64_t)e * CS_THREADS + t);
+                ++base;
+            }
+        }
+        n += tot;
+        __syncthreads();  // red reused
+    }
+    // bits in which some observed key differs (all observed keys agree on the
+    // others): a pass over a constant digit is skipped
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+        kor |= (uint32_t)__shfl_xor((int)kor, dd, 64);
+        kand &= (uint32_t)__shfl_xor((int)kand, dd, 64);
+    }
+    if (lane == 0) {
+        red[1][wave] = kor;
+        red[2][wave] = kand;
+    }
+    // digit bases: exclusive scans of the four histograms (four waves)
+    __syncthreads();
+    if (wave < 4) {
+        uint32_t c4[4], sum = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            c4[i] = hist[wave][4 * lane + i];
+            sum += c4[i];
+        }
+        uint32_t acc = wave_incl_scan_u32(sum) - sum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            hist[wave][4 * lane + i] = acc;
+            acc += c4[i];
+        }
+    }
+    uint32_t vor = 0u, vand = 0xFFFFFFFFu;
+#pragma unroll
+    for (int v = 0; v < CS_WAVES; ++v) {
+        vor |= red[1][v];
+        vand &= red[2][v];
+    }
+    const uint32_t diff = n > 0u ? (vor ^ vand) : 0u;
+    __threadfence();
+    __syncthreads();
+
+    // ---- 4 passes ------------------------------------------------------------
+    uint16_t* wc = &wcnt[wave][0];
+    int cur = 0;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        if (((diff >> shift) & 255u) == 0u) continue;  // uniform
+        const uint32_t* sk = cur ? kB : kA;
+        const uint32_t* si = cur ? iB : iA;
+        uint32_t* dk = cur ? kA : kB;
+        uint32_t* di = cur ? iA : iB;
+        if (t < 256) run[t] = 0u;
+        for (int64_t t0 = 0; t0 < (int64_t)n; t0 += BS_TILE) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wc[q * 64 + lane] = 0;
+            uint32_t key[BS_ET], ix[BS_ET], rk[BS_ET];
+#pragma unroll
+            for (int e = 0; e < BS_ET; ++e) {
+                const int64_t k = t0 + (int64_t)wave * 64 * BS_ET + 64 * e + lane;
+                const bool valid = k < (int64_t)n;
+                key[e] = valid ? sk[k] : 0u;
+                ix[e] = valid ? si[k] : 0u;
+                const uint64_t vm = __ballot(valid);
+                if (vm == 0ull) continue;  // uniform
+                const uint32_t d = (key[e] >> shift) & 255u;
+                const uint64_t peers = match_digit8(d) & vm;
+                const uint32_t below = lanes_below(peers);
+                const uint32_t cnt = (uint32_t)__popcll(peers);
+                if (valid) {
+                    const uint32_t b = wc[d];
+                    if (below + 1u == cnt) wc[d] = (uint16_t)(b + cnt);  // last of the peers
+                    rk[e] = b + below;
+                }
+            }
+            __syncthreads();
+            // destinations per (digit, wave): the digit's base, its keys in
+            // earlier tiles and in earlier waves of this tile
+            if (t < 256) {
+                uint32_t acc = hist[pass][t] + run[t];
+#pragma unroll
+                for (int v = 0; v < CS_WAVES; ++v) {
+                    const uint32_t c = wcnt[v][t];
+                    wcnt[v][t] = (uint16_t)acc;
+                    acc += c;
+                }
+                run[t] = acc - hist[pass][t];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < BS_ET; ++e) {
+                const int64_t k = t0 + (int64_t)wave * 64 * BS_ET + 64 * e + lane;
+                if (k < (int64_t)n) {
+                    const uint32_t dst = (uint32_t)wc[(key[e] >> shift) & 255u] + rk[e];
+                    dk[dst] = key[e];
+                    di[dst] = ix[e];
+                }
+            }
+            __syncthreads();  // wcnt read by the destinations above
+        }
+        __threadfence();
+        __syncthreads();
+        cur ^= 1;
+    }
+    const uint32_t* sk = cur ? kB : kA;  // sorted keys
+    const uint32_t* si = cur ? iB : iA;  // their sample indices
+    uint32_t* END = cur ? kA : kB;       // END[s]: end of the run starting at s
+    uint32_t* RID = cur ? iA : iB;       // RID[s]: index of the tie run starting at s
+
+    // ---- tail, sweep 1: run starts (into runc for now), ends, tie-run numbers
+    int tcarry = 0;       // latest run start so far (uniform)
+    uint32_t trid = 0u;   // tie runs so far (uniform)
+    for (int64_t t0 = 0; t0 < (int64_t)n; t0 += BS_TILE) {
+        int sp[BS_ET];
+        uint32_t fl[BS_ET];
+        int carry = 0;
+        uint32_t ntr = 0u;
+#pragma unroll
+        for (int e = 0; e < BS_ET; ++e) {
+            const int64_t k = t0 + (int64_t)wave * 64 * BS_ET + 64 * e + lane;
+            uint32_t f = 0u;
+            if (k < (int64_t)n) {
+                const uint32_t key = sk[k];
+                const bool st = k == 0 || sk[k - 1] != key;
+                const bool ls = k + 1 == (int64_t)n || sk[k + 1] != key;
+                f = (st ? 1u : 0u) | (ls ? 2u : 0u);
+            }
+            fl[e] = f;
+            ntr += (uint32_t)__popcll(__ballot(f == 1u));
+            const int x = max(wave_incl_max_scan((f & 1u) ? (int)k : 0), carry);
+            carry = __builtin_amdgcn_readlane(x, 63);
+            sp[e] = x;
+        }
+        if (lane == 0) {
+            red[0][wave] = (uint32_t)carry;
+            red[1][wave] = ntr;
+        }
+        __syncthreads();
+        int cin = tcarry;
+        uint32_t rid = trid, tmax = (uint32_t)tcarry, ttot = 0u;
+#pragma unroll
+        for (int v = 0; v < CS_WAVES; ++v) {
+            const uint32_t c = red[0][v], r = red[1][v];
+            if (v < wave) {
+                cin = max(cin, (int)c);
+                rid += r;
+            }
+            tmax = max(tmax, c);
+            ttot += r;
+        }
+#pragma unroll
+        for (int e = 0; e < BS_ET; ++e) {
+            const int64_t k = t0 + (int64_t)wave * 64 * BS_ET + 64 * e + lane;
+            const int s0 = max(sp[e], cin);
+            if (k < (int64_t)n) {
+                runc[k] = (uint32_t)s0;
+                if (fl[e] & 2u) END[s0] = (uint32_t)(k + 1);
+            }
+            const uint64_t m = __ballot(fl[e] == 1u);
+            if (fl[e] == 1u) RID[k] = rid + lanes_below(m);
+            rid += (uint32_t)__popcll(m);
+        }
+        tcarry = (int)tmax;
+        trid += ttot;
+        __syncthreads();  // red reused
+    }
+    __threadfence();
+    __syncthreads();
+    // ---- tail, sweep 2 --------------------------------------------------------
+    uint32_t ntied = 0u;
+    for (int64_t t0 = 0; t0 < (int64_t)n; t0 += BS_TILE) {
+#pragma unroll
+        for (int e = 0; e < BS_ET; ++e) {
+            const int64_t k = t0 + (int64_t)wave * 64 * BS_ET + 64 * e + lane;
+            bool tied = false;
+            if (k < (int64_t)n) {
+                const uint32_t s0 = runc[k], e0 = END[s0];
+                tied = e0 - s0 > 1u;
+                const uint32_t ix = si[k];
+                ordc[k] = (uint16_t)ix;
+                posc[ix] = (uint16_t)k;
+                runc[k] = s0 | (e0 << 16);
+                if (tied && (uint32_t)k == s0) rlc[RID[s0]] = s0 | (e0 << 16);
+            }
+            const uint64_t m = __ballot(tied);
+            const int64_t w0 = (t0 + (int64_t)wave * 64 * BS_ET + 64 * e) >> 6;
+            if (lane == 0 && w0 < nwords && w0 * 64 < (int64_t)n) tbc[w0] = m;
+            ntied += (uint32_t)__popcll(m);
+        }
+    }
+    for (int64_t k = (int64_t)n + t; k < ld; k += CS_THREADS) ordc[k] = (uint16_t)S;
+    for (int64_t i = S + t; i < ld; i += CS_THREADS) posc[i] = 0xFFFF;
+    for (int64_t w = ((int64_t)n + 63) / 64 + t; w < nwords; w += CS_THREADS) tbc[w] = 0ull;
+    if (col == (int)gridDim.x - 1)
+        for (int64_t k = t; k < ORD_TAIL; k += CS_THREADS) ordc[ld + k] = (uint16_t)S;
+    if (lane == 0) red[2][wave] = ntied;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t tc = 0u;
+        for (int v = 0; v < CS_WAVES; ++v) tc += red[2][v];
+        out.ncol[col] = (int32_t)n;
+        out.hasties[col] = tc > 0u ? 1 : 0;
+        out.nruns[col] = (int32_t)trid;
+        out.tcount[col] = (int32_t)tc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // per-pair re-ranking scan
 // ---------------------------------------------------------------------------
 struct PairOut {
@@ -450,22 +737,27 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
     if (i < count) a[i] = 0;
 }
 
+// one step of a 64-bit inclusive scan over the wave: the value of the lane
+// CTRL selects (0 where there is none or its row is masked off) added
+template <int CTRL, int RMASK>
+__device__ __forceinline__ uint64_t dpp_step_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RMASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RMASK, 0xF, false);
+    return v + (((uint64_t)hi << 32) | lo);
+}
+
 // Wave totals by DPP row shifts and broadcasts (an inclusive scan, read at
 // lane 63): no LDS traffic, unlike lane shuffles.  The result is uniform.
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {
     constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
-    const auto step = [&v](int ctrl, int rmask) {
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, ctrl, rmask, 0xF, false);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), ctrl, rmask, 0xF, false);
-        v += ((uint64_t)hi << 32) | lo;
-    };
-    step(ROW_SHR + 1, 0xF);
-    step(ROW_SHR + 2, 0xF);
-    step(ROW_SHR + 4, 0xF);
-    step(ROW_SHR + 8, 0xF);
-    step(ROW_BCAST15, 0xA);
-    step(ROW_BCAST31, 0xC);
+    v = dpp_step_u64<ROW_SHR + 1, 0xF>(v);
+    v = dpp_step_u64<ROW_SHR + 2, 0xF>(v);
+    v = dpp_step_u64<ROW_SHR + 4, 0xF>(v);
+    v = dpp_step_u64<ROW_SHR + 8, 0xF>(v);
+    v = dpp_step_u64<ROW_BCAST15, 0xA>(v);
+    v = dpp_step_u64<ROW_BCAST31, 0xC>(v);
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
 }
@@ -683,6 +975,27 @@ __device__ __forceinline__ uint32_t ra_of_tied(const uint2* tab, const uint32_t*
 // XS for a table lookup).
 constexpr uint32_t MISS_GROUPED = (uint32_t)RUN_TABLE_MAX;
 
+// Doubled rank R_a of a complete sample from a's stored code pv (not the
+// missing code).  TA 0: a untied, pv the position; 1: a tied, a tied
+// sample's pv is POS_TIED plus its run's number; 2: pv an index into the
+// run-rank table; 3 and 4 (columns longer than the LDS sort handles): pv the
+// position, a untied (3) or tied (4), a tied sample found by its run in a's
+// runs array by position (rlA then points at that array).
+template <int TA>
+__device__ __forceinline__ uint32_t a_rank(uint32_t pv, const uint2* tab, const uint32_t* __restrict__ rlA,
+                                           const uint32_t* rrun)
+{
+    if constexpr (TA == 2) return rrun[pv];
+    if constexpr (TA == 1) {
+        if (pv & POS_TIED) return ra_of_tied(tab, rlA, rrun, pv);
+    }
+    if constexpr (TA == 4) {
+        const uint32_t rr = rlA[pv];
+        if ((rr >> 16) - (rr & 0xFFFFu) > 1u) return ra_run(tab, rr);
+    }
+    return 2u * cnt1(tab, pv);
+}
+
 // One chunk of 64 positions of b's sorted order without tied b-positions.
 // b's C1 = carry1 + (complete samples at lower lanes) by mbcnt; a sample is
 // complete when its a-position is not `miss`.  TA = 0 (a untied) or 1 (a
@@ -703,6 +1016,31 @@ __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, cons
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, carry1));
     if constexpr (TA == 2) {
         t32 += __umul24(rrun[pv], cb1);
+    } else if constexpr (TA >= 3) {
+        // long columns: positions up to 65534 (C1 and R up to 2^17), so the
+        // products go straight into 64 bits, the untied ones doubled (R_a R_b
+        // = 4 C1_a C1_b, and sAt carries weight 2)
+        bool tied = false;
+        uint32_t rr = 0u;
+        if constexpr (TA == 4) {
+            if (kept) {
+                rr = rlA[pv];
+                tied = (rr >> 16) - (rr & 0xFFFFu) > 1u;
+            }
+        }
+        const uint32_t ca1 = (kept && !tied) ? cnt1(tab, pv) : 0u;
+        sAt += 2ull * ((uint64_t)ca1 * cb1);
+        uint32_t ra = 0u;
+        if (tied) {
+            ra = ra_run(tab, rr);
+            sAt += (uint64_t)ra * cb1;
+        }
+        if constexpr (DBG) {
+            if (kept) {
+                dbg_ra[iv] = (int32_t)(tied ? ra : 2u * ca1);
+                dbg_rb[iv] = (int32_t)(2u * cb1);
+            }
+        }
     } else {
         const uint32_t ca1 = cnt1(tab, TA == 0 ? pv : min(pv, XS));
         t32 += __umul24(ca1, cb1);
@@ -828,6 +1166,8 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                 uint32_t Ra;
                 if constexpr (TA == 2) {
                     Ra = rrun[pvu];
+                } else if constexpr (TA >= 3) {
+                    Ra = kept ? a_rank<TA>(pvu, tab, rlA, rrun) : 0u;
                 } else {
                     Ra = 2u * cnt1(tab, min(pvu, XS));
                     if constexpr (TA == 1) {
@@ -847,7 +1187,7 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                     const uint32_t e0 = __builtin_amdgcn_readlane(re, 0);
                     if (e0 <= lo + 64u) {
                         const uint32_t r_open = __builtin_amdgcn_readlane(Rb, 0);
-                        uA += (uint64_t)r_open * wave_sum_u32(pend_lane);
+                        uA += (uint64_t)r_open * (TA >= 3 ? wave_sum_u64((uint64_t)pend_lane) : (uint64_t)wave_sum_u32(pend_lane));
                         if constexpr (DBG) {
                             // report the settled rank of every complete sample of the run
                             const uint32_t s0 = __builtin_amdgcn_readlane(rs, 0);
@@ -916,10 +1256,7 @@ __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__
             const uint32_t pv = posA[ordB[k]];
             if (pv == miss) continue;
             ++t;
-            uint32_t Ra;
-            if (TA == 2) Ra = rrun[pv];
-            else if (TA != 0 && (pv & POS_TIED)) Ra = ra_of_tied(tab, rlA, rrun, pv);
-            else Ra = 2u * cnt1(tab, pv);
+            const uint32_t Ra = a_rank<TA>(pv, tab, rlA, rrun);
             sra += Ra;
             sraj += (uint64_t)Ra * t;
         }
@@ -988,6 +1325,8 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
             uint32_t Ra;
             if constexpr (TA == 2) {
                 Ra = rrun[p];  // 0 for a missing sample
+            } else if constexpr (TA >= 3) {
+                Ra = kept ? a_rank<TA>(p, tab, rlA, rrun) : 0u;
             } else {
                 Ra = 2u * cnt1(tab, min(p, XS));
                 if constexpr (TA == 1)
@@ -1001,7 +1340,8 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
                 acc += v;
                 t += (uint32_t)__popcll(__ballot(v != 0u));
                 val = in ? 0u : val;
-                const uint32_t sra = wave_sum_u32(acc);  // below 2^32: t * (2 S + 1)
+                // below t (2 S + 1): 32 bits for the LDS-sorted lengths
+                const uint64_t sra = TA >= 3 ? wave_sum_u64((uint64_t)acc) : (uint64_t)wave_sum_u32(acc);
                 tot += (uint64_t)(2u * carry + t + 1u) * sra;
                 if (t > 1u) d3 += cube_minus(t);
                 carry += t;
@@ -1016,7 +1356,7 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
     }
     if (gcur < G) {
         // the last group ends with the walked chunks (nbv a multiple of 64 U)
-        const uint32_t sra = wave_sum_u32(acc);
+        const uint64_t sra = TA >= 3 ? wave_sum_u64((uint64_t)acc) : (uint64_t)wave_sum_u32(acc);
         tot += (uint64_t)(2u * carry + t + 1u) * sra;
         if (t > 1u) d3 += cube_minus(t);
         carry += t;
@@ -1151,14 +1491,15 @@ struct PairSmem {
     int nwp;  // table entries per partner
 };
 
-// posA: positions of samples 0..S (S is the dummy); tab: PB partner tables;
-// corr: PB tie-defect sums; rrun: [PB][RUN_TABLE_STRIDE] run ranks
-__host__ __device__ inline PairSmem pair_smem(int64_t ld, int64_t S, int PB)
+// posA: positions of samples 0..S (S is the dummy; not in LDS for long
+// columns, big); tab: PB partner tables; corr: PB tie-defect sums; rrun:
+// [PB][RUN_TABLE_STRIDE] run ranks
+__host__ __device__ inline PairSmem pair_smem(int64_t ld, int64_t S, int PB, bool big = false)
 {
     (void)ld;
     PairSmem m;
     m.nwp = (int)((S + 1 + 31) / 32) + 1;
-    m.off_tab = (size_t)round_up(2 * (S + 1), 16);
+    m.off_tab = big ? 0 : (size_t)round_up(2 * (S + 1), 16);
     m.off_corr = m.off_tab + (size_t)PB * m.nwp * 8;
     m.off_rrun = m.off_corr + (size_t)PB * 8;
     m.bytes = m.off_rrun + (size_t)PB * RUN_TABLE_STRIDE * 4;
@@ -1185,7 +1526,11 @@ __host__ inline int64_t pair_grid_size(int64_t F, int64_t nbp, int PB)
     return pair_band_start(G - 1, nbp, PB) + (F - rows * (G - 1)) * (nbp - 8 * (G - 1));
 }
 
-template <int PB, bool DBG>
+// BIG (columns longer than the LDS sort handles): only the partner tables
+// live in LDS; a's positions (no tie flag) and the partner block's presence
+// bytes are read from global memory, a tied a-sample is recognised by its
+// run (TA 4), and products are summed in 64 bits.
+template <int PB, bool DBG, bool BIG>
 __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint8_t* __restrict__ presb,
                                                                  int64_t S, int64_t F, int64_t nbp, PairOut po)
 {
@@ -1213,8 +1558,8 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const int64_t a = DBG ? po.dbg_a : bs.perm[la];
 
     const int64_t ld = bs.ld;
-    const PairSmem L = pair_smem(ld, S, PB);
-    uint16_t* posA = (uint16_t*)smem_raw;
+    const PairSmem L = pair_smem(ld, S, PB, BIG);
+    uint16_t* posA = BIG ? bs.pos + a * ld : (uint16_t*)smem_raw;
     uint2* tab = (uint2*)(smem_raw + L.off_tab);                               // [PB][nwp]
     unsigned long long* corrA = (unsigned long long*)(smem_raw + L.off_corr);  // [PB]
     uint32_t* rrun = (uint32_t*)(smem_raw + L.off_rrun);                       // [PB][RUN_TABLE_STRIDE]
@@ -1223,18 +1568,20 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     const int tA = bs.hasties[a];
     const uint16_t* ordA = bs.ord + a * ld;
     const uint32_t* rlA = bs.rlist + a * (ld / 2);
+    const uint32_t* runsA = bs.runs + a * ld;  // a's runs by position (long columns)
     const int nra = tA ? bs.nruns[a] : 0;
-    const bool rtab = tA && nra <= RUN_TABLE_MAX;  // run-rank table in LDS
-    const int nsg = (!DBG && tA) ? bs.nsing[a] : -1;
+    const bool rtab = !BIG && tA && nra <= RUN_TABLE_MAX;  // run-rank table in LDS
+    const int nsg = (!DBG && !BIG && tA) ? bs.nsing[a] : -1;
     const bool grouped = nsg >= 0;  // implies rtab (runs + untied positions <= RUN_TABLE_MAX)
     const uint16_t* sgA = bs.sing + a * RUN_GROUPS_MAX;
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
     // the partner block's presence bytes go where a's positions will be
     // (they are needed only while the tables are built); lane-wise gathers
     // from LDS instead of global memory
-    uint8_t* presL = (uint8_t*)smem_raw;
+    const uint8_t* presL = BIG ? presb + (b0 / PB) * ld : (const uint8_t*)smem_raw;
     // bytes 0..S: byte S is zero (the sentinel sample of a's padded order)
-    if constexpr (!DBG) copy16_to_lds((uint4*)presL, (const uint4*)(presb + (b0 / PB) * ld), (int)((S + 16) / 16));
+    if constexpr (!DBG && !BIG)
+        copy16_to_lds((uint4*)smem_raw, (const uint4*)(presb + (b0 / PB) * ld), (int)((S + 16) / 16));
     if (threadIdx.x < PB) corrA[threadIdx.x] = 0ull;
     __syncthreads();
 
@@ -1298,9 +1645,10 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
     // run number into the run number and 0xFFFF into RUN_TABLE_MAX (untied
     // samples get theirs below); tied, unchanged
     const uint32_t XS = 32u * (uint32_t)NW;
-    const uint32_t miss = grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS;
-    copy_pos_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8),
-                    grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS);
+    const uint32_t miss = BIG ? 0xFFFFu : grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS;
+    if constexpr (!BIG)
+        copy_pos_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8),
+                        grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS);
     __syncthreads();
     if (tA) {
         // per tie run [s, e) of a and partner: C(e) - C(s) complete samples
@@ -1359,13 +1707,24 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             const int nrb = bs.nruns[b];
             const uint16_t* sgB = bs.sing + b * RUN_GROUPS_MAX;
             uint32_t ng;
-            if (grouped) grouped_b_walk<2>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
+            if constexpr (BIG) {
+                if (tA) grouped_b_walk<4>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, runsA, rj, XS, miss, lane, sA, ng, d3B);
+                else grouped_b_walk<3>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, runsA, rj, XS, miss, lane, sA, ng, d3B);
+            } else if (grouped) grouped_b_walk<2>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
             else if (tA) grouped_b_walk<1>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
             else grouped_b_walk<0>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, rlA, rj, XS, miss, lane, sA, ng, d3B);
             w.n = ng;
         } else {
-#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, rlA, nbv, posA, tj, rj, XS, miss, lane, po.dbg_ra, po.dbg_rb, w)
-            if (grouped) {
+#define NAPY_WALK(A, B) pair_walk<A, B, DBG>(ordB, runsB, tbB, A >= 3 ? runsA : rlA, nbv, posA, tj, rj, XS, miss, lane, po.dbg_ra, po.dbg_rb, w)
+            if constexpr (BIG) {
+                if (tA) {
+                    if (cB == 2) NAPY_WALK(4, true);
+                    else NAPY_WALK(4, false);
+                } else {
+                    if (cB == 2) NAPY_WALK(3, true);
+                    else NAPY_WALK(3, false);
+                }
+            } else if (grouped) {
                 if (cB == 2) NAPY_WALK(2, true);
                 else NAPY_WALK(2, false);
             } else if (tA) {
@@ -1381,7 +1740,10 @@ __global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, c
             if (!DBG && cB == 1) {
                 const uint32_t* rlB = bs.rlist + b * (ld / 2);
                 const int nrb = bs.nruns[b];
-                if (grouped) settle_short_runs_b<2>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
+                if constexpr (BIG) {
+                    if (tA) settle_short_runs_b<4>(ordB, rlB, nrb, posA, tj, runsA, rj, miss, lane, corr, d3s);
+                    else settle_short_runs_b<3>(ordB, rlB, nrb, posA, tj, runsA, rj, miss, lane, corr, d3s);
+                } else if (grouped) settle_short_runs_b<2>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
                 else if (tA) settle_short_runs_b<1>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
                 else settle_short_runs_b<0>(ordB, rlB, nrb, posA, tj, rlA, rj, miss, lane, corr, d3s);
             }
@@ -1617,24 +1979,23 @@ __global__ __launch_bounds__(CP_THREADS) void k_compact(SpearBase base, const in
 constexpr int PAIR_PB = 8;
 static_assert(PAIR_PB * 64 == PAIR_THREADS, "one partner per wave");
 
-template <bool DBG>
+template <bool DBG, bool BIG>
 static int pairs_launch_t(const SpearBase& bs, const uint8_t* presb, int64_t S, int64_t F, PairOut po,
                           hipStream_t st)
 {
-    const size_t smem = pair_smem(bs.ld, S, PAIR_PB).bytes;
+    const size_t smem = pair_smem(bs.ld, S, PAIR_PB, BIG).bytes;
     static std::atomic<uint64_t> attr_done{0};
-    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_spearman_pairs<PAIR_PB, DBG>, 160 * 1024,
+    NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_spearman_pairs<PAIR_PB, DBG, BIG>, 160 * 1024,
                             "hipFuncSetAttribute(k_spearman_pairs)"));
     if (smem > 160 * 1024) return NAPY_E_UNSUPPORTED;
     const int64_t nbp = round_up(ceil_div(F, PAIR_PB), 8);
     const int64_t nblk = DBG ? 1 : pair_grid_size(F, nbp, PAIR_PB);
     if (nblk > 0x7FFFFFFFLL) return NAPY_E_UNSUPPORTED;
-    hipLaunchKernelGGL((k_spearman_pairs<PAIR_PB, DBG>), dim3((unsigned)nblk), dim3(PAIR_THREADS), smem, st, bs,
+    hipLaunchKernelGGL((k_spearman_pairs<PAIR_PB, DBG, BIG>), dim3((unsigned)nblk), dim3(PAIR_THREADS), smem, st, bs,
                        presb, S, F, nbp, po);
     return check_launch("spearman_pairs");
 }
 
-// pres: room for ceil(F / 8) planes of ld presence bytes
 static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t F, PairOut po, hipStream_t st)
 {
     uint8_t* presb = (uint8_t*)pres;
@@ -1642,8 +2003,14 @@ static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t 
     hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)nq), dim3(256), 0, st, bs, S, F,
                        presb);
     NAPY_TRY(check_launch("presence"));
-    if (po.dbg_ra) return pairs_launch_t<true>(bs, presb, S, F, po, st);
-    return pairs_launch_t<false>(bs, presb, S, F, po, st);
+    // columns longer than the LDS sort handles carry no tie flag in their
+    // positions (and would not fit a's positions in LDS next to the tables)
+    if (S > SORT_LDS_MAX_S) {
+        if (po.dbg_ra) return pairs_launch_t<true, true>(bs, presb, S, F, po, st);
+        return pairs_launch_t<false, true>(bs, presb, S, F, po, st);
+    }
+    if (po.dbg_ra) return pairs_launch_t<true, false>(bs, presb, S, F, po, st);
+    return pairs_launch_t<false, false>(bs, presb, S, F, po, st);
 }
 
 struct SpearWs {
@@ -1656,7 +2023,7 @@ struct SpearWs {
 static void spear_carve(Carver& c, int64_t S, int64_t F, SpearWs& w)
 {
     const int64_t ld = spear_ld(S);
-    w.keys = c.take<uint32_t>((size_t)F * ld);
+    w.keys = c.take<uint32_t>((size_t)sort_keys_words(S, F));
     base_carve(c, S, F, w.base);
     w.pres = c.take<uint32_t>((size_t)ceil_div(F, 32) * ld);
     const int64_t npairs = F * (F + 1) / 2;
@@ -1680,6 +2047,11 @@ static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us
     dim3 gk((unsigned)ceil_div(F, 64), (unsigned)ceil_div(base.ld, 64));
     hipLaunchKernelGGL(k_sort_keys, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
     NAPY_TRY(check_launch("sort_keys"));
+    if (S > SORT_LDS_MAX_S) {
+        hipLaunchKernelGGL(k_colsort_big, dim3((unsigned)F), dim3(CS_THREADS), 0, st, keys, S, base.ld, F, base);
+        NAPY_TRY(check_launch("colsort_big"));
+        return tiebits_launch(base, F, st, false);
+    }
     const int64_t E = ceil_div(S, CS_THREADS);
     if (E <= 2) NAPY_TRY(colsort_launch<2>(keys, S, F, base, st));
     else if (E <= 4) NAPY_TRY(colsort_launch<4>(keys, S, F, base, st));
@@ -1753,7 +2125,7 @@ size_t spearman_base_bytes(int64_t S, int64_t F)
     SpearBase b;
     base_carve(c, S, F, b);
     // the keys buffer used while sorting is carved after the base
-    c.take<uint32_t>((size_t)F * spear_ld(S));
+    c.take<uint32_t>((size_t)sort_keys_words(S, F));
     return c.bytes();
 }
 
@@ -1763,7 +2135,7 @@ int spearman_base_prepare_run(const float* X, int64_t S, int64_t F, int64_t ldx,
     Carver c(base);
     SpearBase b;
     base_carve(c, S, F, b);
-    uint32_t* keys = c.take<uint32_t>((size_t)F * spear_ld(S));
+    uint32_t* keys = c.take<uint32_t>((size_t)sort_keys_words(S, F));
     return sort_launch(X, S, F, ldx, opt_use_sent(opts), opt_sent(opts), keys, b, st);
 }
 

@@ -77,10 +77,14 @@ def test_invalid_arguments_rejected_on_host():
     # too many variables
     assert lib.napy_pearson(FAKE, 100, 70000, 70000, FAKE, FAKE, FAKE, 70000, FAKE, 1 << 40, O,
                             None) == _lib.NAPY_E_UNSUPPORTED
-    # Spearman sample limit
-    assert lib.napy_spearman_workspace(30000, 10, O) == 0
-    assert lib.napy_spearman(FAKE, 30000, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, 1 << 30, O,
+    # Spearman sample limit: 16-bit sample indices and positions; query
+    # subsets of a resident base only up to the LDS sort's column length
+    assert lib.napy_spearman_workspace(65535, 10, O) > 0
+    assert lib.napy_spearman_workspace(65536, 10, O) == 0
+    assert lib.napy_spearman(FAKE, 65536, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, 1 << 40, O,
                              None) == _lib.NAPY_E_UNSUPPORTED
+    assert lib.napy_spearman_base_bytes(24576, 10) > 0
+    assert lib.napy_spearman_base_bytes(24577, 10) == 0
     sw = lib.napy_spearman_workspace(100, 10, O)
     assert sw > 0
     assert lib.napy_spearman(FAKE, 100, 10, 10, FAKE, FAKE, FAKE, 10, FAKE, sw - 1, O, None) == _lib.NAPY_E_WORKSPACE
@@ -306,7 +310,9 @@ def test_rank_tests_arguments_rejected_on_host():
     need = lib.napy_mannwhitney_workspace(100, 3, 5, O)
     assert need > 0 and lib.napy_kruskal_workspace(100, 3, 5, 4, O) > 0
     assert lib.napy_kruskal_workspace(100, 3, 5, 1, O) == 0 and lib.napy_kruskal_workspace(100, 3, 5, 33, O) == 0
-    assert lib.napy_mannwhitney_workspace(24577, 3, 5, O) == 0  # 16-bit sorted orders
+    # 16-bit sorted orders
+    assert lib.napy_mannwhitney_workspace(65535, 3, 5, O) > 0
+    assert lib.napy_mannwhitney_workspace(65536, 3, 5, O) == 0
     WS = ctypes.c_void_p(0x2000000)
     ok = dict(L=FAKE, ldl=3, X=FAKE, ldx=5, S=100, FC=3, FQ=5, m=0, u=FAKE, p=FAKE, n=FAKE, ldo=5, ws=WS, nb=need)
 
@@ -323,7 +329,7 @@ def test_rank_tests_arguments_rejected_on_host():
     assert call(ldo=4) == _lib.NAPY_E_INVALID
     assert call(m=2) == _lib.NAPY_E_INVALID
     assert call(p=None) == _lib.NAPY_E_INVALID
-    assert call(S=30000) == _lib.NAPY_E_UNSUPPORTED
+    assert call(S=70000) == _lib.NAPY_E_UNSUPPORTED
     assert call(ws=None) == _lib.NAPY_E_WORKSPACE
     assert call(nb=need - 1) == _lib.NAPY_E_WORKSPACE
     assert call(ws=ctypes.c_void_p(0x2000010)) == _lib.NAPY_E_WORKSPACE  # not 256-byte aligned

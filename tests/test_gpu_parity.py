@@ -468,6 +468,50 @@ def test_spearman_max_samples(gpu_device):
     _check_full("spearman", X.astype(np.float32), gpu_device, where="spearman-max-samples")
 
 
+def _long_columns(S, seed):
+    """Columns longer than the LDS sort takes: untied, Poisson, rounded
+    normals, grouped (three values, complete, the last run ending at S), a
+    complete untied column (positions up to S - 1), one with 40 tied pairs,
+    and plain normals; 30% missing elsewhere."""
+    rng = np.random.default_rng(seed)
+    cols = [rng.standard_normal(S), rng.poisson(4, S).astype(np.float64), np.round(rng.standard_normal(S), 2),
+            rng.integers(0, 3, S).astype(np.float64), rng.standard_normal(S)]
+    d = rng.standard_normal(S)
+    for _ in range(40):
+        a, b = rng.choice(S, 2, replace=False)
+        d[b] = d[a]
+    cols.append(d)
+    X = np.column_stack(cols + [rng.standard_normal(S) for _ in range(4)])
+    X[rng.random(X.shape) < 0.3] = np.nan
+    X[:, 4] = rng.permutation(S)
+    X[:, 3] = rng.integers(0, 3, S)
+    return X.astype(np.float32)
+
+
+@pytest.mark.parametrize("S", [24577, 50000, 65535])
+def test_spearman_long_columns(gpu_device, S):
+    """Above 24,576 samples the columns are sorted in global memory and the
+    pair scan reads a's positions (no tie flag) from there: one sample above
+    that length, 50,000, and the 16-bit limit 65,535."""
+    print(f"[spearman long columns] S={S}", flush=True)
+    _check_full("spearman", _long_columns(S, 900 + S), gpu_device, where=f"spearman-long-{S}")
+
+
+def test_long_columns_ranks_bit_exact(gpu_device):
+    """Doubled ranks within I(g, h) at 50,000 samples, bit for bit, for pairs
+    of every tie class on either side."""
+    napy = _napy()
+    X = _long_columns(50000, 4242)
+    Xd = _to_dev(X, gpu_device)
+    for g, h in [(0, 1), (1, 0), (1, 2), (2, 3), (3, 1), (5, 4), (4, 5), (3, 3), (2, 9)]:
+        rg, rh = napy.spearman_pair_ranks(Xd, g, h)
+        og, oh, n = orc.pair_ranks(X, g, h)
+        exp_g = np.where(np.isnan(og), -1, np.round(2 * np.nan_to_num(og))).astype(np.int64)
+        exp_h = np.where(np.isnan(oh), -1, np.round(2 * np.nan_to_num(oh))).astype(np.int64)
+        assert np.array_equal(_np(rg).astype(np.int64), exp_g), (g, h, "a side")
+        assert np.array_equal(_np(rh).astype(np.int64), exp_h), (g, h, "b side")
+
+
 def test_tie_runs_ranks_bit_exact(gpu_device):
     napy = _napy()
     X = _tie_stress_matrix(S=1500, seed=5)

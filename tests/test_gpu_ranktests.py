@@ -199,12 +199,14 @@ def test_sentinel_and_default_ncat(gpu_device):
     _check("kw", _run("kw", Ls, Xs, gpu_device, missing=-7.0), orank.kruskal(L, X), "sentinel")
 
 
-def test_max_samples(gpu_device):
-    """S = 24,576 (the sorted orders' limit): untied, grouped and densely
-    tied continuous columns, one complete; labels with and without missing."""
-    print("rank tests max samples", flush=True)
-    rng = np.random.default_rng(88)
-    S = 24576
+@pytest.mark.parametrize("S", [24576, 24577, 50000, 65535])
+def test_max_samples(gpu_device, S):
+    """The largest column the LDS sort takes (24,576), one sample more (the
+    global-memory sort), 50,000 and the 16-bit limit 65,535 (labels read from
+    global memory, 64-bit rank sums): untied, grouped and densely tied
+    continuous columns, one complete; labels with and without missing."""
+    print(f"rank tests max samples S={S}", flush=True)
+    rng = np.random.default_rng(88 + S)
     X = np.column_stack([rng.standard_normal(S), rng.poisson(4, S), np.round(rng.standard_normal(S), 1),
                          rng.permutation(S)]).astype(np.float64)
     X[rng.random(X.shape) < 0.3] = np.nan
