@@ -185,6 +185,11 @@ def main() -> int:
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent queries (HIP streams)")
     ap.add_argument("--arena-gib", type=float, default=6.0, help="serving: device memory for queries")
+    ap.add_argument("--sweep", default="",
+                    help="serving: comma-separated arrival rates (q/s) for a capacity sweep after the main run")
+    ap.add_argument("--sweep-queries", type=int, default=1000, help="serving: measured queries per sweep rate")
+    ap.add_argument("--p99-bound-ms", type=float, default=25.0,
+                    help="serving: the p99 latency bound of the capacity figure")
     ap.add_argument("--acc-pairs", type=int, default=20000, help="precision: sampled pairs")
     args = ap.parse_args()
 
@@ -789,6 +794,32 @@ def run_serving(args) -> int:
         "max_concurrent": stats["max_concurrent"], "arena_peak_bytes": stats["arena_peak_bytes"],
         "device_busy_frac": stats.get("device_busy_frac"),
     }
+    if args.sweep:
+        # capacity: the same query mix replayed at rising arrival rates; a rate
+        # is sustained when the queries finish within 5% of their arrival span
+        # and p99 stays under the bound
+        sweep = []
+        for rate in [float(x) for x in args.sweep.split(",") if x.strip()]:
+            qs2 = synth.serving_queries(args.sweep_queries, S, F, rate=rate, seed=int(rate) + 17)
+            rq = [Request(i, q.method, q.rows, q.cols, q.arrival_s) for i, q in enumerate(qs2)]
+            t1 = rq[0].arrival
+            rq = [Request(q.qid, q.method, q.rows, q.cols, q.arrival - t1) for q in rq]
+            print(f"[serving] sweep {rate:g} q/s: {len(rq)} queries", file=sys.stderr, flush=True)
+            st2 = srv.serve(rq)
+            span = rq[-1].arrival
+            sweep.append({"rate_qps": rate, "p50_ms": st2["p50_ms"], "p99_ms": st2["p99_ms"],
+                          "pairs_per_s": st2["pairs_per_s"], "wall_s": st2["wall_s"], "arrival_span_s": span,
+                          "device_busy_frac": st2.get("device_busy_frac"),
+                          "keeps_up": bool(st2["wall_s"] <= 1.05 * span + 0.05),
+                          "within_bound": bool(st2["p99_ms"] <= args.p99_bound_ms)})
+        keep = [x["rate_qps"] for x in sweep if x["keeps_up"]]
+        ok = [x["rate_qps"] for x in sweep if x["keeps_up"] and x["within_bound"]]
+        res["sweep"] = sweep
+        res["p99_bound_ms"] = args.p99_bound_ms
+        # highest swept rate whose queries finish within their arrival span
+        res["throughput_capacity_qps"] = max(keep) if keep else None
+        # highest swept rate that also keeps p99 under the bound
+        res["capacity_qps"] = max(ok) if ok else None
     print(json.dumps(res))
     return 0
 

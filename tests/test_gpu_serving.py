@@ -91,6 +91,47 @@ def test_serving_alone_vs_mix_bit_identical(gpu_device):
         assert_p_close(got["p"], po, ro, no, max(worst, 1e-15), where)
 
 
+def test_serving_large_base_alone_vs_mix(gpu_device):
+    """A 20,000 x 500 resident base (30% MCAR) and queries of up to 18,000
+    rows and all 500 variables: each result bit-identical alone and in the
+    mix; two small queries also against the oracle."""
+    import torch
+    from paper_2505_00448_amd.serve import Request, Server
+    S, F = 20000, 500
+    X = synth.cfg_serving_base(S=S, F=F)
+    Xd = torch.from_numpy(X).to(gpu_device)
+    rng = np.random.default_rng(2024)
+    reqs = []
+    for i in range(12):
+        nr = int(rng.integers(1000, 18001)) if i < 10 else int(rng.integers(200, 2001))
+        nc = int(rng.integers(50, F + 1)) if i < 10 else int(rng.integers(5, 40))
+        rows = np.sort(rng.choice(S, size=nr, replace=False)).astype(np.int32)
+        cols = rng.choice(F, size=nc, replace=False).astype(np.int32)
+        reqs.append(Request(i, "spearman" if i % 2 else "pearson", rows, cols, 1e-4 * i))
+    print(f"[serving] large base: {len(reqs)} queries", flush=True)
+    alone = {}
+    srv1 = Server(Xd, slots=1, capacity=2 << 30)
+    for q in reqs:
+        srv1.serve([q], on_done=_grab(alone), realtime=False)
+    big = max(srv1.ex.nbytes(q) for q in reqs)
+    mix = {}
+    srv = Server(Xd, slots=4, capacity=int(2.5 * big))
+    stats = srv.serve(reqs, on_done=_grab(mix), realtime=False)
+    assert stats["queries"] == len(reqs) and stats["max_concurrent"] >= 2, stats
+    for q in reqs:
+        for k in ("r", "p", "n"):
+            assert np.array_equal(_bits(alone[q.qid][k]), _bits(mix[q.qid][k])), (q.qid, q.method, k)
+    for q in reqs[10:]:
+        sub = X[np.ix_(q.rows, q.cols)]
+        ro, po, no = (orc.pearson if q.method == "pearson" else orc.spearman)(sub)
+        tol = 1e-6 if q.method == "pearson" else 1e-12
+        got = mix[q.qid]
+        where = f"query {q.qid} ({q.method}, {len(q.rows)}x{len(q.cols)})"
+        assert_counts_equal(got["n"], no, where)
+        worst = assert_r_close(got["r"], ro, tol, where)
+        assert_p_close(got["p"], po, ro, no, max(worst, 1e-15), where)
+
+
 def test_serving_device_copies_in_callback(gpu_device):
     """A callback that keeps its results as device copies queued on torch's
     current stream (no host wait): the arena memory is reused by later
