@@ -469,6 +469,7 @@ __device__ __forceinline__ bf16x2 to_bf16x2(float a, float b)
     return __builtin_convertvector((f32x2){a, b}, bf16x2);
 }
 
+template <bool SENT>
 __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
     const float* __restrict__ mu32, int T, int ntiles, int nsplit, int64_t ksplit, double* __restrict__ part)
@@ -493,25 +494,43 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     const float muG = okG ? mu32[colG] : 0.0f, muH = okH ? mu32[colH] : 0.0f;
 
     __shared__ __attribute__((aligned(16))) __bf16 lds[2 * BUF];
-    // raw values of two slabs in flight (sets A and B, alternating); loads
-    // are unconditional from a clamped address, out-of-range values become
-    // NaN (missing) afterwards, so the loop body has no branches
+    // raw values of two slabs in flight (sets A and B, alternating).  A full
+    // slab is read from the slab's row pointer (uniform) plus 32-bit offsets
+    // fixed per thread; only a slab that runs past kend takes the clamped
+    // path, whose out-of-range values become NaN (missing).  A column past F
+    // is read as column 0 and counted missing in store_lds.
     float rawG[4], rawH[4], nxtG[4], nxtH[4];
     const int64_t cG = okG ? colG : 0, cH = okH ? colH : 0;
+    uint32_t offG[4], offH[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        offG[j] = (uint32_t)(kq * 4 + j) * (uint32_t)ldx + (uint32_t)cG;
+        offH[j] = (uint32_t)(kq * 4 + j) * (uint32_t)ldx + (uint32_t)cH;
+    }
     auto load_raw = [&](int slab, float (&rg)[4], float (&rh)[4]) {
-        const int64_t i0 = kbeg + (int64_t)slab * BK + kq * 4;
+        const int64_t s0 = kbeg + (int64_t)slab * BK;  // uniform
+        if (s0 + BK <= kend) {
+            const float* row = X + s0 * ldx;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t i = i0 + j;
-            const int64_t ic = i < kend ? i : kend - 1;
-            rg[j] = X[ic * ldx + cG];
-            rh[j] = X[ic * ldx + cH];
-        }
+            for (int j = 0; j < 4; ++j) {
+                rg[j] = row[offG[j]];
+                rh[j] = row[offH[j]];
+            }
+        } else {
+            const int64_t i0 = s0 + kq * 4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool in = i0 + j < kend;
-            rg[j] = (in && okG) ? rg[j] : __builtin_nanf("");
-            rh[j] = (in && okH) ? rh[j] : __builtin_nanf("");
+            for (int j = 0; j < 4; ++j) {
+                const int64_t i = i0 + j;
+                const int64_t ic = i < kend ? i : kend - 1;
+                rg[j] = X[ic * ldx + cG];
+                rh[j] = X[ic * ldx + cH];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in = i0 + j < kend;
+                rg[j] = in ? rg[j] : __builtin_nanf("");
+                rh[j] = in ? rh[j] : __builtin_nanf("");
+            }
         }
     };
     // LDS rows are 32 B (16 samples); the two 16-B halves of row c are
@@ -530,7 +549,7 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const float raw = side ? rH[2 * jp + u] : rG[2 * jp + u];
-                    miss[u] = is_missing(raw, use_sent, sent);
+                    miss[u] = (raw != raw) || (SENT && raw == sent) || !(side ? okH : okG);
                     x[u] = miss[u] ? 0.0f : raw - (side ? muH : muG);
                     q[u] = x[u] * x[u];
                 }
@@ -1006,8 +1025,12 @@ static int pearson_run_plan(const float* X, int64_t S, int64_t F, int64_t ldx, d
                            cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
         break;
     case NAPY_PREC_BF16X3:
-        hipLaunchKernelGGL(k_pearson_bf16, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T,
-                           pl.ntiles, pl.nsplit, pl.ksplit, part);
+        if (us)
+            hipLaunchKernelGGL(k_pearson_bf16<true>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T,
+                               pl.ntiles, pl.nsplit, pl.ksplit, part);
+        else
+            hipLaunchKernelGGL(k_pearson_bf16<false>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T,
+                               pl.ntiles, pl.nsplit, pl.ksplit, part);
         break;
     default:
         hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_FP64>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv,
