@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "b8e5742af64e0497d1bab6da015c82baa38e674693b42bf4c862e50b929b316d",
-    "fetch_kib": 139924.1,
-    "write_kib": 25740.2,
+    "source_sha256": "b024416590f3c0b70264c4fcab98e515a09a0abd1f90c2d111019cb35a729679",
+    "fetch_kib": 129364.8,
+    "write_kib": 15869.5,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
