@@ -199,7 +199,8 @@ struct TileCfg<NAPY_PREC_FP64> {
 
 // Maps the hardware block index to a logical work index so that every XCD
 // (blocks are dealt to the 8 XCDs round-robin) receives a contiguous range of
-// logical work, which keeps neighbouring tiles' panels in one L2.
+// logical work, which keeps the rows and panels that neighbouring work items
+// read in one L2.
 __device__ __forceinline__ int xcd_logical_block(int bid, int nb)
 {
     const int x = bid & 7, q = bid >> 3;
@@ -230,7 +231,9 @@ __global__ __launch_bounds__(256, 1) void k_pearson_tiles(
     constexpr int BK = C::BK, LDK = C::LDK, RPT = C::RPT;
 
     const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
-    const int t = lb / nsplit, split = lb % nsplit;
+    // split-major: an XCD's workgroups are tiles of one sample range, which
+    // read the same rows of X at about the same time (one fetch into its L2)
+    const int split = lb / ntiles, t = lb % ntiles;
     int tg, th;
     tile_coords(t, T, tg, th);
 
@@ -457,6 +460,7 @@ constexpr int NPL = 7;                  // xh, xm, xl, qh, qm, ql, m
 constexpr int PLANE = TILE * BK;        // bf16 per plane
 constexpr int BUF = 2 * NPL * PLANE;    // one slab, both sides
 constexpr int FLUSH_SLABS = 1024 / BK;
+static_assert(FLUSH_SLABS % 2 == 0, "blocks of slabs start on an even slab");
 }  // namespace bf3
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -469,14 +473,16 @@ __device__ __forceinline__ bf16x2 to_bf16x2(float a, float b)
     return __builtin_convertvector((f32x2){a, b}, bf16x2);
 }
 
-template <bool SENT>
+template <bool SENT, bool GEN>
 __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
     const float* __restrict__ mu32, int T, int ntiles, int nsplit, int64_t ksplit, double* __restrict__ part)
 {
     using namespace bf3;
     const int lb = xcd_logical_block((int)blockIdx.x, (int)gridDim.x);
-    const int t = lb / nsplit, split = lb % nsplit;
+    // split-major: an XCD's workgroups are tiles of one sample range, which
+    // read the same rows of X at about the same time (one fetch into its L2)
+    const int split = lb / ntiles, t = lb % ntiles;
     int tg, th;
     tile_coords(t, T, tg, th);
     const int tid = threadIdx.x;
@@ -494,30 +500,44 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     const float muG = okG ? mu32[colG] : 0.0f, muH = okH ? mu32[colH] : 0.0f;
 
     __shared__ __attribute__((aligned(16))) __bf16 lds[2 * BUF];
-    // raw values of two slabs in flight (sets A and B, alternating).  A full
-    // slab is read from the slab's row pointer (uniform) plus 32-bit offsets
-    // fixed per thread; only a slab that runs past kend takes the clamped
-    // path, whose out-of-range values become NaN (missing).  A column past F
-    // is read as column 0 and counted missing in store_lds.
+    // raw values of two slabs in flight (sets A and B, alternating).  Every
+    // slab is read as 16 whole rows from a row pointer (uniform) plus 32-bit
+    // byte offsets fixed per thread, one instruction sequence for all slabs
+    // (so the wait for a slab's values does not also wait for the loads of
+    // the slab after it): a slab that would run past kend is moved back to
+    // end at kend, and its rows before the slab's own start, counted already
+    // (or belonging to the previous split), are staged as missing.  A column
+    // past F is read as column 0 and counted missing in store_lds.  GEN (S
+    // below one slab, or rows too long for 32-bit offsets) clamps each row
+    // index instead.
     float rawG[4], rawH[4], nxtG[4], nxtH[4];
     const int64_t cG = okG ? colG : 0, cH = okH ? colH : 0;
     uint32_t offG[4], offH[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        offG[j] = (uint32_t)(kq * 4 + j) * (uint32_t)ldx + (uint32_t)cG;
-        offH[j] = (uint32_t)(kq * 4 + j) * (uint32_t)ldx + (uint32_t)cH;
+        offG[j] = ((uint32_t)(kq * 4 + j) * (uint32_t)ldx + (uint32_t)cG) * 4u;
+        offH[j] = ((uint32_t)(kq * 4 + j) * (uint32_t)ldx + (uint32_t)cH) * 4u;
     }
+    // first row of the 16 that slab `slab` reads (uniform)
+    auto slab_base = [&](int slab) -> int64_t {
+        const int64_t s0 = kbeg + (int64_t)slab * BK;
+        return s0 < kend - BK ? s0 : kend - BK;
+    };
+    // leading rows of the slab read as missing
+    auto lead_missing = [&](int slab) -> int {
+        if constexpr (GEN) return 0;
+        return (int)(kbeg + (int64_t)slab * BK - slab_base(slab));
+    };
     auto load_raw = [&](int slab, float (&rg)[4], float (&rh)[4]) {
-        const int64_t s0 = kbeg + (int64_t)slab * BK;  // uniform
-        if (s0 + BK <= kend) {
-            const float* row = X + s0 * ldx;
+        if constexpr (!GEN) {
+            const char* row = (const char*)(X + slab_base(slab) * ldx);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                rg[j] = row[offG[j]];
-                rh[j] = row[offH[j]];
+                rg[j] = *(const float*)(row + offG[j]);
+                rh[j] = *(const float*)(row + offH[j]);
             }
         } else {
-            const int64_t i0 = s0 + kq * 4;
+            const int64_t i0 = kbeg + (int64_t)slab * BK + kq * 4;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t i = i0 + j;
@@ -536,7 +556,10 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     // LDS rows are 32 B (16 samples); the two 16-B halves of row c are
     // swapped when bit 3 of c is set, so that the 16-lane phases of the
     // row-wise 16-B reads below hit distinct banks
-    auto store_lds = [&](int buf, const float (&rG)[4], const float (&rH)[4]) {
+    // (lo: leading rows of the slab read as missing; a comparison per sample
+    // rather than a branch, which would make the wait for this slab's values
+    // also wait for the loads issued after them)
+    auto store_lds = [&](int buf, const float (&rG)[4], const float (&rH)[4], int lo) {
         __bf16* base = lds + buf * BUF;
         const int slot = (kq ^ (((sc >> 3) & 1) << 1)) * 4;
 #pragma unroll
@@ -549,7 +572,10 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const float raw = side ? rH[2 * jp + u] : rG[2 * jp + u];
-                    miss[u] = (raw != raw) || (SENT && raw == sent) || !(side ? okH : okG);
+                    // bitwise, not short-circuit: no control flow in the loop
+                    // body, so the contractions and the staging interleave
+                    miss[u] = (raw != raw) | (SENT & (raw == sent)) | !(side ? okH : okG) |
+                              (kq * 4 + 2 * jp + u < lo);
                     x[u] = miss[u] ? 0.0f : raw - (side ? muH : muG);
                     q[u] = x[u] * x[u];
                 }
@@ -666,26 +692,40 @@ __global__ __launch_bounds__(256, 2) void k_pearson_bf16(
     auto step = [&](int sl, const float (&cG)[4], const float (&cH)[4], float (&lG)[4], float (&lH)[4]) {
         load_raw(sl + 2, lG, lH);
         compute(sl & 1);
-        store_lds((sl + 1) & 1, cG, cH);
+        store_lds((sl + 1) & 1, cG, cH, lead_missing(sl + 1));
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // six VALU
         }
-        if ((sl + 1) % FLUSH_SLABS == 0 && sl + 1 < nslab) flush();
         __syncthreads();
     };
+    // blocks of FLUSH_SLABS slabs (an even count, so every block starts with
+    // the next slab's values in rawG / rawH), the flush between blocks: the
+    // inner loop holds no global access but the raw loads, and its body is
+    // one block of code
     if (nslab > 0) {
         load_raw(0, rawG, rawH);
-        store_lds(0, rawG, rawH);
+        store_lds(0, rawG, rawH, lead_missing(0));
         load_raw(1, rawG, rawH);
         __syncthreads();
         int sl = 0;
-        for (; sl + 1 < nslab; sl += 2) {
-            step(sl, rawG, rawH, nxtG, nxtH);
-            step(sl + 1, nxtG, nxtH, rawG, rawH);
+        for (;;) {
+            const int be = min(nslab, sl + FLUSH_SLABS);
+            for (; sl + 1 < be; sl += 2) {
+                step(sl, rawG, rawH, nxtG, nxtH);
+                step(sl + 1, nxtG, nxtH, rawG, rawH);
+            }
+            if (sl < be) {  // an odd count: the last block
+                step(sl, rawG, rawH, nxtG, nxtH);
+                ++sl;
+            }
+            if (sl >= nslab) break;
+            flush();
+            // every global access complete (vmcnt 0): the next block starts
+            // in the state its own loop leaves, so its waits stay exact
+            __builtin_amdgcn_s_waitcnt(0x0F70);
         }
-        if (sl < nslab) step(sl, rawG, rawH, nxtG, nxtH);
     }
     flush();
     double* d0 = slice(0);
@@ -1025,13 +1065,15 @@ static int pearson_run_plan(const float* X, int64_t S, int64_t F, int64_t ldx, d
                            cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);
         break;
     case NAPY_PREC_BF16X3:
-        if (us)
-            hipLaunchKernelGGL(k_pearson_bf16<true>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T,
-                               pl.ntiles, pl.nsplit, pl.ksplit, part);
-        else
-            hipLaunchKernelGGL(k_pearson_bf16<false>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T,
-                               pl.ntiles, pl.nsplit, pl.ksplit, part);
+    {
+        // 16 rows of ldx floats must be addressable with 32-bit byte offsets
+        const bool gen = S < bf3::BK || ldx >= ((int64_t)1 << 26);
+        auto kern = us ? (gen ? k_pearson_bf16<true, true> : k_pearson_bf16<true, false>)
+                       : (gen ? k_pearson_bf16<false, true> : k_pearson_bf16<false, false>);
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv, cs.mu32, pl.T, pl.ntiles,
+                           pl.nsplit, pl.ksplit, part);
         break;
+    }
     default:
         hipLaunchKernelGGL(k_pearson_tiles<NAPY_PREC_FP64>, dim3(nb), dim3(256), 0, st, X, S, F, ldx, us, sv,
                            cs.mu32, cs.mu64, pl.T, pl.ntiles, pl.nsplit, pl.ksplit, part);

@@ -91,7 +91,8 @@ def test_edge_matrix(gpu_device, method):
 # ragged shapes: several tiles, partial tiles, tiny and empty inputs
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("S,F", [(1, 3), (2, 5), (3, 1), (0, 4), (777, 130), (1500, 65), (64, 64), (65, 129)])
+@pytest.mark.parametrize("S,F", [(1, 3), (2, 5), (3, 1), (0, 4), (15, 9), (16, 7), (17, 33), (31, 70), (777, 130),
+                                 (1500, 65), (64, 64), (65, 129)])
 def test_ragged_shapes(gpu_device, S, F):
     rng = np.random.default_rng(S * 1000 + F)
     X = rng.standard_normal((S, F)).astype(np.float32)
