@@ -946,6 +946,7 @@ struct WalkSums {
 };
 
 constexpr int WALK_U = 4;  // chunks of 64 positions per group; rows are padded to 64 * WALK_U
+static_assert(WALK_U == 4, "the grouped walk of a with ties ORs four chunk masks");
 
 // a's tied samples: their stored position is the flag bit plus the index of
 // their tie run in a's run list.  With at most RUN_TABLE_MAX runs each run's
@@ -1127,6 +1128,40 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
         }
         const bool dirty = dbits != 0u;
         uint32_t t32 = 0;
+        if constexpr (TA == 1 && !DBG) {
+            if (!dirty) {
+                // a with ties, most of them rare: the four chunks as untied
+                // (a tied or missing a-position is clamped to XS, whose
+                // table entry gives 0), one block of code; the tied lanes'
+                // products after them, in a branch taken only by a group
+                // that holds tied a-positions
+                uint64_t km[U], tm[U];
+                uint32_t c0[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool kept = pv[u] != miss;
+                    km[u] = __ballot(kept);
+                    tm[u] = __ballot(kept && (pv[u] & POS_TIED));
+                    c0[u] = carry1;
+                    const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(km[u] >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)km[u], carry1));
+                    t32 += __umul24(cnt1(tab, min(pv[u], XS)), cb1);
+                    carry1 += (uint32_t)__popcll(km[u]);
+                }
+                sA4 += t32;
+                if ((tm[0] | tm[1] | tm[2] | tm[3]) != 0ull) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if ((tm[u] >> lane) & 1ull) {
+                            const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(km[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km[u], c0[u]));
+                            sAt += __umul24(ra_of_tied(tab, rlA, rrun, pv[u]), cb1);
+                        }
+                    }
+                }
+                continue;
+            }
+        }
         if (!dirty) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -1531,7 +1566,7 @@ __host__ inline int64_t pair_grid_size(int64_t F, int64_t nbp, int PB)
 // bytes are read from global memory, a tied a-sample is recognised by its
 // run (TA 4), and products are summed in 64 bits.
 template <int PB, bool DBG, bool BIG>
-__global__ __launch_bounds__(PAIR_THREADS) void k_spearman_pairs(SpearBase bs, const uint8_t* __restrict__ presb,
+__global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs, const uint8_t* __restrict__ presb,
                                                                  int64_t S, int64_t F, int64_t nbp, PairOut po)
 {
     static_assert(PB == 8, "a partner block is one plane of presence bytes");
