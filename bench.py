@@ -188,6 +188,8 @@ def main() -> int:
     ap.add_argument("--sweep", default="",
                     help="serving: comma-separated arrival rates (q/s) for a capacity sweep after the main run")
     ap.add_argument("--sweep-queries", type=int, default=1000, help="serving: measured queries per sweep rate")
+    ap.add_argument("--alone-queries", type=int, default=2000,
+                    help="serving: measured queries run again one at a time (service-time floor); 0 skips")
     ap.add_argument("--p99-bound-ms", type=float, default=25.0,
                     help="serving: the p99 latency bound of the capacity figure")
     ap.add_argument("--acc-pairs", type=int, default=20000, help="precision: sampled pairs")
@@ -794,6 +796,27 @@ def run_serving(args) -> int:
         "max_concurrent": stats["max_concurrent"], "arena_peak_bytes": stats["arena_peak_bytes"],
         "device_busy_frac": stats.get("device_busy_frac"),
     }
+    if args.alone_queries > 0:
+        # each (sampled) measured query once more on its own: its service time
+        # with the whole device, the floor under its latency in the stream
+        rng = np.random.default_rng(11)
+        pick = meas if len(meas) <= args.alone_queries else \
+            [meas[i] for i in sorted(rng.choice(len(meas), args.alone_queries, replace=False).tolist())]
+        print(f"[serving] {len(pick)} queries alone", file=sys.stderr, flush=True)
+        alone = {}
+        for q in pick:
+            got = []
+            srv.serve([Request(q.qid, q.method, q.rows, q.cols, 0.0)], on_done=got.append, realtime=False)
+            alone[q.qid] = got[0].latency * 1e3
+        a = np.array(list(alone.values()))
+        lat_by = {c.qid: c.latency * 1e3 for c in comps}
+        ratio = np.array([lat_by[k] / v for k, v in alone.items() if k in lat_by and v > 0])
+        res["alone"] = {
+            "queries": int(len(a)), "p50_ms": _pct(a, 50), "p99_ms": _pct(a, 99), "max_ms": float(a.max()),
+            "stream_over_alone_p50": _pct(ratio, 50), "stream_over_alone_p99": _pct(ratio, 99),
+            "definition": "service time of each query run by itself on the idle device (latency floor); "
+                          "ratio = its latency in the stream / that time",
+        }
     if args.sweep:
         # capacity: the same query mix replayed at rising arrival rates; a rate
         # is sustained when the queries finish within 5% of their arrival span
