@@ -132,7 +132,9 @@ int napy_pearson_noalloc(const float* X, int64_t S, int64_t F, int64_t ldx,
  * ranks for ties (IEEE equality: -0 ties +0).  rho is the Pearson
  * coefficient of those ranks, computed from exact integer sums.
  * n <= 1 -> rho = p = NaN; n = 2 -> p = NaN; all tied on I -> NaN.
- * Supported: 1 <= S <= 24576 samples, 1 <= F <= 65535.
+ * Supported: 1 <= S <= 65535 samples (sorted orders hold 16-bit sample
+ * indices; columns longer than 24576 are sorted and walked through global
+ * memory), 1 <= F <= 65535.
  * ------------------------------------------------------------------------ */
 size_t napy_spearman_workspace(int64_t S, int64_t F, const napy_opts* opts);
 
@@ -201,7 +203,7 @@ int napy_pearson_backward(const float* X, int64_t S, int64_t F, int64_t ldx,
  * napy_spearman_base_bytes(S, F) bytes, 256-byte aligned), and
  * napy_spearman_subset compacts each selected column's sorted order by the
  * row set, so no query sorts again.  The base stays valid while X is
- * unchanged; S <= 24576.
+ * unchanged; S <= 24576 (the compaction holds a base column in LDS).
  * ------------------------------------------------------------------------ */
 size_t napy_pearson_subset_workspace(int64_t Sq, int64_t Fq, const napy_opts* opts);
 
@@ -305,7 +307,9 @@ int napy_anova(const float* L, int64_t ldl, const float* X, int64_t ldx, int64_t
  * those of napy_ttest / napy_anova above.  Within I(g, h) the continuous
  * values are ranked 1..n with tied values given the average of their ranks;
  * R_k is the rank sum of label k, n_k its size, T = sum over groups of tied
- * values of t^3 - t.  S <= 24,576 (sorted orders hold 16-bit sample indices).
+ * values of t^3 - t.  S <= 65,535 (sorted orders hold 16-bit sample indices;
+ * with more than 24,576 the labels are read from global memory when they and
+ * the tables do not fit LDS together).
  *
  * napy_mannwhitney: groups are label 0 and label 1; the statistic is
  *   U1 = R_0 - n0 (n0 + 1) / 2.  Two-sided p with U = max(U1, n0 n1 - U1):

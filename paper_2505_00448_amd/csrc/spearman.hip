@@ -18,7 +18,8 @@
 //   k_sort_keys      transposes X into per-column order-preserving uint32 keys
 //                    (-0 canonicalised to +0; missing -> 0xFFFFFFFF).
 //   k_colsort        one 1024-thread workgroup per column: LSD radix sort of
-//                    the keys in LDS (8 passes of 4 bits), then
+//                    the keys in LDS (4 passes of 8 bits; k_colsort_big
+//                    over global memory for columns past 24,576), then
 //                    ord[c][k] (sample at sorted position k), pos[c][i]
 //                    (sorted position of sample i, 0xFFFF if missing),
 //                    runs[c][k] = s | e << 16 (tie run of position k), n_c and
