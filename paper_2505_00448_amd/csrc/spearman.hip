@@ -1136,28 +1136,34 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                 // table entry gives 0), one block of code; the tied lanes'
                 // products after them, in a branch taken only by a group
                 // that holds tied a-positions
-                uint64_t km[U], tm[U];
-                uint32_t c0[U];
+                // (only the group's first carry and one OR of the tied-lane
+                // ballots stay live; the rare branch rebuilds the chunks'
+                // ballots from the positions)
+                const uint32_t cg = carry1;
+                uint64_t anyt = 0ull;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool kept = pv[u] != miss;
-                    km[u] = __ballot(kept);
-                    tm[u] = __ballot(kept && (pv[u] & POS_TIED));
-                    c0[u] = carry1;
-                    const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(km[u] >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)km[u], carry1));
+                    const uint64_t km = __ballot(kept);
+                    anyt |= __ballot((pv[u] & POS_TIED) != 0u) & km;
+                    const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)km, carry1));
                     t32 += __umul24(cnt1(tab, min(pv[u], XS)), cb1);
-                    carry1 += (uint32_t)__popcll(km[u]);
+                    carry1 += (uint32_t)__popcll(km);
                 }
                 sA4 += t32;
-                if ((tm[0] | tm[1] | tm[2] | tm[3]) != 0ull) {
+                if (anyt != 0ull) {
+                    uint32_t c = cg;
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        if ((tm[u] >> lane) & 1ull) {
+                        const bool kept = pv[u] != miss;
+                        const uint64_t km = __ballot(kept);
+                        if (kept && (pv[u] & POS_TIED)) {
                             const uint32_t cb1 = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(km[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km[u], c0[u]));
+                                (uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, c));
                             sAt += __umul24(ra_of_tied(tab, rlA, rrun, pv[u]), cb1);
                         }
+                        c += (uint32_t)__popcll(km);
                     }
                 }
                 continue;
@@ -1478,7 +1484,7 @@ __device__ __forceinline__ void presence_words(const uint16_t* __restrict__ ordw
 // are predicated.
 __device__ __forceinline__ void copy16_to_lds(uint4* dst, const uint4* __restrict__ src, int n16)
 {
-    constexpr int CU = 8;
+    constexpr int CU = 2;
     for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
         uint4 v[CU];
 #pragma unroll
@@ -1501,7 +1507,7 @@ __device__ __forceinline__ void copy_pos_to_lds(uint4* dst, const uint4* __restr
                                                 uint32_t clamp)
 {
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-    constexpr int CU = 4;
+    constexpr int CU = 3;
     const u16x2 c2 = __builtin_bit_cast(u16x2, clamp | (clamp << 16));
     const uint32_t k2 = keep | (keep << 16);
     const auto fix = [c2, k2](uint32_t w) {
@@ -1578,13 +1584,15 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     int64_t la = 0, b0 = 0;
     if constexpr (!DBG) {
         const int64_t id = (int64_t)blockIdx.x;
-        // band g: pair_band_start(g) <= id < pair_band_start(g + 1)
-        const double A = (double)(nbp + 4);
-        const double disc = A * A - 16.0 * (double)id / (8.0 * PB);
-        int64_t g = (int64_t)((A - sqrt(disc > 0.0 ? disc : 0.0)) / 8.0);
-        if (g < 0) g = 0;
-        while (g > 0 && pair_band_start(g, nbp, PB) > id) --g;
-        while (pair_band_start(g + 1, nbp, PB) <= id && 8 * (g + 1) < nbp) ++g;
+        // band g: the last band (8 g < nbp) with pair_band_start(g) <= id;
+        // the band starts rise with g, so a binary search on the scalar
+        // unit finds it (integer work on uniform values, no vector FP64)
+        int64_t g = 0, ghi = nbp / 8;
+        while (ghi - g > 1) {
+            const int64_t mid = (g + ghi) >> 1;
+            if (pair_band_start(mid, nbp, PB) <= id) g = mid;
+            else ghi = mid;
+        }
         const int64_t r = id - pair_band_start(g, nbp, PB);
         const int64_t len = nbp - 8 * g;
         la = 8 * (int64_t)PB * g + r / len;
