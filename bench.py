@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "57b1aa1907b90f562736d6b8229d2bcbf5970123903efacf8fed4d6b44f2915a",
-    "fetch_kib": 129260.0,
-    "write_kib": 15904.9,
+    "source_sha256": "ddf739dd61500b17b7735d32f3c02cb413e74f88b9ff370f20753dd4af7c39a6",
+    "fetch_kib": 129254.5,
+    "write_kib": 15907.6,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
