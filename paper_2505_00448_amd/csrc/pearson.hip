@@ -796,7 +796,7 @@ __global__ __launch_bounds__(FT_THREADS) void k_pearson_combine(
 {
     __shared__ FinSmem f;
     int tg, th;
-    tile_coords((int)blockIdx.x, T32, tg, th);
+    finish_tile_coords((int)blockIdx.x, T32, tg, th);
     const int64_t g0 = (int64_t)tg * FT, h0 = (int64_t)th * FT;
     const int t = tile_index(tg >> 1, th >> 1, T);
     const int ro = (tg & 1) * FT, co = (th & 1) * FT;  // the quarter inside the 64 x 64 tile

@@ -1816,7 +1816,7 @@ __global__ __launch_bounds__(FT_THREADS) void k_spearman_final(const double4* __
 {
     __shared__ FinSmem f;
     int tg, th;
-    tile_coords((int)blockIdx.x, T32, tg, th);
+    finish_tile_coords((int)blockIdx.x, T32, tg, th);
     const int64_t g0 = (int64_t)tg * FT, h0 = (int64_t)th * FT;
     const int j = ft_col();
     bool valid[FT_K];

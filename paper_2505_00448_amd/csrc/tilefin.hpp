@@ -51,6 +51,26 @@ __host__ __device__ inline int tile_index(int tg, int th, int T)
     return tg * T - tg * (tg - 1) / 2 + (th - tg);
 }
 
+// Launch order of the finish kernels' T (T + 1) / 2 tiles: the T (T - 1) / 2
+// tiles off the diagonal first (row-major over tg < th), the T diagonal
+// tiles last.  A diagonal tile holds about half the pairs, so when the tile
+// count slightly exceeds the workgroups the GPU runs at once (528 tiles at
+// T = 32 against 512 slots), the short second round is made of half tiles.
+__device__ inline void finish_tile_coords(int b, int T, int& tg, int& th)
+{
+    const int noff = T * (T - 1) / 2;
+    if (b >= noff) {
+        tg = th = b - noff;
+        return;
+    }
+    // off-diagonal tile b of the triangle of a (T - 1) x (T - 1) grid whose
+    // row g holds the tiles (g, g + 1 .. T - 1)
+    int g, hh;
+    tile_coords(b, T - 1, g, hh);
+    tg = g;
+    th = hh + 1;
+}
+
 __device__ __forceinline__ int ft_row(int k) { return (int)(threadIdx.x >> 5) + (FT_THREADS / 32) * k; }
 __device__ __forceinline__ int ft_col() { return (int)(threadIdx.x & 31); }
 
