@@ -9,6 +9,8 @@ namespace napy {
 
 struct SpearBase {
     uint16_t* ord;     // [F][ld]
+    uint16_t* ord2;    // [F][ld]: 2 x ord, the byte offset of each sample's entry in a uint16 array
+                       //     indexed by sample (columns sorted in LDS only, S <= SORT_LDS_MAX_S)
     uint16_t* pos;     // [F][ld]
     uint32_t* runs;    // [F][ld]
     uint64_t* tbits;   // [F][ld/64]: bit k set if sorted position k lies in a tie run
@@ -49,6 +51,7 @@ inline void base_carve(Carver& c, int64_t S, int64_t F, SpearBase& b)
 {
     b.ld = spear_ld(S);
     b.ord = c.take<uint16_t>((size_t)F * b.ld + ORD_TAIL);
+    b.ord2 = c.take<uint16_t>((size_t)F * b.ld + ORD_TAIL);
     b.pos = c.take<uint16_t>((size_t)F * b.ld);
     b.runs = c.take<uint32_t>((size_t)F * b.ld);
     b.tbits = c.take<uint64_t>((size_t)F * (b.ld / 64));

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
     const SortSmem sm = sort_smem(sort_raw, E);
     const uint32_t* kc = keys + (int64_t)col * ld;
     uint16_t* ordc = out.ord + (int64_t)col * ld;
+    uint16_t* ord2c = out.ord2 + (int64_t)col * ld;
     uint16_t* posc = out.pos + (int64_t)col * ld;
     uint32_t* runc = out.runs + (int64_t)col * ld;
 
@@ -372,6 +373,7 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
                 const uint32_t s0 = key[e], e0 = END[s0];
                 tied = e0 - s0 > 1u;
                 ordc[k] = (uint16_t)pk[e];
+                ord2c[k] = (uint16_t)(2u * (pk[e] & 0xFFFFu));
                 // a tied sample's position entry holds the flag bit and its
                 // run index instead of the sorted position
                 const uint32_t r0 = tied ? (uint32_t)RID[s0] : 0u;
@@ -388,11 +390,17 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
     // padding: sorted positions past the observed count hold the dummy
     // sample S, whose position is "missing"; tie-bit words past the slots
     // are zero
-    for (int64_t k = nc + t; k < ld; k += CS_THREADS) ordc[k] = (uint16_t)S;
+    for (int64_t k = nc + t; k < ld; k += CS_THREADS) {
+        ordc[k] = (uint16_t)S;
+        ord2c[k] = (uint16_t)(2 * S);
+    }
     for (int64_t i = S + t; i < ld; i += CS_THREADS) posc[i] = 0xFFFF;
     for (int64_t w = (int64_t)(slots >> 6) + t; w < nwords; w += CS_THREADS) tbc[w] = 0ull;
     if (col == (int)gridDim.x - 1)
-        for (int64_t k = t; k < ORD_TAIL; k += CS_THREADS) ordc[ld + k] = (uint16_t)S;
+        for (int64_t k = t; k < ORD_TAIL; k += CS_THREADS) {
+            ordc[ld + k] = (uint16_t)S;
+            ord2c[ld + k] = (uint16_t)(2 * S);
+        }
     if (lane == 0) sm.red[wave] = ntied;
     __syncthreads();
     if (t == 0) {
@@ -1006,6 +1014,21 @@ __device__ __forceinline__ uint32_t a_rank(uint32_t pv, const uint2* tab, const 
 // separately; C1_a C1_b goes to t32.  TA = 2 (a grouped): every sample's R_a
 // from the run-rank table, no partner-table lookup and no branch; R_a C1_b
 // (below 2^31) goes to t32, which the caller empties every two chunks.
+// The walks of columns sorted in LDS (TA <= 2) read b's order doubled
+// (2 x sample index): a's positions sit at the start of the kernel's LDS,
+// which is its dynamic block alone (the launcher checks that the kernel has
+// no static LDS), so the code is the LDS byte address of the sample's
+// a-position and feeds the load with no address arithmetic.  Long columns
+// (TA >= 3) read plain sample indices into a's positions in global memory.
+template <int TA>
+__device__ __forceinline__ uint32_t pos_at(const uint16_t* posA, uint32_t code)
+{
+    if constexpr (TA <= 2) return *(const __attribute__((address_space(3))) uint16_t*)(uintptr_t)code;
+    else return posA[code];
+}
+template <int TA>
+__device__ __forceinline__ uint32_t sample_at(uint32_t code) { return TA <= 2 ? code >> 1 : code; }
+
 template <int TA, bool DBG>
 __device__ __forceinline__ void walk_chunk_untied(uint32_t iv, uint32_t pv, const uint2* tab, uint32_t XS,
                                                   uint32_t miss, const uint32_t* __restrict__ rlA,
@@ -1105,10 +1128,10 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
         const int c0 = g * U;
         uint32_t iv[U] = {}, pv[U];  // iv: sample indices, kept for the debug output only
 #pragma unroll
-        for (int u = 0; u < U; ++u) pv[u] = posA[ivn[u]];
+        for (int u = 0; u < U; ++u) pv[u] = pos_at<TA>(posA, ivn[u]);
         if constexpr (DBG) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) iv[u] = ivn[u];
+            for (int u = 0; u < U; ++u) iv[u] = sample_at<TA>(ivn[u]);
         }
         // prefetch the next group's sample indices into the same registers
         // (rows are padded, so a whole group is always inside the row); the
@@ -1190,8 +1213,8 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
             for (int u = 0; u < U; ++u) {
                 const int c = c0 + u;
                 const uint32_t k = (uint32_t)(c * 64 + lane);
-                const uint32_t ivu = ordB[k];
-                const uint32_t pvu = posA[ivu];
+                const uint32_t ivu = sample_at<TA>(ordB[k]);
+                const uint32_t pvu = pos_at<TA>(posA, ordB[k]);
                 if (((dbits >> u) & 1u) == 0u) {
                     // no tied b-position here, and no run crosses into this chunk
                     walk_chunk_untied<TA, DBG>(ivu, pvu, tab, XS, miss, rlA, rrun, carry1, t32, sAt, dbg_ra, dbg_rb);
@@ -1234,8 +1257,7 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
                             // report the settled rank of every complete sample of the run
                             const uint32_t s0 = __builtin_amdgcn_readlane(rs, 0);
                             for (uint32_t kk = s0 + (uint32_t)lane; kk < e0; kk += 64u) {
-                                const uint32_t ii = ordB[kk];
-                                if (posA[ii] != miss) dbg_rb[ii] = (int32_t)r_open;
+                                if (pos_at<TA>(posA, ordB[kk]) != miss) dbg_rb[sample_at<TA>(ordB[kk])] = (int32_t)r_open;
                             }
                         }
                         pend_lane = 0;
@@ -1295,7 +1317,7 @@ __device__ __forceinline__ void settle_short_runs_b(const uint16_t* __restrict__
         uint32_t t = 0;
         uint64_t sra = 0, sraj = 0;
         for (uint32_t k = s; k < e; ++k) {
-            const uint32_t pv = posA[ordB[k]];
+            const uint32_t pv = pos_at<TA>(posA, ordB[k]);
             if (pv == miss) continue;
             ++t;
             const uint32_t Ra = a_rank<TA>(pv, tab, rlA, rrun);
@@ -1353,7 +1375,7 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
     for (int gi = 0; gi < ngrp; ++gi) {
         uint32_t pv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pv[u] = posA[ivn[u]];
+        for (int u = 0; u < U; ++u) pv[u] = pos_at<TA>(posA, ivn[u]);
         // rows are padded to whole groups of U chunks; the read past the
         // last group stays inside the ord allocation
 #pragma unroll
@@ -1733,7 +1755,7 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
         const int64_t b = DBG ? po.dbg_b : bs.perm[lb];
         const int nbv = bs.ncol[b];
         const int tB = bs.hasties[b];
-        const uint16_t* ordB = bs.ord + b * ld;
+        const uint16_t* ordB = (BIG ? bs.ord : bs.ord2) + b * ld;  // doubled for the LDS path
         const uint32_t* runsB = bs.runs + b * ld;
         const uint64_t* tbB = bs.tbits + b * (ld / 64);
         const uint2* tj = tab + (size_t)j * L.nwp;
@@ -1912,6 +1934,7 @@ __global__ __launch_bounds__(CP_THREADS) void k_compact(SpearBase base, const in
     const uint32_t* brl = base.rlist + c * (base.ld / 2);
     const int nrb = base.nruns[c];
     uint16_t* qord = q.ord + (int64_t)qc * q.ld;
+    uint16_t* qord2 = q.ord2 + (int64_t)qc * q.ld;
     uint16_t* qpos = q.pos + (int64_t)qc * q.ld;
     uint32_t* qruns = q.runs + (int64_t)qc * q.ld;
     uint32_t* qrl = q.rlist + (int64_t)qc * (q.ld / 2);
@@ -1948,14 +1971,21 @@ __global__ __launch_bounds__(CP_THREADS) void k_compact(SpearBase base, const in
         const uint32_t x = X[k];
         if (x != 0xFFFFu) {
             qord[kp] = (uint16_t)x;
+            qord2[kp] = (uint16_t)(2u * x);
             qpos[x] = (uint16_t)kp;
             ++kp;
         }
     }
     if (t == 0) P[nc] = (uint16_t)total;
-    for (int64_t k = total + t; k < q.ld; k += CP_THREADS) qord[k] = (uint16_t)Sq;
+    for (int64_t k = total + t; k < q.ld; k += CP_THREADS) {
+        qord[k] = (uint16_t)Sq;
+        qord2[k] = (uint16_t)(2 * Sq);
+    }
     if (qc == (int)gridDim.x - 1)
-        for (int64_t k = t; k < ORD_TAIL; k += CP_THREADS) qord[q.ld + k] = (uint16_t)Sq;
+        for (int64_t k = t; k < ORD_TAIL; k += CP_THREADS) {
+            qord[q.ld + k] = (uint16_t)Sq;
+            qord2[q.ld + k] = (uint16_t)(2 * Sq);
+        }
     __syncthreads();
 
     // C
@@ -2031,6 +2061,24 @@ static int pairs_launch_t(const SpearBase& bs, const uint8_t* presb, int64_t S, 
     static std::atomic<uint64_t> attr_done{0};
     NAPY_TRY(ensure_dyn_lds(attr_done, (const void*)k_spearman_pairs<PAIR_PB, DBG, BIG>, 160 * 1024,
                             "hipFuncSetAttribute(k_spearman_pairs)"));
+    if constexpr (!BIG) {
+        // the walks take a doubled sample index as the LDS address of its
+        // a-position: the dynamic block (a's positions first) must begin at
+        // LDS address 0, so the kernel may hold no static LDS
+        static std::atomic<int> lds_at0{-1};
+        int v = lds_at0.load(std::memory_order_acquire);
+        if (v < 0) {
+            hipFuncAttributes fa;
+            const hipError_t e = hipFuncGetAttributes(&fa, (const void*)k_spearman_pairs<PAIR_PB, DBG, BIG>);
+            if (e != hipSuccess) return hip_status(e, "hipFuncGetAttributes(k_spearman_pairs)");
+            v = fa.sharedSizeBytes == 0 ? 1 : 0;
+            lds_at0.store(v, std::memory_order_release);
+        }
+        if (v == 0) {
+            set_last_error("k_spearman_pairs holds static LDS: its dynamic block does not begin at address 0");
+            return NAPY_E_HIP;
+        }
+    }
     if (smem > 160 * 1024) return NAPY_E_UNSUPPORTED;
     const int64_t nbp = round_up(ceil_div(F, PAIR_PB), 8);
     const int64_t nblk = DBG ? 1 : pair_grid_size(F, nbp, PAIR_PB);
