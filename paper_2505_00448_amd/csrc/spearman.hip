@@ -1454,6 +1454,20 @@ __device__ __forceinline__ void bit_transpose8(uint32_t& lo, uint32_t& hi)
     hi ^= t >> 4;
 }
 
+// b0 | b1 << 8 | b2 << 16 | b3 << 24 for bytes b0..b3 (values below 256):
+// the pairs (b0, b2) and (b1, b3) as two 16-bit lanes each, then one
+// shift-or (three instructions instead of a shift and an or per byte)
+__device__ __forceinline__ uint32_t join_bytes(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    u16x2 e, o;
+    e.x = (unsigned short)b0;
+    e.y = (unsigned short)b2;
+    o.x = (unsigned short)b1;
+    o.y = (unsigned short)b3;
+    return __builtin_bit_cast(uint32_t, e) | (__builtin_bit_cast(uint32_t, o) << 8);
+}
+
 // Presence of the block's 8 partners at a's sorted positions k0 .. k0 + 31
 // (k0 = 32 w), as one 32-bit word per partner: bit t of x[j] = partner j
 // present at position k0 + t.  Each position's presence byte (bit j =
@@ -1479,8 +1493,9 @@ __device__ __forceinline__ void presence_words(const uint16_t* __restrict__ ordw
             else
                 by[t] = presL[idx];
         }
-        uint32_t lo = by[0] | (by[1] << 8) | (by[2] << 16) | (by[3] << 24);
-        uint32_t hi = by[4] | (by[5] << 8) | (by[6] << 16) | (by[7] << 24);
+        // bytes 0 and 2, then 1 and 3, as 16-bit halves; one shift-or joins them
+        uint32_t lo = join_bytes(by[0], by[1], by[2], by[3]);
+        uint32_t hi = join_bytes(by[4], by[5], by[6], by[7]);
         bit_transpose8(lo, hi);
         blk[q][0] = lo;
         blk[q][1] = hi;
@@ -1659,6 +1674,7 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     // inside a's padded order, and positions from na on hold the sentinel S,
     // whose presence byte is zero; lanes past NW read word NW - 1 and store
     // nothing.  The run-rank table's space holds the per-wave scan totals.
+    static_assert(PAIR_WAVES == 8, "the wave totals fill two rows of 16 lanes");
     const uint16_t* posDbg = bs.pos + (int64_t)po.dbg_b * ld;
     uint32_t* wtot = rrun;  // [PAIR_WAVES][4]
     uint32_t carry[4] = {0u, 0u, 0u, 0u};
@@ -1685,14 +1701,23 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
             for (int h = 0; h < 4; ++h) wtot[wave * 4 + h] = incl[h];
         }
         __syncthreads();
-        uint32_t base[4] = {carry[0], carry[1], carry[2], carry[3]};
-#pragma unroll
-        for (int v = 0; v < PAIR_WAVES; ++v) {
+        // the wave totals, lane 4 v + h holding wave v's for pair h, summed
+        // over the waves of each row of 16 lanes (waves 0-3 and 4-7) by two
+        // row shifts; this wave's base and the pass total are then read
+        // from the row ends and the lane of the wave before it
+        uint32_t base[4];
+        {
+            constexpr int ROW_SHR = 0x110;
+            int sv = lane < 4 * PAIR_WAVES ? (int)wtot[lane] : 0;
+            sv += __builtin_amdgcn_update_dpp(0, sv, ROW_SHR + 4, 0xF, 0xF, false);
+            sv += __builtin_amdgcn_update_dpp(0, sv, ROW_SHR + 8, 0xF, 0xF, false);
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                const uint32_t tv = wtot[v * 4 + h];
-                if (v < wave) base[h] += tv;
-                carry[h] += tv;
+                const uint32_t row0 = (uint32_t)__builtin_amdgcn_readlane(sv, 12 + h);
+                const uint32_t row1 = (uint32_t)__builtin_amdgcn_readlane(sv, 28 + h);
+                const uint32_t prev = wave > 0 ? (uint32_t)__builtin_amdgcn_readlane(sv, 4 * (wave - 1) + h) : 0u;
+                base[h] = carry[h] + prev + (wave > 4 ? row0 : 0u);
+                carry[h] += row0 + row1;
             }
         }
         if (valid) {
