@@ -1630,10 +1630,12 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
             if (pair_band_start(mid, nbp, PB) <= id) g = mid;
             else ghi = mid;
         }
-        const int64_t r = id - pair_band_start(g, nbp, PB);
-        const int64_t len = nbp - 8 * g;
-        la = 8 * (int64_t)PB * g + r / len;
-        b0 = (8 * g + r % len) * PB;
+        // the offset in the band and the band's row length are below 2^31
+        // (the grid is), so the division is a 32-bit one
+        const uint32_t r = (uint32_t)(id - pair_band_start(g, nbp, PB));
+        const uint32_t len = (uint32_t)(nbp - 8 * g);
+        la = 8 * (int64_t)PB * g + (int64_t)(r / len);
+        b0 = (8 * g + (int64_t)(r % len)) * PB;
         if (la >= F || b0 >= F || b0 + PB - 1 < la) return;
     }
     const int64_t a = DBG ? po.dbg_a : bs.perm[la];
@@ -1681,7 +1683,8 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     for (int w0 = 0; w0 < NW; w0 += PAIR_THREADS) {
         const int w = w0 + (int)threadIdx.x;
         const bool valid = w < NW;
-        uint32_t x[8] = {};
+        // a wave past the last word has no masks and zero counts
+        uint32_t x[8] = {}, pc[4] = {}, incl[4] = {};
         if (w0 + wave * 64 < NW) {  // wave-uniform
             const int wl = valid ? w : NW - 1;
             presence_words<DBG>(ordA + 32 * wl, presL, posDbg, 32 * wl, na, x);
@@ -1689,12 +1692,11 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
 #pragma unroll
                 for (int j = 0; j < 8; ++j) x[j] = 0u;
             }
-        }
-        uint32_t pc[4], incl[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            pc[h] = (uint32_t)__popc(x[2 * h]) | ((uint32_t)__popc(x[2 * h + 1]) << 16);
-            incl[h] = wave_incl_scan_u32(pc[h]);
+            for (int h = 0; h < 4; ++h) {
+                pc[h] = (uint32_t)__popc(x[2 * h]) | ((uint32_t)__popc(x[2 * h + 1]) << 16);
+                incl[h] = wave_incl_scan_u32(pc[h]);
+            }
         }
         if (lane == 63) {
 #pragma unroll
