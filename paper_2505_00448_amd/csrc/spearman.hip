@@ -1014,6 +1014,23 @@ __device__ __forceinline__ uint32_t a_rank(uint32_t pv, const uint2* tab, const 
 // separately; C1_a C1_b goes to t32.  TA = 2 (a grouped): every sample's R_a
 // from the run-rank table, no partner-table lookup and no branch; R_a C1_b
 // (below 2^31) goes to t32, which the caller empties every two chunks.
+// A wave-uniform pointer computed where it stands: the lane read is
+// convergent, so the compiler does not sink the address arithmetic into the
+// divergent blocks that use it (which would keep the base's pointers live
+// through the walk loops, spilled and reloaded there)
+// (the lane-read builtin takes and returns 32 bits: the two halves of the
+// address are read separately; the result is rebuilt as a global-memory
+// pointer, so that its loads stay global loads, not flat ones)
+template <class T>
+__device__ __forceinline__ T* pin_uniform(T* p)
+{
+    typedef __attribute__((address_space(1))) T GT;
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (T*)(GT*)(((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
 // The walks of columns sorted in LDS (TA <= 2) read b's order doubled
 // (2 x sample index): a's positions sit at the start of the kernel's LDS,
 // which is its dynamic block alone (the launcher checks that the kernel has
@@ -1642,21 +1659,44 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
 
     const int64_t ld = bs.ld;
     const PairSmem L = pair_smem(ld, S, PB, BIG);
-    uint16_t* posA = BIG ? bs.pos + a * ld : (uint16_t*)smem_raw;
+    uint16_t* posA = BIG ? pin_uniform(bs.pos + a * ld) : (uint16_t*)smem_raw;
     uint2* tab = (uint2*)(smem_raw + L.off_tab);                               // [PB][nwp]
     unsigned long long* corrA = (unsigned long long*)(smem_raw + L.off_corr);  // [PB]
     uint32_t* rrun = (uint32_t*)(smem_raw + L.off_rrun);                       // [PB][RUN_TABLE_STRIDE]
 
     const int na = bs.ncol[a];
     const int tA = bs.hasties[a];
-    const uint16_t* ordA = bs.ord + a * ld;
-    const uint32_t* rlA = bs.rlist + a * (ld / 2);
-    const uint32_t* runsA = bs.runs + a * ld;  // a's runs by position (long columns)
+    const uint16_t* ordA = pin_uniform(bs.ord + a * ld);
+    const uint32_t* rlA = pin_uniform(bs.rlist + a * (ld / 2));
+    const uint32_t* runsA = pin_uniform(bs.runs + a * ld);  // a's runs by position (long columns)
     const int nra = tA ? bs.nruns[a] : 0;
     const bool rtab = !BIG && tA && nra <= RUN_TABLE_MAX;  // run-rank table in LDS
     const int nsg = (!DBG && !BIG && tA) ? bs.nsing[a] : -1;
     const bool grouped = nsg >= 0;  // implies rtab (runs + untied positions <= RUN_TABLE_MAX)
-    const uint16_t* sgA = bs.sing + a * RUN_GROUPS_MAX;
+    const uint16_t* sgA = pin_uniform(bs.sing + a * RUN_GROUPS_MAX);
+    const uint16_t* posAg = pin_uniform(bs.pos + a * ld);
+
+    // this wave's partner j = wave (one partner per wave; the debug form has
+    // one partner, on wave 0): its column and pointers are read here, so
+    // that the base's pointers die before the tables are built
+    static_assert(PB <= PAIR_WAVES, "one partner per wave");
+    const int j = wave;
+    const int64_t lb = b0 + j;
+    const bool jact = DBG ? j == 0 : (j < PB && lb < F && lb >= la);
+    const int64_t b = DBG ? (int64_t)po.dbg_b : (jact ? (int64_t)bs.perm[lb] : 0);
+    const int nbv = jact ? bs.ncol[b] : 0;
+    const int tB = jact ? bs.hasties[b] : 0;
+    // b's tie runs resolved in the walk (class 2), or settled after an
+    // untied walk (class 1; the debug walk reports every rank, so it
+    // resolves them in the walk)
+    const int cB = DBG ? (tB ? 2 : 0) : (jact ? bs.tcls[b] : 0);
+    const int nsgB = DBG ? -1 : (jact ? bs.nsing[b] : -1);
+    const int nrb = jact ? bs.nruns[b] : 0;
+    const uint16_t* ordB = pin_uniform((BIG ? bs.ord : bs.ord2) + b * ld);  // doubled for the LDS path
+    const uint32_t* runsB = pin_uniform(bs.runs + b * ld);
+    const uint64_t* tbB = pin_uniform(bs.tbits + b * (ld / 64));
+    const uint32_t* rlB = pin_uniform(bs.rlist + b * (ld / 2));
+    const uint16_t* sgB = pin_uniform(bs.sing + b * RUN_GROUPS_MAX);
     const int NW = (na + 1 + 31) >> 5;  // words covering positions 0..na
     // the partner block's presence bytes go where a's positions will be
     // (they are needed only while the tables are built); lane-wise gathers
@@ -1677,7 +1717,7 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     // whose presence byte is zero; lanes past NW read word NW - 1 and store
     // nothing.  The run-rank table's space holds the per-wave scan totals.
     static_assert(PAIR_WAVES == 8, "the wave totals fill two rows of 16 lanes");
-    const uint16_t* posDbg = bs.pos + (int64_t)po.dbg_b * ld;
+    const uint16_t* posDbg = pin_uniform(bs.pos + (int64_t)po.dbg_b * ld);
     uint32_t* wtot = rrun;  // [PAIR_WAVES][4]
     uint32_t carry[4] = {0u, 0u, 0u, 0u};
     for (int w0 = 0; w0 < NW; w0 += PAIR_THREADS) {
@@ -1740,7 +1780,7 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     const uint32_t XS = 32u * (uint32_t)NW;
     const uint32_t miss = BIG ? 0xFFFFu : grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS;
     if constexpr (!BIG)
-        copy_pos_to_lds((uint4*)posA, (const uint4*)(bs.pos + a * ld), (int)((S + 1 + 7) / 8),
+        copy_pos_to_lds((uint4*)posA, (const uint4*)posAg, (int)((S + 1 + 7) / 8),
                         grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS);
     __syncthreads();
     if (tA) {
@@ -1776,29 +1816,13 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     }
 
     // ---- step 2: one walk of each partner's sorted order ---------------------
-    for (int j = wave; j < (DBG ? 1 : PB); j += PAIR_WAVES) {
-        const int64_t lb = b0 + j;
-        if (!DBG && (lb >= F || lb < la)) continue;
-        const int64_t b = DBG ? po.dbg_b : bs.perm[lb];
-        const int nbv = bs.ncol[b];
-        const int tB = bs.hasties[b];
-        const uint16_t* ordB = (BIG ? bs.ord : bs.ord2) + b * ld;  // doubled for the LDS path
-        const uint32_t* runsB = bs.runs + b * ld;
-        const uint64_t* tbB = bs.tbits + b * (ld / 64);
+    if (jact) {
         const uint2* tj = tab + (size_t)j * L.nwp;
         const uint32_t* rj = rtab ? rrun + j * RUN_TABLE_STRIDE : nullptr;
-        // b's tie runs resolved in the walk (class 2), or settled after an
-        // untied walk (class 1; the debug walk reports every rank, so it
-        // resolves them in the walk)
-        const int cB = DBG ? (tB ? 2 : 0) : bs.tcls[b];
-        const int nsgB = DBG ? -1 : bs.nsing[b];
         WalkSums w;
         uint64_t sA, d3B;
         if (nsgB >= 0) {
             // b grouped: one pass by value groups
-            const uint32_t* rlB = bs.rlist + b * (ld / 2);
-            const int nrb = bs.nruns[b];
-            const uint16_t* sgB = bs.sing + b * RUN_GROUPS_MAX;
             uint32_t ng;
             if constexpr (BIG) {
                 if (tA) grouped_b_walk<4>(ordB, nbv, rlB, nrb, sgB, nsgB, posA, tj, runsA, rj, XS, miss, lane, sA, ng, d3B);
@@ -1831,8 +1855,6 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
             int64_t corr = 0;
             uint64_t d3s = 0;
             if (!DBG && cB == 1) {
-                const uint32_t* rlB = bs.rlist + b * (ld / 2);
-                const int nrb = bs.nruns[b];
                 if constexpr (BIG) {
                     if (tA) settle_short_runs_b<4>(ordB, rlB, nrb, posA, tj, runsA, rj, miss, lane, corr, d3s);
                     else settle_short_runs_b<3>(ordB, rlB, nrb, posA, tj, runsA, rj, miss, lane, corr, d3s);
