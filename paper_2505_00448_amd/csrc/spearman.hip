@@ -1154,9 +1154,11 @@ __device__ __forceinline__ void pair_walk(const uint16_t* __restrict__ ordB, con
         // (rows are padded, so a whole group is always inside the row); the
         // last group reloads its own, which keeps the loop body one block
         {
-            const uint16_t* nx = ordB + (size_t)((g + 1 < ngrp) ? c0 + U : c0) * 64;  // wave-uniform
+            // (a scalar base pinned per group and an unsigned lane offset: the
+            // loads take the scalar-base form, with no 64-bit address add)
+            const uint16_t* nx = pin_uniform(ordB + (size_t)((g + 1 < ngrp) ? c0 + U : c0) * 64);
 #pragma unroll
-            for (int u = 0; u < U; ++u) ivn[u] = nx[u * 64 + lane];
+            for (int u = 0; u < U; ++u) ivn[u] = nx[(uint32_t)lane + 64u * (uint32_t)u];
         }
         uint32_t dbits = 0;  // bit u: chunk c0 + u holds tied b-positions
         if constexpr (TB) {
@@ -1395,8 +1397,11 @@ __device__ __forceinline__ void grouped_b_walk(const uint16_t* __restrict__ ordB
         for (int u = 0; u < U; ++u) pv[u] = pos_at<TA>(posA, ivn[u]);
         // rows are padded to whole groups of U chunks; the read past the
         // last group stays inside the ord allocation
+        {
+            const uint16_t* nx = pin_uniform(ordB + (size_t)(gi + 1) * U * 64);
 #pragma unroll
-        for (int u = 0; u < U; ++u) ivn[u] = ordB[((gi + 1) * U + u) * 64 + lane];
+            for (int u = 0; u < U; ++u) ivn[u] = nx[(uint32_t)lane + 64u * (uint32_t)u];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t c0 = (uint32_t)((gi * U + u) * 64);
@@ -1556,9 +1561,22 @@ __device__ __forceinline__ void copy16_to_lds(uint4* dst, const uint4* __restric
 
 // copy16_to_lds for a column's sorted positions (u16, 0xFFFF for a missing
 // sample), each u16 v written as min(v & keep, clamp) (two u16 per packed
-// 16-bit min)
+// 16-bit min).  The first POS_PRE x PAIR_THREADS words are loaded ahead by
+// pos_prefetch (so that their latency passes during the table build) and
+// handed in as pre; the rest are loaded here.
+constexpr int POS_PRE = 3;
+
+__device__ __forceinline__ void pos_prefetch(const uint4* __restrict__ src, int n16, uint4 (&pre)[POS_PRE])
+{
+#pragma unroll
+    for (int u = 0; u < POS_PRE; ++u) {
+        const int w = u * PAIR_THREADS + (int)threadIdx.x;
+        pre[u] = src[w < n16 ? w : n16 - 1];
+    }
+}
+
 __device__ __forceinline__ void copy_pos_to_lds(uint4* dst, const uint4* __restrict__ src, int n16, uint32_t keep,
-                                                uint32_t clamp)
+                                                uint32_t clamp, const uint4 (&pre)[POS_PRE])
 {
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
     constexpr int CU = 3;
@@ -1567,7 +1585,12 @@ __device__ __forceinline__ void copy_pos_to_lds(uint4* dst, const uint4* __restr
     const auto fix = [c2, k2](uint32_t w) {
         return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, w & k2), c2));
     };
-    for (int w0 = 0; w0 < n16; w0 += PAIR_THREADS * CU) {
+#pragma unroll
+    for (int u = 0; u < POS_PRE; ++u) {
+        const int w = u * PAIR_THREADS + (int)threadIdx.x;
+        if (w < n16) dst[w] = make_uint4(fix(pre[u].x), fix(pre[u].y), fix(pre[u].z), fix(pre[u].w));
+    }
+    for (int w0 = POS_PRE * PAIR_THREADS; w0 < n16; w0 += PAIR_THREADS * CU) {
         uint4 v[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
@@ -1702,6 +1725,9 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     // (they are needed only while the tables are built); lane-wise gathers
     // from LDS instead of global memory
     const uint8_t* presL = BIG ? presb + (b0 / PB) * ld : (const uint8_t*)smem_raw;
+    // a's positions: the first words loaded now, stored after the table build
+    uint4 pos_pre[POS_PRE];
+    if constexpr (!BIG) pos_prefetch((const uint4*)posAg, (int)((S + 1 + 7) / 8), pos_pre);
     // bytes 0..S: byte S is zero (the sentinel sample of a's padded order)
     if constexpr (!DBG && !BIG)
         copy16_to_lds((uint4*)smem_raw, (const uint4*)(presb + (b0 / PB) * ld), (int)((S + 16) / 16));
@@ -1781,7 +1807,7 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
     const uint32_t miss = BIG ? 0xFFFFu : grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS;
     if constexpr (!BIG)
         copy_pos_to_lds((uint4*)posA, (const uint4*)posAg, (int)((S + 1 + 7) / 8),
-                        grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS);
+                        grouped ? POS_MASK : 0xFFFFu, grouped ? MISS_GROUPED : tA ? 0xFFFFu : XS, pos_pre);
     __syncthreads();
     if (tA) {
         // per tie run [s, e) of a and partner: C(e) - C(s) complete samples
@@ -1790,9 +1816,13 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
         // after the runs, and its untied samples' positions become those
         // runs' numbers (its tied samples' became their runs' numbers in
         // the copy)
-        const int nj = DBG ? 1 : PB;
+        // one thread per (run, partner): a's few runs are spread over the
+        // block instead of taking the partners one after another
+        constexpr int LNJ = DBG ? 0 : 3;
+        static_assert(DBG || PB == (1 << LNJ), "partners per block");
         const int ngr = grouped ? nra + nsg : nra;
-        for (int r = threadIdx.x; r < ngr; r += PAIR_THREADS) {
+        for (int q = threadIdx.x; q < (ngr << LNJ); q += PAIR_THREADS) {
+            const int r = q >> LNJ, jr = q & ((1 << LNJ) - 1);
             uint32_t s, e;
             if (r < nra) {
                 const uint32_t rr = rlA[r];
@@ -1801,17 +1831,15 @@ __global__ __launch_bounds__(PAIR_THREADS, 8) void k_spearman_pairs(SpearBase bs
             } else {
                 s = sgA[r - nra];
                 e = s + 1u;
-                posA[ordA[s]] = (uint16_t)r;
+                if (jr == 0) posA[ordA[s]] = (uint16_t)r;
             }
-            for (int j = 0; j < nj; ++j) {
-                const uint2* tj = tab + (size_t)j * L.nwp;
-                const uint32_t c1s = cnt1(tj, s), c1e = cnt1(tj, e);
-                if (rtab) rrun[j * RUN_TABLE_STRIDE + r] = c1s + c1e - 1u;
-                const uint32_t tt = c1e - c1s;
-                if (tt > 1u) atomicAdd(&corrA[j], (unsigned long long)cube_minus(tt));
-            }
+            const uint2* tj = tab + (size_t)jr * L.nwp;
+            const uint32_t c1s = cnt1(tj, s), c1e = cnt1(tj, e);
+            if (rtab) rrun[jr * RUN_TABLE_STRIDE + r] = c1s + c1e - 1u;
+            const uint32_t tt = c1e - c1s;
+            if (tt > 1u) atomicAdd(&corrA[jr], (unsigned long long)cube_minus(tt));
         }
-        if (rtab && threadIdx.x < nj) rrun[threadIdx.x * RUN_TABLE_STRIDE + RUN_TABLE_MAX] = 0u;
+        if (rtab && threadIdx.x < (1 << LNJ)) rrun[threadIdx.x * RUN_TABLE_STRIDE + RUN_TABLE_MAX] = 0u;
         __syncthreads();
     }
 
