@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "ddf739dd61500b17b7735d32f3c02cb413e74f88b9ff370f20753dd4af7c39a6",
-    "fetch_kib": 129254.5,
-    "write_kib": 15907.6,
+    "source_sha256": "55b9731163c243bd9d93010073836b68634dd2d2cb9d65e63a56f000601f3a25",
+    "fetch_kib": 135840.6,
+    "write_kib": 15913.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
