@@ -746,30 +746,37 @@ __global__ void k_fill_zero_i32(int32_t* __restrict__ a, int64_t count)
     if (i < count) a[i] = 0;
 }
 
-// one step of a 64-bit inclusive scan over the wave: the value of the lane
-// CTRL selects (0 where there is none or its row is masked off) added
-template <int CTRL, int RMASK>
-__device__ __forceinline__ uint64_t dpp_step_u64(uint64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RMASK, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RMASK, 0xF, false);
-    return v + (((uint64_t)hi << 32) | lo);
-}
+// Wave total of a 64-bit value: an inclusive scan by DPP row shifts and
+// broadcasts, read at lane 63 (no LDS traffic, unlike lane shuffles).  Each
+// step is one add of the low halves with carry-out and one add of the high
+// halves with that carry, both taking their first operand from the lane the
+// DPP control selects.  With the bound control off, a lane with no such
+// source (first lanes of a row, rows masked off) does not execute the adds
+// and keeps its value, which is what a scan step adds to it (nothing).  The
+// compiler does not fuse the row moves into 64-bit adds, so the two adds are
+// written out; the leading s_nop covers the two wait states a DPP read needs
+// after a VALU write of its source (the other step's or the caller's).
+#define NAPY_DPP_ADD64_STEP(CTRL)                                          \
+    asm volatile("s_nop 1\n\t"                                            \
+                 "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL "\n\t"         \
+                 "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL            \
+                 : "+v"(lo), "+v"(hi)                                      \
+                 :                                                          \
+                 : "vcc")
 
-// Wave totals by DPP row shifts and broadcasts (an inclusive scan, read at
-// lane 63): no LDS traffic, unlike lane shuffles.  The result is uniform.
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {
-    constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
-    v = dpp_step_u64<ROW_SHR + 1, 0xF>(v);
-    v = dpp_step_u64<ROW_SHR + 2, 0xF>(v);
-    v = dpp_step_u64<ROW_SHR + 4, 0xF>(v);
-    v = dpp_step_u64<ROW_SHR + 8, 0xF>(v);
-    v = dpp_step_u64<ROW_BCAST15, 0xA>(v);
-    v = dpp_step_u64<ROW_BCAST31, 0xC>(v);
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    NAPY_DPP_ADD64_STEP("row_shr:1 row_mask:0xf bank_mask:0xf");
+    NAPY_DPP_ADD64_STEP("row_shr:2 row_mask:0xf bank_mask:0xf");
+    NAPY_DPP_ADD64_STEP("row_shr:4 row_mask:0xf bank_mask:0xf");
+    NAPY_DPP_ADD64_STEP("row_shr:8 row_mask:0xf bank_mask:0xf");
+    NAPY_DPP_ADD64_STEP("row_bcast:15 row_mask:0xa bank_mask:0xf");
+    NAPY_DPP_ADD64_STEP("row_bcast:31 row_mask:0xc bank_mask:0xf");
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
 }
+#undef NAPY_DPP_ADD64_STEP
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
