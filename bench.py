@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "55b9731163c243bd9d93010073836b68634dd2d2cb9d65e63a56f000601f3a25",
-    "fetch_kib": 135840.6,
-    "write_kib": 15913.4,
+    "source_sha256": "79f2d5b0c3706c1230a08a7fab2f19a58a6ca1c2a3d04139917ae5e573dadb9b",
+    "fetch_kib": 135855.2,
+    "write_kib": 15915.7,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
