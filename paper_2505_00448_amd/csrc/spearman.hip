@@ -160,6 +160,28 @@ __device__ __forceinline__ int wave_incl_max_scan(int x)
 // into destinations, scatters the keys in LDS and reloads them.  The tail
 // derives tie runs from the sorted keys: ord, pos, runs, the tie-run list,
 // tie bits and counts.
+// Sum (op 0) or maximum (op 1) over the waves of the sort block of one value
+// per wave, stored at w[0 .. CS_WAVES): lane v reads wave v's value and a
+// scan over the first row of 16 lanes (four DPP row shifts) gives, by lane
+// reads, the part over the waves before this one and the whole (both
+// wave-uniform), instead of every thread looping over the 16 values
+template <int OP>
+__device__ __forceinline__ void cs_wave_prefix(const uint32_t* w, int lane, int wave, uint32_t& before,
+                                               uint32_t& total)
+{
+    static_assert(CS_WAVES == 16, "one row of 16 lanes");
+    constexpr int ROW_SHR = 0x110;
+    int x = lane < CS_WAVES ? (int)w[lane] : 0;
+    // (values are non-negative: 0, shifted in, is the identity of both)
+    const auto op = [](int a, int b) { return OP == 0 ? a + b : max(a, b); };
+    x = op(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 1, 0xF, 0xF, false));
+    x = op(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 2, 0xF, 0xF, false));
+    x = op(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 4, 0xF, 0xF, false));
+    x = op(x, __builtin_amdgcn_update_dpp(0, x, ROW_SHR + 8, 0xF, 0xF, false));
+    total = (uint32_t)__builtin_amdgcn_readlane(x, CS_WAVES - 1);
+    before = wave > 0 ? (uint32_t)__builtin_amdgcn_readlane(x, wave - 1) : 0u;
+}
+
 template <int EPT>
 __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const uint32_t* __restrict__ keys, int64_t S,
                                                           int64_t ld, SpearBase out)
@@ -189,13 +211,8 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
     const uint32_t oincl = wave_incl_scan_u32(nobs);
     if (lane == 63) sm.red[wave] = oincl;
     __syncthreads();
-    uint32_t obase = 0, ncount = 0;
-#pragma unroll
-    for (int v = 0; v < CS_WAVES; ++v) {
-        const uint32_t tv = sm.red[v];
-        obase += v < wave ? tv : 0u;
-        ncount += tv;
-    }
+    uint32_t obase, ncount;
+    cs_wave_prefix<0>(sm.red, lane, wave, obase, ncount);
     obase += oincl - nobs;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -271,9 +288,9 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
             const uint32_t incl = wave_incl_scan_u32(sum);
             if (lane == 63) sm.red[CS_WAVES + wave] = incl;
             __syncthreads();
-            uint32_t run = incl - sum;
-#pragma unroll
-            for (int v = 0; v < CS_WAVES; ++v) run += v < wave ? sm.red[CS_WAVES + v] : 0u;
+            uint32_t before, all;
+            cs_wave_prefix<0>(sm.red + CS_WAVES, lane, wave, before, all);
+            uint32_t run = incl - sum + before;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 sm.wcnt[(4 * q + i) * 256 + dd] = (uint16_t)run;
@@ -333,17 +350,10 @@ __global__ __launch_bounds__(CS_THREADS, EPT <= 10 ? 8 : 4) void k_colsort(const
         sm.red[3 * CS_WAVES + wave] = ntr;
     }
     __syncthreads();  // also: every neighbour key has been read
-    int cin = 0;
-    uint32_t rid = 0, nrun = 0;
-#pragma unroll
-    for (int v = 0; v < CS_WAVES; ++v) {
-        const uint32_t c = sm.red[2 * CS_WAVES + v], r = sm.red[3 * CS_WAVES + v];
-        if (v < wave) {
-            cin = max(cin, (int)c);
-            rid += r;
-        }
-        nrun += r;
-    }
+    uint32_t cin_u, cmax, rid, nrun;
+    cs_wave_prefix<1>(sm.red + 2 * CS_WAVES, lane, wave, cin_u, cmax);
+    cs_wave_prefix<0>(sm.red + 3 * CS_WAVES, lane, wave, rid, nrun);
+    int cin = (int)cin_u;
     uint16_t* END = sm.idx;             // END[s] = end of the run starting at s
     uint16_t* RID = (uint16_t*)sm.key;  // RID[s] = index of the tie run starting at s
     uint32_t* rlc = out.rlist + (int64_t)col * (ld / 2);
