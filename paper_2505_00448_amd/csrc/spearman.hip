@@ -124,9 +124,13 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d)
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);  // 0 or all ones
-        const uint64_t bl = __ballot(sb != 0u);
-        nlo |= (uint32_t)bl ^ sb;
-        nhi |= (uint32_t)(bl >> 32) ^ sb;
+        // the lane mask of sb != 0 as a compare of sb itself (33: not equal;
+        // written as a ballot, the compare is rebuilt from a shift of d)
+        const uint64_t bl = __builtin_amdgcn_uicmp(sb, 0u, 33);
+        // the lanes that differ from this one in bit b: n |= bl ^ sb, one
+        // three-input bit operation per half (0xF6: a | (b ^ c))
+        nlo = __builtin_amdgcn_bitop3_b32(nlo, (uint32_t)bl, sb, 0xF6);
+        nhi = __builtin_amdgcn_bitop3_b32(nhi, (uint32_t)(bl >> 32), sb, 0xF6);
     }
     return ((uint64_t)~nhi << 32) | (uint64_t)~nlo;
 }
