@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "79f2d5b0c3706c1230a08a7fab2f19a58a6ca1c2a3d04139917ae5e573dadb9b",
-    "fetch_kib": 135855.2,
-    "write_kib": 15915.7,
+    "source_sha256": "0a6d75a37f62d83008c801e7c01f9379969f1aea2b4b73fddbf7c4f0d6f88559",
+    "fetch_kib": 135812.1,
+    "write_kib": 15904.6,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
