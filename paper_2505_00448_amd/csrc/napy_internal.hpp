@@ -149,8 +149,10 @@ int labels_launch(const float* L, int64_t ldl, int64_t S, int64_t FC, int ncat, 
 
 int colstats_plan_chunks(int64_t S, int64_t F);
 void colstats_carve(Carver& c, int64_t S, int64_t F, ColStats& cs);
+// zero_word (may be null): a 32-bit word the final kernel also sets to zero
+// (a counter that a later kernel of the same call starts from)
 int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
-                    const ColStats& cs, hipStream_t st);
+                    const ColStats& cs, hipStream_t st, uint32_t* zero_word = nullptr);
 
 // Row/column gather for subset queries: Xq[i][c] = X[rows[i]][cols[c]].
 int gather_launch(const float* X, int64_t ldx, const int32_t* rows, int64_t Sq,

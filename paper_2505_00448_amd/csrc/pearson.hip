@@ -94,8 +94,9 @@ __global__ __launch_bounds__(256) void k_colstats_partial(
 // and a fixed butterfly adds the lanes (the same order on every call)
 __global__ __launch_bounds__(256) void k_colstats_final(
     int R, int64_t F, const int32_t* __restrict__ pcnt, const double* __restrict__ psum,
-    int32_t* __restrict__ ncol, float* __restrict__ mu32, double* __restrict__ mu64)
+    int32_t* __restrict__ ncol, float* __restrict__ mu32, double* __restrict__ mu64, uint32_t* __restrict__ zero_word)
 {
+    if (zero_word && blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0u;
     const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (c >= F) return;
@@ -139,7 +140,7 @@ void colstats_carve(Carver& c, int64_t S, int64_t F, ColStats& cs)
 }
 
 int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
-                    const ColStats& cs, hipStream_t st)
+                    const ColStats& cs, hipStream_t st, uint32_t* zero_word)
 {
     const int R = cs.rows_chunks;
     const int64_t rows_per = ceil_div(S, R);
@@ -148,7 +149,7 @@ int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_s
                        rows_per, cs.pcnt, cs.psum);
     NAPY_TRY(check_launch("colstats_partial"));
     hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, R, F,
-                       cs.pcnt, cs.psum, cs.n, cs.mu32, cs.mu64);
+                       cs.pcnt, cs.psum, cs.n, cs.mu32, cs.mu64, zero_word);
     return check_launch("colstats_final");
 }
 
@@ -840,8 +841,6 @@ __global__ __launch_bounds__(FT_THREADS) void k_pearson_combine(
     ft_write(f, g0, h0, F, r, p, n, ldo);
 }
 
-__global__ void k_zero_u32(uint32_t* __restrict__ a) { *a = 0u; }
-
 // Recomputation of the listed pairs from the raw values in FP64, one
 // workgroup per pair: a first pass over the samples takes n, the sums of
 // both sides and their minima and maxima over I(g,h); a second pass the
@@ -1056,7 +1055,9 @@ static int pearson_run_plan(const float* X, int64_t S, int64_t F, int64_t ldx, d
     double* part = w.part;
 
     NAPY_TRY(record_stage(ev, 0, st));
-    NAPY_TRY(colstats_launch(X, S, F, ldx, us, sv, cs, st));
+    // (the final column-statistics kernel also clears the recomputation
+    // list's counter, which the combine appends to)
+    NAPY_TRY(colstats_launch(X, S, F, ldx, us, sv, cs, st, w.redo_count));
     NAPY_TRY(record_stage(ev, 1, st));
     const unsigned nb = (unsigned)(pl.ntiles * pl.nsplit);
     switch (prec) {
@@ -1081,8 +1082,6 @@ static int pearson_run_plan(const float* X, int64_t S, int64_t F, int64_t ldx, d
     }
     NAPY_TRY(check_launch("pearson_tiles"));
     NAPY_TRY(record_stage(ev, 2, st));
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, w.redo_count);
-    NAPY_TRY(check_launch("zero"));
     const int T32 = (int)ceil_div(F, FT);
     hipLaunchKernelGGL(k_pearson_combine, dim3((unsigned)(T32 * (T32 + 1) / 2)), dim3(FT_THREADS), 0, st, part,
                        pl.T, pl.ntiles, pl.nsplit, F, T32, r, p, n, ldo, saved, w.redo_count, w.redo);
