@@ -905,22 +905,36 @@ static int tiebits_launch(const SpearBase& bs, int64_t F, hipStream_t st, bool w
 
 // Presence bytes in processing order, one plane per block of 8 columns:
 // bit j of presb[q][i] = sample i present in column perm[8 q + j].  A pair
-// workgroup copies its partner block's plane (S bytes) into LDS.
+// workgroup copies its partner block's plane (S bytes) into LDS.  Each
+// thread makes four consecutive bytes (ld is a multiple of 256), from eight
+// 8-byte loads issued together.
 __global__ __launch_bounds__(256) void k_presence(SpearBase bs, int64_t S, int64_t F, uint8_t* __restrict__ presb)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     const int64_t q = blockIdx.y;
-    if (i >= bs.ld) return;
-    uint32_t byte = 0u;
-    if (i < S) {
-        const int64_t c0 = q * 8;
-        const int nj = (int)min((int64_t)8, F - c0);
-        for (int j = 0; j < nj; ++j) {
-            const int64_t col = bs.perm[c0 + j];
-            byte |= (uint32_t)(bs.pos[col * bs.ld + i] != 0xFFFF) << j;
-        }
+    if (i0 >= bs.ld) return;
+    const int64_t c0 = q * 8;
+    uint2 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        // a column past F reads column perm[c0] and is masked below
+        const int64_t col = bs.perm[c0 + j < F ? c0 + j : c0];
+        v[j] = *(const uint2*)(bs.pos + col * bs.ld + i0);
     }
-    presb[q * bs.ld + i] = (uint8_t)byte;
+    uint32_t word = 0u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (c0 + j >= F) continue;
+        const uint32_t h[4] = {v[j].x & 0xFFFFu, v[j].x >> 16, v[j].y & 0xFFFFu, v[j].y >> 16};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) word |= (uint32_t)(h[u] != 0xFFFFu) << (8 * u + j);
+    }
+    // samples from S on are absent (their positions hold 0xFFFF, but the
+    // bytes are cleared explicitly)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (i0 + u >= S) word &= ~(0xFFu << (8 * u));
+    *(uint32_t*)(presb + q * bs.ld + i0) = word;
 }
 
 constexpr int PAIR_THREADS = 512;
@@ -2190,7 +2204,7 @@ static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t 
 {
     uint8_t* presb = (uint8_t*)pres;
     const int64_t nq = ceil_div(F, 8);
-    hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 256), (unsigned)nq), dim3(256), 0, st, bs, S, F,
+    hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 1024), (unsigned)nq), dim3(256), 0, st, bs, S, F,
                        presb);
     NAPY_TRY(check_launch("presence"));
     // columns longer than the LDS sort handles carry no tie flag in their
