@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "0a6d75a37f62d83008c801e7c01f9379969f1aea2b4b73fddbf7c4f0d6f88559",
-    "fetch_kib": 135812.1,
-    "write_kib": 15904.6,
+    "source_sha256": "8294eecde72479a6d48946ed59bb731647224c681041401b4a8d3d4afb37ffd7",
+    "fetch_kib": 135842.5,
+    "write_kib": 15910.7,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
