@@ -148,8 +148,9 @@ int napy_spearman(const float* X, int64_t S, int64_t F, int64_t ldx,
  * entry is skipped).  Event 0 is recorded on `stream` before the first
  * kernel, events 1..3 after each stage:
  *   Pearson:  1 column statistics, 2 masked contractions, 3 combine + p;
- *   Spearman: 1 sort of every column, 2 per-pair re-ranking scan,
- *             3 combine + p.
+ *   Spearman: 1 sort of every column and the partner blocks' presence
+ *             planes, 2 per-pair re-ranking scan (k_spearman_pairs
+ *             alone), 3 combine + p.
  * Results are those of the plain calls.
  * ------------------------------------------------------------------------ */
 int napy_pearson_profiled(const float* X, int64_t S, int64_t F, int64_t ldx,

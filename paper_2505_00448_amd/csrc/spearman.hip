@@ -2200,13 +2200,21 @@ static int pairs_launch_t(const SpearBase& bs, const uint8_t* presb, int64_t S, 
     return check_launch("spearman_pairs");
 }
 
-static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t F, PairOut po, hipStream_t st)
+// the partner blocks' presence planes (input of the pair scan)
+static int presence_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t F, hipStream_t st)
 {
-    uint8_t* presb = (uint8_t*)pres;
     const int64_t nq = ceil_div(F, 8);
     hipLaunchKernelGGL(k_presence, dim3((unsigned)ceil_div(bs.ld, 1024), (unsigned)nq), dim3(256), 0, st, bs, S, F,
-                       presb);
-    NAPY_TRY(check_launch("presence"));
+                       (uint8_t*)pres);
+    return check_launch("presence");
+}
+
+// presence planes, then the pair scan
+static int pairs_launch(const SpearBase& bs, uint32_t* pres, int64_t S, int64_t F, PairOut po, hipStream_t st,
+                        bool with_presence = true)
+{
+    uint8_t* presb = (uint8_t*)pres;
+    if (with_presence) NAPY_TRY(presence_launch(bs, pres, S, F, st));
     // columns longer than the LDS sort handles carry no tie flag in their
     // positions (and would not fit a's positions in LDS next to the tables)
     if (S > SORT_LDS_MAX_S) {
@@ -2294,9 +2302,12 @@ int spearman_run(const float* X, int64_t S, int64_t F, int64_t ldx, double* r, d
     spear_carve(c, S, F, w);
     NAPY_TRY(record_stage(ev, 0, st));
     NAPY_TRY(sort_launch(X, S, F, ldx, opt_use_sent(opts), opt_sent(opts), w.keys, w.base, st));
+    // the presence planes close the first stage, so that the second is the
+    // pair scan kernel alone
+    NAPY_TRY(presence_launch(w.base, w.pres, S, F, st));
     NAPY_TRY(record_stage(ev, 1, st));
     PairOut po{w.sums, nullptr, nullptr, 0, 0};
-    NAPY_TRY(pairs_launch(w.base, w.pres, S, F, po, st));
+    NAPY_TRY(pairs_launch(w.base, w.pres, S, F, po, st, false));
     NAPY_TRY(record_stage(ev, 2, st));
     NAPY_TRY(final_launch(w, F, r, p, n, ldo, st));
     return record_stage(ev, 3, st);
