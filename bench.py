@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "8294eecde72479a6d48946ed59bb731647224c681041401b4a8d3d4afb37ffd7",
-    "fetch_kib": 135842.5,
-    "write_kib": 15910.7,
+    "source_sha256": "b4c6e22f4ba292a4ddf633ed67b22e69228b687821013bdc869ec35f254594cd",
+    "fetch_kib": 135951.4,
+    "write_kib": 15908.5,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
