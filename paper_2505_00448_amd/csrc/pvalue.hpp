@@ -18,7 +18,9 @@
 // formed in logs.  ln B(a, 1/2) = ln(sqrt(pi)) - [ln G(a + 1/2) - ln G(a)];
 // for a >= 20 the bracket is evaluated as 0.5 ln a plus the asymptotic series
 // obtained from Stirling's series of both log-gammas (so no two large
-// log-gammas are subtracted), below that from lgamma directly.
+// log-gammas are subtracted), below that from lgamma directly; the factors
+// |r| and a^(+-1/2) multiply the exponential instead of entering its
+// argument as logarithms.
 //
 // Compiled for host and device: the host copy serves only to unit-test the
 // arithmetic on a machine without a GPU.
@@ -33,23 +35,6 @@
 
 namespace napy {
 
-// ln G(a + 1/2) - ln G(a)
-NAPY_HD inline double lgamma_half_ratio(double a)
-{
-    if (a >= 20.0) {
-        const double ia = 1.0 / a;
-        const double ia2 = ia * ia;
-        // -1/(8a) + 1/(192a^3) - 1/(640a^5) + 17/(14336a^7) - 31/(18432a^9)
-        double s = -31.0 / 18432.0;
-        s = s * ia2 + 17.0 / 14336.0;
-        s = s * ia2 - 1.0 / 640.0;
-        s = s * ia2 + 1.0 / 192.0;
-        s = s * ia2 - 1.0 / 8.0;
-        return 0.5 * log(a) + s * ia;
-    }
-    return lgamma(a + 0.5) - lgamma(a);
-}
-
 // 1/x: on the device the hardware reciprocal refined by two Newton steps
 // (full double precision without the IEEE division sequence); on the host a
 // plain division.
@@ -63,6 +48,21 @@ NAPY_HD inline double recip(double x)
 #else
     return 1.0 / x;
 #endif
+}
+
+// ln G(a + 1/2) - ln G(a) - ln(a) / 2 for a >= 20: Stirling's series of the
+// two log-gammas, -1/(8a) + 1/(192a^3) - 1/(640a^5) + 17/(14336a^7) -
+// 31/(18432a^9) (the next term is below 1e-17 there)
+NAPY_HD inline double lgamma_half_ratio_tail(double a)
+{
+    const double ia = recip(a);
+    const double ia2 = ia * ia;
+    double s = -31.0 / 18432.0;
+    s = s * ia2 + 17.0 / 14336.0;
+    s = s * ia2 - 1.0 / 640.0;
+    s = s * ia2 + 1.0 / 192.0;
+    s = s * ia2 - 1.0 / 8.0;
+    return s * ia;
 }
 
 // Continued fraction of I_x(a, b) (A&S 26.5.8): I_x(a, b) = x^a (1-x)^b /
@@ -147,7 +147,7 @@ NAPY_HD inline double betacf_lentz(double a, double b, double x)
 // are chosen first so that one continued-fraction loop serves both tails
 // (lanes of a wave taking different tails do not run two loops).
 struct CorrPSetup {
-    double a, b, x, lf, value;
+    double a, b, x, lf, m, value;
     bool done, direct;
 };
 
@@ -157,6 +157,7 @@ NAPY_HD inline CorrPSetup corr_p_params(double r, int64_t n)
 {
     CorrPSetup q;
     q.a = q.b = q.x = q.lf = 0.0;
+    q.m = 1.0;
     q.direct = true;
     q.done = true;
     q.value = NAN;
@@ -189,24 +190,37 @@ NAPY_HD inline CorrPSetup corr_p_params(double r, int64_t n)
     return q;
 }
 
+// The prefactor is m exp(lf).  With x = 1 - r^2, y = r^2 and ln B(a, 1/2) =
+// ln(pi) / 2 - [ln G(a + 1/2) - ln G(a)], the direct tail's prefactor
+// x^a y^(1/2) / (a B(a, 1/2)) is |r| exp(a ln x - ln a - ln B), and the
+// complement's y^(1/2) x^a / ((1/2) B(1/2, a)) is 2 |r| exp(a ln x - ln B):
+// |r| stays outside the exponential (no logarithm of it).  For a >= 20 the
+// bracket is ln(a) / 2 plus Stirling's tail T(a), so that -ln a - ln B =
+// T(a) - ln(pi a) / 2 and -ln B = T(a) + ln(a / pi) / 2: the square roots
+// go into m as well, and the exponential's argument is a ln x + T(a) alone.
 NAPY_HD inline CorrPSetup corr_p_setup(double r, int64_t n)
 {
     CorrPSetup q = corr_p_params(r, n);
     if (q.done) return q;
     const double ar = fabs(r);
     const double a = 0.5 * (double)(n - 2);
-    const double lnx = log1p(-(ar * ar));
-    const double lny = 2.0 * log(ar);
-    // ln B(a, 1/2) = 0.5 ln(pi) - [ln G(a+1/2) - ln G(a)]
-    const double lnB = 0.57236494292470008707 - lgamma_half_ratio(a);
-    q.lf = q.direct ? a * lnx + 0.5 * lny - log(a) - lnB : 0.5 * lny + a * lnx + 0.69314718055994530942 - lnB;
+    const double alnx = a * log1p(-(ar * ar));
+    if (a >= 20.0) {
+        constexpr double PI = 3.14159265358979323846;
+        q.lf = alnx + lgamma_half_ratio_tail(a);
+        q.m = q.direct ? ar * recip(sqrt(PI * a)) : 2.0 * ar * sqrt(a * (1.0 / PI));
+    } else {
+        const double lnB = 0.57236494292470008707 - (lgamma(a + 0.5) - lgamma(a));
+        q.lf = q.direct ? alnx - log(a) - lnB : alnx + 0.69314718055994530942 - lnB;
+        q.m = ar;
+    }
     return q;
 }
 
 // p from the setup and the fraction's value h
 NAPY_HD inline double corr_p_finish(const CorrPSetup& q, double h)
 {
-    const double t = exp(q.lf) * h;
+    const double t = q.m * exp(q.lf) * h;
     if (q.direct) return t;
     const double p = 1.0 - t;
     return p < 0.0 ? 0.0 : p;
