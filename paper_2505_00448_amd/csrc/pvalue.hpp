@@ -9,9 +9,9 @@
 //
 // which is also the two-sided Student-t tail with n - 2 degrees of freedom.
 //
-// Method: the continued fraction of I_x(a, b) (Abramowitz & Stegun 26.5.8)
-// evaluated with the modified Lentz algorithm (Lentz 1976; Thompson & Barnett
-// 1986).  It converges fast for x < (a + 1) / (a + b + 2); otherwise the
+// Method: the continued fraction of I_x(a, b) (Abramowitz & Stegun 26.5.8),
+// evaluated by the forward recurrences of its convergents after an
+// equivalence transformation that leaves no division in the loop.  It converges fast for x < (a + 1) / (a + b + 2); otherwise the
 // symmetry I_x(a, b) = 1 - I_{1-x}(b, a) is used, so the tail that is computed
 // directly is the small one (for p the complement is kept a little beyond
 // that point, see corr_p_params).  The prefactor x^a (1-x)^b / (a B(a,b)) is
@@ -66,78 +66,93 @@ NAPY_HD inline double lgamma_half_ratio_tail(double a)
 }
 
 // Continued fraction of I_x(a, b) (A&S 26.5.8): I_x(a, b) = x^a (1-x)^b /
-// (a B(a, b)) * 1 / (1 + e_1 / (1 + e_2 / (1 + ...))), with the partial
-// numerators e_{2k} = k (b - k) x / ((a + 2k - 1)(a + 2k)) and e_{2k+1} =
-// -(a + k)(a + b + k) x / ((a + 2k)(a + 2k + 1)).  It is evaluated forwards
-// by the modified Lentz method (Lentz 1976; Thompson & Barnett 1986): with
-// the ratios C_j = A_j / A_{j-1} and 1/D_j = B_{j-1} / B_j of successive
-// numerators and denominators, C_j = 1 + e_j / C_{j-1}, D_j = 1 + e_j /
-// D_{j-1}, and the value is the product of the C_j / D_j; ratios that come
-// out near zero are replaced by a tiny number.  CfLentz holds the product
-// (prod), the last C (cr) and 1/D (id), and the index k of the next pair of
-// terms, so a caller can interleave the steps of several evaluations.  A
-// term pair takes 1/C and 1/D from one reciprocal of C D (four reciprocals
-// per pair instead of six; sharing one between the two coefficient
-// denominators as well costs about a third more rounding error in the slow
-// cases near the tail switch at large a).
-struct CfLentz {
+// (a B(a, b)) * h, h = 1 / (1 + e_1 / (1 + e_2 / (1 + ...))), with the
+// partial numerators e_j = p_j / (d_{j-1} d_j), d_m = a + m, p_{2k} = k (b -
+// k) x and p_{2k+1} = -(a + k)(a + b + k) x.
+//
+// Evaluation: the fundamental recurrences of the convergents A_n / B_n of a
+// continued fraction (A_n = b_n A_{n-1} + a_n A_{n-2}, the same for B), after
+// the equivalence transformation that multiplies the n-th partial
+// denominator by d_{n-1} (n >= 2).  The transformed fraction has partial
+// numerators p_j (and -(a + b) x for j = 1) and partial denominators d_j, so
+// that each term is
+//
+//     A <- d_j A + p_j A_prev,   B <- d_j B + p_j B_prev
+//
+// (two products and two fused multiply-adds, no division), starting from
+// A_0 = 0, A_1 = 1, B_0 = B_1 = 1.  The four values grow by about d_j per
+// term; after each pair of terms all four are scaled by the power of two
+// that brings B near one (exact, and the ratio A / B is unchanged).  Two
+// successive convergents differ by W_n / (B_n B_{n-1}), where the
+// determinant W_n = A_n B_{n-1} - A_{n-1} B_n obeys W_n = -p W_{n-1} for the
+// term's partial numerator p: it is carried as a product (so the difference
+// is known without the cancellation of forming it from A and B), and the
+// fraction has converged when |W| < CF_EPS |A_{n-1} B_n|; h = A / B at the
+// end.  CfState holds the two latest convergents, W and the index k of the
+// next pair of terms, so a caller can interleave the steps of several
+// evaluations.
+struct CfState {
     double a, b, x;
-    double prod, cr, id;
+    double A, Ap, B, Bp;  // latest and previous convergent
+    double W;             // A Bp - Ap B
     int k;
 };
 
-constexpr double CF_TINY = 1e-300;
 constexpr double CF_EPS = 1e-16;
 constexpr int CF_MAXK = 2000;
 
-NAPY_HD inline void cf_start(CfLentz& s, double a, double b, double x)
+NAPY_HD inline void cf_start(CfState& s, double a, double b, double x)
 {
     s.a = a;
     s.b = b;
     s.x = x;
-    s.cr = 1.0;
-    double d0 = 1.0 - (a + b) * x * recip(a + 1.0);  // D_1 (e_1 / C_0 with C_0 = 1 folded in)
-    if (fabs(d0) < CF_TINY) d0 = CF_TINY;
-    s.id = recip(d0);
-    s.prod = s.id;
+    // the first term, e_1 = -(a + b) x / (a (a + 1)), transformed
+    s.Ap = 1.0;
+    s.Bp = 1.0;
+    s.A = a + 1.0;
+    s.B = fma(-(a + b), x, a + 1.0);
+    s.W = (a + b) * x;
     s.k = 1;
 }
 
-// one Lentz update with partial numerator e: D = 1 + e / D_prev, C = 1 + e /
-// C_prev; returns C / D
-NAPY_HD inline double cf_term(CfLentz& s, double e)
+// terms 2k and 2k + 1, then the scaling; true once the last two convergents
+// agree to CF_EPS (or after CF_MAXK pairs)
+NAPY_HD inline bool cf_advance(CfState& s)
 {
-    double den = 1.0 + e * s.id;
-    if (fabs(den) < CF_TINY) den = CF_TINY;
-    const double inv = recip(s.cr * den);
-    double num = 1.0 + e * (den * inv);  // 1 + e / C_prev
-    if (fabs(num) < CF_TINY) num = CF_TINY;
-    s.id = s.cr * inv;  // 1 / den
-    s.cr = num;
-    return s.id * num;
-}
-
-// terms 2k and 2k + 1; true once the last ratio is within CF_EPS of one (or
-// after CF_MAXK pairs)
-NAPY_HD inline bool cf_advance(CfLentz& s)
-{
-    const double kk = (double)s.k, k2 = 2.0 * kk;
+    const double kk = (double)s.k, k2 = kk + kk;
     const double a = s.a, b = s.b, x = s.x;
-    s.prod *= cf_term(s, kk * (b - kk) * x * recip((a - 1.0 + k2) * (a + k2)));
-    const double ratio = cf_term(s, -(a + kk) * (a + b + kk) * x * recip((a + k2) * (a + 1.0 + k2)));
-    s.prod *= ratio;
+    // term 2k: d = a + 2k, p = k (b - k) x
+    const double de = a + k2, pe = kk * (b - kk) * x;
+    double A = fma(pe, s.Ap, de * s.A), B = fma(pe, s.Bp, de * s.B);
+    s.Ap = s.A;
+    s.Bp = s.B;
+    // term 2k + 1: d = a + 2k + 1, p = -(a + k)(a + b + k) x
+    const double dq = de + 1.0, pq = -((a + kk) * (a + b + kk) * x);
+    const double An = fma(pq, s.A, dq * A), Bn = fma(pq, s.B, dq * B);
+    // An / Bn - A / B = W / (B Bn)
+    const double W = s.W * (pe * pq);
+    const bool done = fabs(W) < CF_EPS * fabs(A * Bn) || s.k >= CF_MAXK;
+    // scale by 2^-e, e the exponent of Bn (Bn = 0 leaves the values as they
+    // are); W is bilinear in them
+    int e = 0;
+    (void)frexp(Bn, &e);
+    s.A = ldexp(An, -e);
+    s.B = ldexp(Bn, -e);
+    s.Ap = ldexp(A, -e);
+    s.Bp = ldexp(B, -e);
+    s.W = ldexp(W, -2 * e);
     ++s.k;
-    return fabs(ratio - 1.0) < CF_EPS || s.k > CF_MAXK;
+    return done;
 }
 
 // the continued-fraction factor h of I_x(a, b) = x^a (1-x)^b / (a B(a, b)) h
-NAPY_HD inline double betacf_lentz(double a, double b, double x)
+NAPY_HD inline double betacf(double a, double b, double x)
 {
-    CfLentz s;
+    CfState s;
     cf_start(s, a, b, x);
     while (!cf_advance(s)) {
     }
-    return s.prod;
+    return s.A / s.B;
 }
 
 // Setup of p = I_{1-r^2}((n-2)/2, 1/2) for n >= 3 and finite r: either a
@@ -231,7 +246,7 @@ NAPY_HD inline double corr_pvalue(double r, int64_t n)
 {
     const CorrPSetup q = corr_p_setup(r, n);
     if (q.done) return q.value;
-    return corr_p_finish(q, betacf_lentz(q.a, q.b, q.x));
+    return corr_p_finish(q, betacf(q.a, q.b, q.x));
 }
 
 // ln G(a + b) - ln G(a) for a, b > 0.  For a >= 20 from Stirling's series of
@@ -276,7 +291,7 @@ NAPY_HD inline double fdist_sf(double f, double d1, double d2)
     // one continued-fraction loop for either tail, as in corr_pvalue
     const bool direct = x < (a + 1.0) / (a + b + 2.0);
     const double lf = direct ? a * lnx + b * lny - log(a) - lnB : b * lny + a * lnx - log(b) - lnB;
-    const double t = exp(lf) * betacf_lentz(direct ? a : b, direct ? b : a, direct ? x : y);
+    const double t = exp(lf) * betacf(direct ? a : b, direct ? b : a, direct ? x : y);
     if (direct) return t;
     const double p = 1.0 - t;
     return p < 0.0 ? 0.0 : p;
