@@ -63,22 +63,49 @@ __device__ __forceinline__ uint32_t order_key(float v, int use_sent, float sent)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// X (S x F row-major) -> keys [F][ld] through a 64 x 64 LDS tile.
+// X (S x F row-major) -> keys [F][ld] through a 64 x 64 LDS tile.  Lane
+// groups of 16 take a tile row as 16 runs of 4 columns (one 16-byte load per
+// lane when VEC: ldx a multiple of 4 and X 16-byte aligned, and the 4
+// columns inside the matrix), and write a tile column as 16 runs of 4
+// samples (one 16-byte store).  The tile rows are 65 words apart, so both
+// the stores into the tile and the column reads out of it fall on distinct
+// banks.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_sort_keys(const float* __restrict__ X, int64_t S, int64_t F,
                                                    int64_t ldx, int use_sent, float sent,
                                                    uint32_t* __restrict__ keys, int64_t ld)
 {
     __shared__ uint32_t tile[64][65];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int q = threadIdx.x & 15, g = threadIdx.x >> 4;  // run of 4, lane group
     const int64_t i0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t i = i0 + r, c = c0 + tx;
-        tile[r][tx] = (i < S && c < F) ? order_key(X[i * ldx + c], use_sent, sent) : 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = g + 16 * u;
+        const int64_t i = i0 + r, c = c0 + 4 * q;
+        float v[4];
+        if (VEC && i < S && c + 3 < F) {
+            const float4 x4 = *(const float4*)(X + i * ldx + c);
+            v[0] = x4.x;
+            v[1] = x4.y;
+            v[2] = x4.z;
+            v[3] = x4.w;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) tile[r][4 * q + k] = order_key(v[k], use_sent, sent);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                tile[r][4 * q + k] =
+                    (i < S && c + k < F) ? order_key(X[i * ldx + c + k], use_sent, sent) : 0xFFFFFFFFu;
+        }
     }
     __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int64_t c = c0 + r, i = i0 + tx;
-        if (c < F && i < ld) keys[c * ld + i] = tile[tx][r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int cc = g + 16 * u;
+        const int64_t c = c0 + cc, i = i0 + 4 * q;  // ld is a multiple of 4: i < ld covers i + 3
+        if (c < F && i < ld)
+            *(uint4*)(keys + c * ld + i) =
+                make_uint4(tile[4 * q][cc], tile[4 * q + 1][cc], tile[4 * q + 2][cc], tile[4 * q + 3][cc]);
     }
 }
 
@@ -2257,7 +2284,15 @@ static int sort_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int us
                        uint32_t* keys, const SpearBase& base, hipStream_t st)
 {
     dim3 gk((unsigned)ceil_div(F, 64), (unsigned)ceil_div(base.ld, 64));
-    hipLaunchKernelGGL(k_sort_keys, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
+    // (the key rows are 16-byte aligned: the workspace's carve aligns them and ld is a multiple of 256)
+    if (base.ld % 4 != 0 || ((uintptr_t)keys & 15u) != 0u) {
+        set_last_error("sort keys: key rows not 16-byte aligned");
+        return NAPY_E_INVALID;
+    }
+    if (ldx % 4 == 0 && ((uintptr_t)X & 15u) == 0u)
+        hipLaunchKernelGGL(k_sort_keys<true>, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
+    else
+        hipLaunchKernelGGL(k_sort_keys<false>, gk, dim3(256), 0, st, X, S, F, ldx, us, sv, keys, base.ld);
     NAPY_TRY(check_launch("sort_keys"));
     if (S > SORT_LDS_MAX_S) {
         hipLaunchKernelGGL(k_colsort_big, dim3((unsigned)F), dim3(CS_THREADS), 0, st, keys, S, base.ld, F, base);

@@ -193,6 +193,31 @@ def test_bitwise_determinism(gpu_device):
             assert np.array_equal(u, v, equal_nan=True), (method, prec)
 
 
+@pytest.mark.parametrize("F,pad,offset", [(64, 4, 0), (70, 4, 0), (70, 3, 0), (64, 4, 1), (130, 0, 1)])
+def test_padded_and_unaligned_rows(gpu_device, F, pad, offset):
+    """X handed over as a view of a wider buffer: leading dimension F + pad,
+    first element `offset` floats into it (16-byte aligned rows and a
+    multiple-of-4 leading dimension take the key transpose's vector loads,
+    the rest its element loads).  Results bit-identical to the contiguous
+    call, which the oracle pins."""
+    import torch
+    napy = _napy()
+    S = 300
+    X = synth.heavy_ties(S, F, levels=7, missing=0.2, seed=77)
+    X[:, : F // 2] = synth.cfg_plain_small(S=S, F=F // 2)
+    print(f"[padded] F={F} pad={pad} offset={offset}", flush=True)
+    big = torch.full((S, F + pad + offset), 123.0, dtype=torch.float32, device=gpu_device)
+    big[:, offset:offset + F] = torch.from_numpy(X).to(gpu_device)
+    view = big[:, offset:offset + F]
+    assert view.stride(0) == F + pad + offset
+    for method in ("spearman", "pearson"):
+        got = napy.spearman(view) if method == "spearman" else napy.pearson(view, precision="fp32")
+        ref = _run(method, X, gpu_device)
+        for k, want in zip(("r", "p", "n"), ref):
+            assert np.array_equal(_np(got[k]), want, equal_nan=True), (method, k)
+    _check_full("spearman", X, gpu_device, where=f"padded-{F}-{pad}-{offset}")
+
+
 def test_subset_queries_match_full_calls(gpu_device):
     import torch
     napy = _napy()
