@@ -298,10 +298,18 @@ NAPY_HD inline double fdist_sf(double f, double d1, double d2)
 }
 
 // Regularized upper incomplete gamma Q(a, x) = Gamma(a, x) / Gamma(a), a > 0
-// (A&S 6.5.3).  For x < a + 1 the series of P = 1 - Q (A&S 6.5.29,
-// P = e^-x x^a / Gamma(a) * sum_n x^n / (a (a+1) ... (a+n))); otherwise the
-// continued fraction of Q (A&S 6.5.31) by the modified Lentz algorithm, so the
-// tail computed directly is the small one.  The prefactor is formed in logs.
+// (A&S 6.5.3), with the prefactor e^-x x^a / Gamma(a) formed in logs.
+//   x < a + 1: Q = 1 - P from the series of P (A&S 6.5.29), P = prefactor *
+//     sum_{m >= 0} x^m / (a (a+1) ... (a+m)); its terms t_m = t_{m-1} x /
+//     (a + m) are summed until one falls below 1e-17 of the sum.
+//   otherwise: Q = prefactor * 1 / (x + 1 - a - 1 (1 - a) / (x + 3 - a -
+//     2 (2 - a) / (x + 5 - a - ...))), the even contraction of A&S 6.5.31:
+//     partial numerators -m (m - a), denominators x + 2m + 1 - a.  As for
+//     the beta fraction above, by the forward recurrences of the convergents
+//     (division-free: the coefficients are polynomials), rescaled by powers of
+//     two and stopped from the running determinant W, which each term
+//     multiplies by -(its partial numerator).
+// The tail computed directly is the small one.
 NAPY_HD inline double gamma_q(double a, double x)
 {
     if (!(x == x) || !(a > 0.0)) return NAN;
@@ -309,31 +317,34 @@ NAPY_HD inline double gamma_q(double a, double x)
     if (x == INFINITY) return 0.0;
     const double lpre = -x + a * log(x) - lgamma(a);
     if (x < a + 1.0) {
-        double ap = a, del = 1.0 / a, sum = del;
-        for (int n = 1; n <= 100000; ++n) {
-            ap += 1.0;
-            del *= x / ap;
-            sum += del;
-            if (fabs(del) < fabs(sum) * 1e-17) break;
+        double term = 1.0 / a, total = term, am = a;
+        for (int m = 1; m <= 100000; ++m) {
+            am += 1.0;
+            term *= x / am;
+            total += term;
+            if (fabs(term) < fabs(total) * 1e-17) break;
         }
-        const double q = 1.0 - sum * exp(lpre);
+        const double q = 1.0 - total * exp(lpre);
         return q < 0.0 ? 0.0 : q;
     }
-    const double tiny = 1e-300;
-    double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
-    for (int i = 1; i <= 100000; ++i) {
-        const double an = -(double)i * ((double)i - a);
-        b += 2.0;
-        d = an * d + b;
-        if (fabs(d) < tiny) d = tiny;
-        c = b + an / c;
-        if (fabs(c) < tiny) c = tiny;
-        d = 1.0 / d;
-        const double del = d * c;
-        h *= del;
-        if (fabs(del - 1.0) < 1e-16) break;
+    // convergents: 0 / 1, then 1 / (x + 1 - a)
+    const double d0 = x + 1.0 - a;
+    double Ap = 0.0, Bp = 1.0, A = 1.0, B = d0, W = 1.0;
+    for (int m = 1; m <= 100000; ++m) {
+        const double num = -(double)m * ((double)m - a), den = fma(2.0, (double)m, d0);
+        const double An = fma(num, Ap, den * A), Bn = fma(num, Bp, den * B);
+        W *= -num;  // A_n B_{n-1} - A_{n-1} B_n
+        const bool done = fabs(W) < CF_EPS * fabs(A * Bn);
+        int e = 0;
+        (void)frexp(Bn, &e);
+        Ap = ldexp(A, -e);
+        Bp = ldexp(B, -e);
+        A = ldexp(An, -e);
+        B = ldexp(Bn, -e);
+        W = ldexp(W, -2 * e);
+        if (done) break;
     }
-    return exp(lpre) * h;
+    return exp(lpre) * (A / B);
 }
 
 // P(chi2_df > x) = Q(df / 2, x / 2)
