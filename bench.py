@@ -68,9 +68,9 @@ FP64_PEAK_FLOPS = 78.6e12              # FP64 matrix (and vector) peak
 # figures belong to one version of the kernel source: for any other version
 # the traffic is reported as unknown.
 SCAN_TRAFFIC = {
-    "source_sha256": "b4c6e22f4ba292a4ddf633ed67b22e69228b687821013bdc869ec35f254594cd",
-    "fetch_kib": 135951.4,
-    "write_kib": 15908.5,
+    "source_sha256": "7cf019a2aff050544340d0c66694e480a08ba9c73d2c368c6f49a00304ca7491",
+    "fetch_kib": 135831.2,
+    "write_kib": 15909.9,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
