@@ -90,6 +90,70 @@ __global__ __launch_bounds__(256) void k_colstats_partial(
     }
 }
 
+// The same partial sums from 16-byte loads (X 16-byte aligned, ldx a
+// multiple of 4): four adjacent columns per thread, 256 per workgroup, four
+// rows' loads issued before their adds.  Each column's rows are added in the
+// same order as above (rows r0 + rl, r0 + rl + 4, ... per wave, then the four
+// waves' sums as ((w0 + w1) + w2) + w3), so the sums are bit-identical.
+__global__ __launch_bounds__(256) void k_colstats_partial4(
+    const float* __restrict__ X, int64_t S, int64_t F, int64_t ldx, int use_sent, float sent,
+    int64_t rows_per, int32_t* __restrict__ pcnt, double* __restrict__ psum)
+{
+    __shared__ int32_t sc[4][256];
+    __shared__ double ss[4][256];
+    const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+    const int64_t col0 = (int64_t)blockIdx.x * 256 + 4 * c;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+    const int64_t r1 = min(S, r0 + rows_per);
+    int32_t cnt[4] = {0, 0, 0, 0};
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    const auto add = [&](int q, float v) {
+        if (!is_missing(v, use_sent, sent)) {
+            ++cnt[q];
+            sum[q] += (double)v;
+        }
+    };
+    if (col0 + 3 < F) {
+        int64_t i = r0 + rl;
+        for (; i + 12 < r1; i += 16) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = *(const float4*)(X + (i + 4 * u) * ldx + col0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                add(0, v[u].x);
+                add(1, v[u].y);
+                add(2, v[u].z);
+                add(3, v[u].w);
+            }
+        }
+        for (; i < r1; i += 4) {
+            const float4 v = *(const float4*)(X + i * ldx + col0);
+            add(0, v.x);
+            add(1, v.y);
+            add(2, v.z);
+            add(3, v.w);
+        }
+    } else if (col0 < F) {
+        for (int64_t i = r0 + rl; i < r1; i += 4)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (col0 + q < F) add(q, X[i * ldx + col0 + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        sc[rl][4 * c + q] = cnt[q];
+        ss[rl][4 * c + q] = sum[q];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int64_t col = (int64_t)blockIdx.x * 256 + t;
+    if (col < F) {
+        pcnt[(int64_t)blockIdx.y * F + col] = sc[0][t] + sc[1][t] + sc[2][t] + sc[3][t];
+        psum[(int64_t)blockIdx.y * F + col] = ((ss[0][t] + ss[1][t]) + ss[2][t]) + ss[3][t];
+    }
+}
+
 // one wave per column: each lane sums the partials r = lane, lane + 64, ...
 // and a fixed butterfly adds the lanes (the same order on every call)
 __global__ __launch_bounds__(256) void k_colstats_final(
@@ -144,9 +208,15 @@ int colstats_launch(const float* X, int64_t S, int64_t F, int64_t ldx, int use_s
 {
     const int R = cs.rows_chunks;
     const int64_t rows_per = ceil_div(S, R);
-    dim3 g1((unsigned)ceil_div(F, 64), (unsigned)R);
-    hipLaunchKernelGGL(k_colstats_partial, g1, dim3(256), 0, st, X, S, F, ldx, use_sent, sent,
-                       rows_per, cs.pcnt, cs.psum);
+    if (((uintptr_t)X & 15u) == 0 && (ldx & 3) == 0) {
+        dim3 g1((unsigned)ceil_div(F, 256), (unsigned)R);
+        hipLaunchKernelGGL(k_colstats_partial4, g1, dim3(256), 0, st, X, S, F, ldx, use_sent, sent,
+                           rows_per, cs.pcnt, cs.psum);
+    } else {
+        dim3 g1((unsigned)ceil_div(F, 64), (unsigned)R);
+        hipLaunchKernelGGL(k_colstats_partial, g1, dim3(256), 0, st, X, S, F, ldx, use_sent, sent,
+                           rows_per, cs.pcnt, cs.psum);
+    }
     NAPY_TRY(check_launch("colstats_partial"));
     hipLaunchKernelGGL(k_colstats_final, dim3((unsigned)ceil_div(F, 4)), dim3(256), 0, st, R, F,
                        cs.pcnt, cs.psum, cs.n, cs.mu32, cs.mu64, zero_word);
